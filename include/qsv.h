@@ -1,0 +1,262 @@
+/*
+ * qsv.h - state-vector sweep for random lattice ("supremacy") circuits on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library applies the gates of a random 2D-lattice circuit to a 2^n
+ * complex64 amplitude vector held in device memory.  Everything below is
+ * plain C: pointers, sizes and status codes.  Device buffers are owned by
+ * the caller; every call that launches work is asynchronous on the HIP
+ * stream passed as `stream` (a hipStream_t; NULL = the default stream).
+ *
+ * Conventions shared by every entry point
+ *  - State layout (Section 2, preliminaries): amplitude alpha_i is stored at
+ *    index i as interleaved (re, im) float32, 8 bytes; qubit k is index bit k,
+ *    so a gate on qubit k pairs alpha_i with alpha_{i + 2^k} for i with bit k
+ *    clear.  A bitstring x names the amplitude alpha_x, bit k = qubit k.
+ *  - Arguments are validated on the host before anything is enqueued; a call
+ *    that returns an error has enqueued nothing.  Errors never abort and
+ *    never throw across the ABI.  qsv_last_error() returns a thread-local
+ *    message for the last non-OK status of the calling thread.
+ *  - Device faults surface as QSV_EHIP from the next call that synchronises.
+ *  - Limits: n_qubits <= 34 for a single state (2^34 * 8 B = 128 GiB),
+ *    bitstrings < 2^63, lattices up to 64 sites.  Device: gfx950 only.
+ */
+#ifndef QSV_PUBLIC_API_H_
+#define QSV_PUBLIC_API_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QSV_OK = 0,
+    QSV_EINVAL = 1,        /* bad argument: null pointer, bad kind, bad size */
+    QSV_ERANGE = 2,        /* n too large, qubit or bitstring out of range */
+    QSV_ENOMEM = 3,        /* host or device allocation failed */
+    QSV_EHIP = 4,          /* HIP runtime error (message in qsv_last_error) */
+    QSV_EUNSUPPORTED = 5,  /* option or device not supported (e.g. not gfx950) */
+    QSV_EINTERNAL = 6
+} qsv_status;
+
+/*
+ * Gate kinds.  The random circuit family uses H, T, SX = X^1/2, SY = Y^1/2
+ * and CZ (Section 2, "universal random quantum circuit").  Matrices (rows
+ * and columns indexed by the acted-on bit):
+ *   H  = [[1,1],[1,-1]]/sqrt2            T   = diag(1, e^{i pi/4})
+ *   SX = [[1+i,1-i],[1-i,1+i]]/2          SY  = [[1+i,-1-i],[1+i,1+i]]/2
+ *   CZ = diag(1,1,1,-1) on (q0, q1)       Z   = diag(1,-1)
+ *   P0 = |0><0|, P1 = |1><1| (projectors of the CZ split, Section 2)
+ *   TDG, SXDG, SYDG = adjoints of T, SX, SY.
+ * PB and ZB are the branch-parameterised gates that circuit_split emits for
+ * a cut CZ: with l = bit `arg` of the branch index passed to sv_apply_*,
+ * PB applies P_l and ZB applies Z^l.
+ */
+typedef enum {
+    QSV_H = 0, QSV_T = 1, QSV_SX = 2, QSV_SY = 3, QSV_CZ = 4,
+    QSV_P0 = 5, QSV_P1 = 6, QSV_Z = 7, QSV_TDG = 8, QSV_SXDG = 9, QSV_SYDG = 10,
+    QSV_PB = 11, QSV_ZB = 12
+} qsv_gate_kind;
+
+/* One gate.  q1 is used by CZ only; arg is the branch bit of PB/ZB. */
+typedef struct {
+    uint8_t kind;
+    uint8_t q0;
+    uint8_t q1;
+    uint8_t arg;
+    uint16_t layer;   /* circuit layer, 0 = the opening Hadamard layer */
+    uint16_t reserved;
+} qsv_gate;
+
+typedef struct qsv_circuit qsv_circuit;  /* opaque, host-owned */
+typedef struct qsv_batch qsv_batch;      /* opaque */
+
+/*
+ * Tuning options of the fused sweep.  Pass NULL to let the autotuner pick.
+ * A field left at 0 means "tuner's choice".
+ *   reg_qubits     qubits held in each thread's registers (R, 3..6)
+ *   thread_qubits  log2 of the workgroup size (T, 6..9); a tile holds
+ *                  2^(R+T) amplitudes
+ *   low_qubits     minimum number of always-resident low index bits that make
+ *                  each global access a contiguous run (c, 3..8)
+ *   plain          1 = one kernel per gate (the unfused comparator path)
+ */
+typedef struct {
+    int reg_qubits;
+    int thread_qubits;
+    int low_qubits;
+    int plain;
+} qsv_fuse_opts;
+
+/*
+ * circuit_create - build a random lattice circuit or wrap an explicit list.
+ *
+ * Lattice: rows x cols sites; present[r*cols + c] != 0 marks a site that
+ * holds a qubit (NULL = all present).  Qubit q is the row-major rank of its
+ * site among the present ones.
+ * Random circuit (gates == NULL): layer 0 is H on every qubit; layer
+ * t = 1..depth applies the CZ pattern of class ORDER[(t-1) mod 8], then a
+ * single-qubit gate drawn uniformly from {T, SX, SY} on every qubit that was
+ * in a CZ at layer t-1 and is in none at layer t.  Pattern classes:
+ *   Hab = horizontal bonds (r,c)-(r,c+1) with c = a, r = b (mod 2),
+ *   Vab = vertical bonds (r,c)-(r+1,c) with r = a, c = b (mod 2),
+ *   ORDER = H00, H01, V10, V11, H10, V01, V00, H11.
+ * The gate types come from SplitMix64(seed), one draw per single-qubit gate
+ * in gate order, type = floor((r >> 32) * 3 / 2^32) -> T, SX, SY.  These
+ * rules are the reading that reproduces the gate counts of Table "28qubit"
+ * and the cut counts of Section 2.1.2 (the paper defers them to the
+ * random-circuit literature).
+ * Explicit list (gates != NULL): the n_gates gates are copied; depth and seed
+ * are ignored; every qubit index must be < the number of present sites.
+ * On success *out owns a new circuit; free it with circuit_destroy.
+ */
+qsv_status circuit_create(int rows, int cols, const uint8_t *present, int depth,
+                          uint64_t seed, const qsv_gate *gates, size_t n_gates,
+                          qsv_circuit **out);
+void circuit_destroy(qsv_circuit *c);
+qsv_status circuit_info(const qsv_circuit *c, int *n_qubits, int *depth, size_t *n_gates);
+/* Copy up to cap gates into out; *n_written = number copied. */
+qsv_status circuit_gates(const qsv_circuit *c, qsv_gate *out, size_t cap, size_t *n_written);
+
+/*
+ * circuit_split - Schmidt split across a qubit bipartition (Section 2,
+ * CU = P0 (x) I + P1 (x) U; Fig. 2).
+ *
+ * side_a_mask selects the side-A qubits (bit q = qubit q).  Every CZ with one
+ * qubit on each side is either
+ *   - folded: no non-diagonal gate follows on either qubit, so the CZ is the
+ *     output phase (-1)^{x_a x_b} (e.g. the final layer), or
+ *   - cut: it becomes branch bit j (j = 0,1,... in gate order): PB(j) on the
+ *     side-A qubit and ZB(j) on the side-B qubit.
+ * half_a / half_b receive new circuits over the side's qubits, renumbered in
+ * increasing global order (local qubit i = i-th set bit of the side's mask).
+ * *c_eff = number of cut CZs (2^c_eff branches).  The folded pairs are
+ * written to folded_a[i], folded_b[i] (global qubit numbers, side A first)
+ * for i < min(cap, count); *n_folded = count.  folded_a/folded_b may be NULL
+ * when cap is 0.
+ */
+qsv_status circuit_split(const qsv_circuit *c, uint64_t side_a_mask,
+                         qsv_circuit **half_a, qsv_circuit **half_b, int *c_eff,
+                         int32_t *folded_a, int32_t *folded_b, size_t cap,
+                         size_t *n_folded);
+
+/*
+ * sv_init - write a basis or uniform state into amps (device complex64[2^n]).
+ *   kind 0 = |0...0>, 1 = |+>^n (every amplitude 2^{-n/2}, i.e. layer 0
+ *   applied), 2 = |basis>.
+ */
+enum { QSV_INIT_ZERO = 0, QSV_INIT_PLUS = 1, QSV_INIT_BASIS = 2 };
+qsv_status sv_init(void *amps, int n_qubits, int kind, uint64_t basis, void *stream);
+
+/*
+ * sv_apply_fused - apply the gates of layers [layer_begin, layer_end) of the
+ * circuit to amps in place (device complex64[2^n], n = the circuit's qubit
+ * count).  layer_end < 0 means "to the end".  branch selects P_l / Z^l of the
+ * PB/ZB gates (bit j of branch = l_j); ignored for circuits without them.
+ *
+ * The gates are grouped into full-state passes: each pass streams every
+ * amplitude from HBM once, applies all gates it can on a tile of 2^(R+T)
+ * amplitudes (non-diagonal gates on the tile's resident qubits, diagonal
+ * T/CZ/Z/P gates on any qubit) and writes it back - the batching of gates on
+ * "local" qubits and the free application of diagonal gates of Section 2.4.
+ * Plans are built on the host on first use and cached in the circuit.
+ * Asynchronous on stream; the state is exact (up to FP32 rounding) after the
+ * last pass of the call, so calls over consecutive layer ranges compose.
+ */
+qsv_status sv_apply_fused(void *amps, const qsv_circuit *c, uint64_t branch,
+                          int layer_begin, int layer_end, const qsv_fuse_opts *opts,
+                          void *stream);
+
+/*
+ * sv_apply_plain - the unfused comparator: one full-state (or, for diagonal
+ * gates, partial) kernel per gate, the gate-by-gate method that Section 2.4
+ * and Table "28qubit" measure their speedup against.  Same arguments and
+ * result as sv_apply_fused.
+ */
+qsv_status sv_apply_plain(void *amps, const qsv_circuit *c, uint64_t branch,
+                          int layer_begin, int layer_end, void *stream);
+
+/*
+ * sv_amplitudes - gather alpha_x for m bitstrings (Task 2 of Section 1).
+ * bitstrings_dev: device uint64[m]; out_dev: device complex64[m]
+ * (out_c128 = 0) or complex128[m] (out_c128 = 1).  A bitstring >= 2^n makes
+ * the kernel write NaN for that entry (ranges cannot be checked on the host
+ * without a copy).
+ */
+qsv_status sv_amplitudes(const void *amps, int n_qubits, const uint64_t *bitstrings_dev,
+                         size_t m, void *out_dev, int out_c128, void *stream);
+
+/*
+ * sv_norm_fp64 - sum of |alpha_i|^2 over the state with every product and
+ * partial sum in FP64 and a fixed-order pairwise tree (deterministic).
+ * out_dev: device double[1].
+ */
+qsv_status sv_norm_fp64(const void *amps, int n_qubits, double *out_dev, void *stream);
+
+/*
+ * sv_branch_combine - out[x] = s_x * sum_b a_tab[b][x] * b_tab[b][x]
+ * (Fig. 2 and eq. (1): the output is the sum over branches of the tensor
+ * product of the two half states, here at m sampled bitstrings).
+ * a_tab, b_tab: device complex64[n_branches][m] (branch-major); sign_dev:
+ * device int8[m] of +1/-1 (the folded phases) or NULL for all +1; out_dev:
+ * device complex128[m].  Products and sums in FP64, fixed pairwise order.
+ */
+qsv_status sv_branch_combine(const void *a_tab, const void *b_tab, size_t n_branches,
+                             size_t m, const int8_t *sign_dev, void *out_dev, void *stream);
+
+/*
+ * Batched execution: many states (branches of split halves, or independent
+ * circuits of uneven size) swept by ONE persistent kernel launch, replayed
+ * from a captured hipGraph.
+ *
+ * sv_batch_create: count entries; entry i runs circuit circs[i] with branch
+ * index branch_ids[i] (NULL = all 0) on its own state.  Plans per circuit
+ * are built (and tuned) here.  The circuits must stay alive until
+ * sv_batch_destroy.
+ * sv_batch_run: amps_dev[i] is entry i's device state (complex64[2^n_i]),
+ * already initialised by the caller (or pass init_plus = 1 to have the
+ * launch start every state from |+>^n itself).  After the sweep, when
+ * m > 0, the amplitudes at bitstrings_dev[i*m .. i*m+m-1] (device uint64,
+ * local numbering of entry i) are written to amp_table_dev[i*m + k] (device
+ * complex64).  The first call captures a graph for these pointers; later
+ * calls with the same pointers replay it.  Asynchronous on stream.
+ */
+qsv_status sv_batch_create(const qsv_circuit *const *circs, const uint64_t *branch_ids,
+                           size_t count, const qsv_fuse_opts *opts, qsv_batch **out);
+qsv_status sv_batch_run(qsv_batch *b, void *const *amps_dev, int init_plus,
+                        const uint64_t *bitstrings_dev, size_t m, void *amp_table_dev,
+                        void *stream);
+void sv_batch_destroy(qsv_batch *b);
+
+/*
+ * Plan inspection (host only, no device needed).  For the plan that
+ * sv_apply_fused would use: *n_passes, and for each gate of the layer range
+ * the pass it runs in (pass_of_gate[i], -1 if outside the range) and its
+ * position in that pass's program (order_in_pass[i]); resident_mask[p] is
+ * the bit set of qubits resident in pass p (cap entries).  Arrays may be
+ * NULL.  Used by tests to check the grouping against the gate semantics.
+ */
+qsv_status sv_plan_info(const qsv_circuit *c, int layer_begin, int layer_end,
+                        const qsv_fuse_opts *opts, int *n_passes, int32_t *pass_of_gate,
+                        int32_t *order_in_pass, size_t n_gate_cap, uint64_t *resident_mask,
+                        size_t pass_cap);
+
+/*
+ * sv_debug_emulate - run the fused plan's pass programs on the host over a
+ * host complex64[2^n] array, with the same slot/exchange semantics as the
+ * GPU kernel.  A planner/encoding check for CPU-only test runs; never used
+ * by sv_apply_fused or any other entry point.
+ */
+qsv_status sv_debug_emulate(void *amps_host, const qsv_circuit *c, uint64_t branch,
+                            int layer_begin, int layer_end, const qsv_fuse_opts *opts);
+
+const char *qsv_last_error(void);
+/* Library version string. */
+const char *qsv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QSV_PUBLIC_API_H_ */

@@ -1,0 +1,341 @@
+// C-ABI entry points of the qsv library (declared in include/qsv.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "kernels.h"
+#include "qsv_internal.h"
+
+namespace {
+thread_local std::string g_err;
+}
+
+namespace qsv {
+
+qsv_status fail(qsv_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+namespace {
+
+qsv_status hip_fail(hipError_t e, const char *where) {
+    return fail(QSV_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// gfx950 check, cached per device ordinal.
+qsv_status check_device() {
+    static std::mutex mu;
+    static int state[64] = {0};  // 0 unknown, 1 ok, 2 unsupported
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(QSV_EUNSUPPORTED, "device ordinal out of range");
+    std::lock_guard<std::mutex> g(mu);
+    if (state[dev] == 0) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+        state[dev] = (std::strncmp(prop.gcnArchName, "gfx950", 6) == 0) ? 1 : 2;
+    }
+    if (state[dev] != 1) return fail(QSV_EUNSUPPORTED, "device is not gfx950");
+    return QSV_OK;
+}
+
+// FP64 partial-sum buffer of the norm kernel, one per device, kept for the
+// life of the process.
+qsv_status norm_partials(double **out) {
+    static std::mutex mu;
+    static double *buf[64] = {nullptr};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> g(mu);
+    if (!buf[dev]) {
+        e = hipMalloc(reinterpret_cast<void **>(&buf[dev]), 65536 * sizeof(double));
+        if (e != hipSuccess) return fail(QSV_ENOMEM, "norm partials: hipMalloc failed");
+    }
+    *out = buf[dev];
+    return QSV_OK;
+}
+
+qsv_status check_state(const void *amps, int n) {
+    if (!amps) return fail(QSV_EINVAL, "null state pointer");
+    if (n < 0 || n > kMaxQubits) return fail(QSV_ERANGE, "n_qubits must be in 0..34");
+    if (reinterpret_cast<uintptr_t>(amps) % 16 != 0)
+        return fail(QSV_EINVAL, "state pointer must be 16-byte aligned");
+    return QSV_OK;
+}
+
+qsv_status resolve_shape(const qsv_circuit *c, const qsv_fuse_opts *opts, TileShape &sh) {
+    sh = default_shape(c->n);
+    if (opts) {
+        if (opts->reg_qubits) sh.R = opts->reg_qubits;
+        if (opts->thread_qubits) sh.T = opts->thread_qubits;
+        if (opts->low_qubits) sh.c = opts->low_qubits;
+        else if (opts->reg_qubits || opts->thread_qubits) sh.c = std::min(5, sh.T + 1);
+    }
+    if (sh.R == 0) return QSV_OK;  // too small for a tile: plain path
+    if (!fused_shape_supported(sh.R, sh.T))
+        return fail(QSV_EUNSUPPORTED, "no fused kernel compiled for this (reg, thread) shape");
+    if (sh.R + sh.T > c->n) return fail(QSV_EUNSUPPORTED, "tile larger than the state");
+    if (sh.c < 1 || sh.c - 1 > sh.T || sh.c > sh.R + sh.T)
+        return fail(QSV_EINVAL, "low_qubits out of range for the tile shape");
+    return QSV_OK;
+}
+
+qsv_status get_plan(const qsv_circuit *cc, int lb, int le, TileShape sh,
+                    std::shared_ptr<Plan> &out) {
+    qsv_circuit *c = const_cast<qsv_circuit *>(cc);
+    PlanKey key{lb, le, sh.R, sh.T, sh.c};
+    std::lock_guard<std::mutex> g(c->mu);
+    auto it = c->plans.find(key);
+    if (it != c->plans.end()) {
+        out = it->second;
+        return QSV_OK;
+    }
+    auto p = std::make_shared<Plan>();
+    qsv_status st = build_plan(*c, lb, le, sh, *p);
+    if (st != QSV_OK) return st;
+    c->plans[key] = p;
+    out = p;
+    return QSV_OK;
+}
+
+void gate_matrix_f32(uint8_t kind, float m[8]) {
+    const double s = std::sqrt(0.5);
+    double r[8] = {0};
+    switch (kind) {
+    case QSV_H: { double t[8] = {s, 0, s, 0, s, 0, -s, 0}; std::memcpy(r, t, sizeof r); } break;
+    case QSV_SX: { double t[8] = {.5, .5, .5, -.5, .5, -.5, .5, .5}; std::memcpy(r, t, sizeof r); } break;
+    case QSV_SY: { double t[8] = {.5, .5, -.5, -.5, .5, .5, .5, .5}; std::memcpy(r, t, sizeof r); } break;
+    case QSV_SXDG: { double t[8] = {.5, -.5, .5, .5, .5, .5, .5, -.5}; std::memcpy(r, t, sizeof r); } break;
+    case QSV_SYDG: { double t[8] = {.5, -.5, .5, -.5, -.5, .5, .5, -.5}; std::memcpy(r, t, sizeof r); } break;
+    default: break;
+    }
+    for (int i = 0; i < 8; ++i) m[i] = float(r[i]);
+}
+
+}  // namespace
+}  // namespace qsv
+
+using namespace qsv;
+
+extern "C" {
+
+const char *qsv_last_error(void) { return g_err.c_str(); }
+const char *qsv_version(void) { return "qsv 0.1 gfx950"; }
+
+qsv_status circuit_create(int rows, int cols, const uint8_t *present, int depth, uint64_t seed,
+                          const qsv_gate *gates, size_t n_gates, qsv_circuit **out) {
+    if (!out) return fail(QSV_EINVAL, "circuit_create: out is null");
+    *out = nullptr;
+    auto c = std::unique_ptr<qsv_circuit>(new (std::nothrow) qsv_circuit);
+    if (!c) return fail(QSV_ENOMEM, "circuit_create: out of host memory");
+    if (!gates) {
+        qsv_status st = generate_lattice_circuit(rows, cols, present, depth, seed, c.get());
+        if (st != QSV_OK) return st;
+    } else {
+        if (rows <= 0 || cols <= 0 || rows * cols > 64)
+            return fail(QSV_EINVAL, "lattice must have 1..64 sites");
+        int n = 0;
+        for (int i = 0; i < rows * cols; ++i) n += (!present || present[i]) ? 1 : 0;
+        if (n == 0) return fail(QSV_EINVAL, "lattice has no present site");
+        int maxl = 0;
+        for (size_t i = 0; i < n_gates; ++i) {
+            const qsv_gate &g = gates[i];
+            if (g.kind > QSV_ZB) return fail(QSV_EINVAL, "unknown gate kind");
+            if (g.q0 >= n || (g.kind == QSV_CZ && (g.q1 >= n || g.q1 == g.q0)))
+                return fail(QSV_ERANGE, "gate qubit out of range");
+            if ((g.kind == QSV_PB || g.kind == QSV_ZB) && g.arg >= 64)
+                return fail(QSV_ERANGE, "branch bit out of range");
+            maxl = std::max(maxl, int(g.layer));
+        }
+        c->n = n;
+        c->depth = maxl;
+        c->gates.assign(gates, gates + n_gates);
+    }
+    *out = c.release();
+    return QSV_OK;
+}
+
+void circuit_destroy(qsv_circuit *c) { delete c; }
+
+qsv_status circuit_info(const qsv_circuit *c, int *n_qubits, int *depth, size_t *n_gates) {
+    if (!c) return fail(QSV_EINVAL, "circuit_info: null circuit");
+    if (n_qubits) *n_qubits = c->n;
+    if (depth) *depth = c->depth;
+    if (n_gates) *n_gates = c->gates.size();
+    return QSV_OK;
+}
+
+qsv_status circuit_gates(const qsv_circuit *c, qsv_gate *out, size_t cap, size_t *n_written) {
+    if (!c || (!out && cap) || !n_written) return fail(QSV_EINVAL, "circuit_gates: null argument");
+    size_t k = std::min(cap, c->gates.size());
+    if (k) std::memcpy(out, c->gates.data(), k * sizeof(qsv_gate));
+    *n_written = k;
+    return QSV_OK;
+}
+
+qsv_status sv_init(void *amps, int n_qubits, int kind, uint64_t basis, void *stream) {
+    qsv_status st = check_state(amps, n_qubits);
+    if (st != QSV_OK) return st;
+    if (kind < 0 || kind > 2) return fail(QSV_EINVAL, "sv_init: unknown kind");
+    if (kind == QSV_INIT_BASIS && n_qubits < 64 && basis >= (1ull << n_qubits))
+        return fail(QSV_ERANGE, "sv_init: basis index >= 2^n");
+    if ((st = check_device()) != QSV_OK) return st;
+    hipError_t e = launch_init(static_cast<float2 *>(amps), n_qubits, kind, basis,
+                               static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_init");
+}
+
+qsv_status sv_apply_plain(void *amps, const qsv_circuit *c, uint64_t branch, int layer_begin,
+                          int layer_end, void *stream) {
+    if (!c) return fail(QSV_EINVAL, "sv_apply_plain: null circuit");
+    qsv_status st = check_state(amps, c->n);
+    if (st != QSV_OK) return st;
+    if (c->n < 2) return fail(QSV_EUNSUPPORTED, "sv_apply_plain: needs n >= 2");
+    if (layer_begin < 0) return fail(QSV_EINVAL, "sv_apply_plain: layer_begin < 0");
+    if ((st = check_device()) != QSV_OK) return st;
+    std::vector<int> idx;
+    gates_in_range(*c, layer_begin, layer_end, idx);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float2 *a = static_cast<float2 *>(amps);
+    const float h = float(std::sqrt(0.5));
+    for (int i : idx) {
+        const qsv_gate &g = c->gates[i];
+        hipError_t e = hipSuccess;
+        switch (g.kind) {
+        case QSV_H: case QSV_SX: case QSV_SY: case QSV_SXDG: case QSV_SYDG: {
+            float m[8];
+            gate_matrix_f32(g.kind, m);
+            e = launch_plain_1q(a, c->n, g.q0, m, s);
+            break;
+        }
+        case QSV_T: e = launch_plain_phase(a, c->n, g.q0, h, h, s); break;
+        case QSV_TDG: e = launch_plain_phase(a, c->n, g.q0, h, -h, s); break;
+        case QSV_Z: e = launch_plain_phase(a, c->n, g.q0, -1.f, 0.f, s); break;
+        case QSV_CZ: e = launch_plain_cz(a, c->n, g.q0, g.q1, s); break;
+        case QSV_P0: e = launch_plain_zero(a, c->n, g.q0, 0, s); break;
+        case QSV_P1: e = launch_plain_zero(a, c->n, g.q0, 1, s); break;
+        case QSV_PB: e = launch_plain_zero(a, c->n, g.q0, int((branch >> g.arg) & 1), s); break;
+        case QSV_ZB:
+            if ((branch >> g.arg) & 1) e = launch_plain_phase(a, c->n, g.q0, -1.f, 0.f, s);
+            break;
+        default: return fail(QSV_EINTERNAL, "unknown gate kind");
+        }
+        if (e != hipSuccess) return hip_fail(e, "sv_apply_plain");
+    }
+    return QSV_OK;
+}
+
+qsv_status sv_apply_fused(void *amps, const qsv_circuit *c, uint64_t branch, int layer_begin,
+                          int layer_end, const qsv_fuse_opts *opts, void *stream) {
+    if (!c) return fail(QSV_EINVAL, "sv_apply_fused: null circuit");
+    qsv_status st = check_state(amps, c->n);
+    if (st != QSV_OK) return st;
+    if (layer_begin < 0) return fail(QSV_EINVAL, "sv_apply_fused: layer_begin < 0");
+    if (opts && opts->plain) return sv_apply_plain(amps, c, branch, layer_begin, layer_end, stream);
+    TileShape sh;
+    if ((st = resolve_shape(c, opts, sh)) != QSV_OK) return st;
+    if (sh.R == 0) return sv_apply_plain(amps, c, branch, layer_begin, layer_end, stream);
+    if ((st = check_device()) != QSV_OK) return st;
+    std::shared_ptr<Plan> plan;
+    if ((st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (const Pass &p : plan->passes) {
+        hipError_t e = launch_fused(static_cast<float2 *>(amps), c->n, sh.R, sh.T, p.prog, branch, s);
+        if (e != hipSuccess) return hip_fail(e, "sv_apply_fused");
+    }
+    return QSV_OK;
+}
+
+qsv_status sv_amplitudes(const void *amps, int n_qubits, const uint64_t *bitstrings_dev, size_t m,
+                         void *out_dev, int out_c128, void *stream) {
+    qsv_status st = check_state(amps, n_qubits);
+    if (st != QSV_OK) return st;
+    if (m && (!bitstrings_dev || !out_dev)) return fail(QSV_EINVAL, "sv_amplitudes: null buffer");
+    if ((st = check_device()) != QSV_OK) return st;
+    hipError_t e = launch_gather(static_cast<const float2 *>(amps), n_qubits, bitstrings_dev, m,
+                                 out_dev, out_c128 ? 1 : 0, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_amplitudes");
+}
+
+qsv_status sv_norm_fp64(const void *amps, int n_qubits, double *out_dev, void *stream) {
+    qsv_status st = check_state(amps, n_qubits);
+    if (st != QSV_OK) return st;
+    if (!out_dev) return fail(QSV_EINVAL, "sv_norm_fp64: null output");
+    if ((st = check_device()) != QSV_OK) return st;
+    double *part = nullptr;
+    if ((st = norm_partials(&part)) != QSV_OK) return st;
+    hipError_t e = launch_norm(static_cast<const float2 *>(amps), n_qubits, out_dev, part,
+                               static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_norm_fp64");
+}
+
+qsv_status sv_branch_combine(const void *a_tab, const void *b_tab, size_t n_branches, size_t m,
+                             const int8_t *sign_dev, void *out_dev, void *stream) {
+    if (m && (!a_tab || !b_tab || !out_dev)) return fail(QSV_EINVAL, "sv_branch_combine: null buffer");
+    if (m > (size_t(1) << 36) || n_branches > (size_t(1) << 40))
+        return fail(QSV_ERANGE, "sv_branch_combine: size out of range");
+    qsv_status st = check_device();
+    if (st != QSV_OK) return st;
+    hipError_t e = launch_branch_combine(static_cast<const float2 *>(a_tab),
+                                         static_cast<const float2 *>(b_tab), n_branches, m, sign_dev,
+                                         static_cast<double2 *>(out_dev),
+                                         static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_branch_combine");
+}
+
+qsv_status sv_plan_info(const qsv_circuit *c, int layer_begin, int layer_end,
+                        const qsv_fuse_opts *opts, int *n_passes, int32_t *pass_of_gate,
+                        int32_t *order_in_pass, size_t n_gate_cap, uint64_t *resident_mask,
+                        size_t pass_cap) {
+    if (!c || !n_passes) return fail(QSV_EINVAL, "sv_plan_info: null argument");
+    TileShape sh;
+    qsv_status st = resolve_shape(c, opts, sh);
+    if (st != QSV_OK) return st;
+    if (sh.R == 0) return fail(QSV_EUNSUPPORTED, "sv_plan_info: state too small for a tile");
+    std::shared_ptr<Plan> plan;
+    if ((st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) return st;
+    *n_passes = int(plan->passes.size());
+    if (pass_of_gate || order_in_pass) {
+        size_t ng = std::min(n_gate_cap, c->gates.size());
+        for (size_t i = 0; i < ng; ++i) {
+            if (pass_of_gate) pass_of_gate[i] = -1;
+            if (order_in_pass) order_in_pass[i] = -1;
+        }
+        for (size_t p = 0; p < plan->passes.size(); ++p) {
+            const auto &gs = plan->passes[p].gates;
+            for (size_t k = 0; k < gs.size(); ++k) {
+                if (size_t(gs[k]) >= ng) continue;
+                if (pass_of_gate) pass_of_gate[gs[k]] = int32_t(p);
+                if (order_in_pass) order_in_pass[gs[k]] = int32_t(k);
+            }
+        }
+    }
+    if (resident_mask)
+        for (size_t p = 0; p < std::min(pass_cap, plan->passes.size()); ++p)
+            resident_mask[p] = plan->passes[p].resident_logical;
+    return QSV_OK;
+}
+
+qsv_status sv_debug_emulate(void *amps_host, const qsv_circuit *c, uint64_t branch,
+                            int layer_begin, int layer_end, const qsv_fuse_opts *opts) {
+    if (!c || !amps_host) return fail(QSV_EINVAL, "sv_debug_emulate: null argument");
+    if (c->n > 26) return fail(QSV_ERANGE, "sv_debug_emulate: n must be <= 26");
+    TileShape sh;
+    qsv_status st = resolve_shape(c, opts, sh);
+    if (st != QSV_OK) return st;
+    if (sh.R == 0) return fail(QSV_EUNSUPPORTED, "sv_debug_emulate: state too small for a tile");
+    std::shared_ptr<Plan> plan;
+    if ((st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) return st;
+    for (const Pass &p : plan->passes)
+        emulate_pass(p.prog, c->n, sh.R, sh.T, branch, static_cast<float *>(amps_host));
+    return QSV_OK;
+}
+
+}  // extern "C"

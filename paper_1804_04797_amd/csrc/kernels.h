@@ -1,0 +1,24 @@
+// Host-side launchers of the HIP kernels (implemented in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "qsv_internal.h"
+
+namespace qsv {
+
+bool fused_shape_supported(int R, int T);
+hipError_t launch_fused(float2 *amps, int n, int R, int T, const PassProg &p, uint64_t branch,
+                        hipStream_t s);
+hipError_t launch_plain_1q(float2 *amps, int n, int q, const float m[8], hipStream_t s);
+hipError_t launch_plain_phase(float2 *amps, int n, int q, float cr, float ci, hipStream_t s);
+hipError_t launch_plain_cz(float2 *amps, int n, int q0, int q1, hipStream_t s);
+hipError_t launch_plain_zero(float2 *amps, int n, int q, int l, hipStream_t s);
+hipError_t launch_init(float2 *amps, int n, int kind, uint64_t basis, hipStream_t s);
+hipError_t launch_gather(const float2 *amps, int n, const uint64_t *xs, uint64_t m, void *out,
+                         int c128, hipStream_t s);
+hipError_t launch_norm(const float2 *amps, int n, double *out, double *partials, hipStream_t s);
+hipError_t launch_branch_combine(const float2 *A, const float2 *B, uint64_t nb, uint64_t m,
+                                 const int8_t *sign, double2 *out, hipStream_t s);
+
+}  // namespace qsv

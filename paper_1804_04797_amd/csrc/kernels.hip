@@ -1,0 +1,605 @@
+// HIP kernels of the state-vector sweep for gfx950 (MI355X), and their
+// host-side launchers.
+//
+// State: 2^n complex64 amplitudes, interleaved (re, im) float32, qubit k =
+// index bit k (Section 2, preliminaries).  All kernels use 64-bit indices
+// (2^34 amplitudes exceed 32 bits).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace qsv {
+namespace {
+
+__device__ __forceinline__ float2 f2(float x, float y) { return make_float2(x, y); }
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// e^{i pi k / 4}, k = 0..7
+__constant__ float c_wr[8] = {1.f, 0.70710678118654752f, 0.f, -0.70710678118654752f,
+                              -1.f, -0.70710678118654752f, 0.f, 0.70710678118654752f};
+__constant__ float c_wi[8] = {0.f, 0.70710678118654752f, 1.f, 0.70710678118654752f,
+                              0.f, -0.70710678118654752f, -1.f, -0.70710678118654752f};
+
+// ---------------------------------------------------------------------------
+// Register-slot primitives.  v[j] holds the amplitude whose register-slot
+// bits are j; slot S pairs v[j] with v[j | 2^S].
+// ---------------------------------------------------------------------------
+
+template <int S, int N> __device__ __forceinline__ void bf_h(float2 (&v)[N]) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if (j & (1 << S)) continue;
+        const float2 x = v[j], y = v[j | (1 << S)];
+        v[j] = f2(x.x + y.x, x.y + y.y);
+        v[j | (1 << S)] = f2(x.x - y.x, x.y - y.y);
+    }
+}
+template <int S, int N> __device__ __forceinline__ void bf_sx(float2 (&v)[N]) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if (j & (1 << S)) continue;
+        const float2 x = v[j], y = v[j | (1 << S)];
+        v[j] = f2(x.x + y.y, x.y - y.x);            // x - i y
+        v[j | (1 << S)] = f2(y.x + x.y, y.y - x.x); // y - i x
+    }
+}
+template <int S, int N> __device__ __forceinline__ void bf_sy(float2 (&v)[N]) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if (j & (1 << S)) continue;
+        const float2 x = v[j], y = v[j | (1 << S)];
+        v[j] = f2(x.x - y.x, x.y - y.y);
+        v[j | (1 << S)] = f2(x.x + y.x, x.y + y.y);
+    }
+}
+template <int S, int N> __device__ __forceinline__ void bf_sxdg(float2 (&v)[N]) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if (j & (1 << S)) continue;
+        const float2 x = v[j], y = v[j | (1 << S)];
+        v[j] = f2(x.x - y.y, x.y + y.x);            // x + i y
+        v[j | (1 << S)] = f2(y.x - x.y, y.y + x.x); // y + i x
+    }
+}
+template <int S, int N> __device__ __forceinline__ void bf_sydg(float2 (&v)[N]) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if (j & (1 << S)) continue;
+        const float2 x = v[j], y = v[j | (1 << S)];
+        v[j] = f2(x.x + y.x, x.y + y.y);
+        v[j | (1 << S)] = f2(y.x - x.x, y.y - x.y);
+    }
+}
+__device__ __forceinline__ float2 cmul(float2 a, float cr, float ci) {
+    return f2(a.x * cr - a.y * ci, a.x * ci + a.y * cr);
+}
+// multiply amplitudes with slot bit S = 1 by (cr, ci)
+template <int S, int N> __device__ __forceinline__ void ph_slot(float2 (&v)[N], float cr, float ci) {
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        if (j & (1 << S)) v[j] = cmul(v[j], cr, ci);
+}
+template <int S, int N> __device__ __forceinline__ void neg_slot(float2 (&v)[N]) {
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        if (j & (1 << S)) v[j] = f2(-v[j].x, -v[j].y);
+}
+template <int S1, int S2, int N> __device__ __forceinline__ void neg_slot2(float2 (&v)[N]) {
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        if ((j & (1 << S1)) && (j & (1 << S2))) v[j] = f2(-v[j].x, -v[j].y);
+}
+// zero amplitudes whose slot bit S differs from l
+template <int S, int N> __device__ __forceinline__ void proj_slot(float2 (&v)[N], int l) {
+    if (l) {
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            if (!(j & (1 << S))) v[j] = f2(0.f, 0.f);
+    } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            if (j & (1 << S)) v[j] = f2(0.f, 0.f);
+    }
+}
+
+// Dispatch a runtime register-slot index to a compile-time template.
+#define QSV_SLOT_DISPATCH(s, CALL)                                   \
+    switch (s) {                                                     \
+    case 0: { constexpr int S_ = 0; CALL; } break;                   \
+    case 1: if constexpr (R > 1) { constexpr int S_ = 1; CALL; } break; \
+    case 2: if constexpr (R > 2) { constexpr int S_ = 2; CALL; } break; \
+    case 3: if constexpr (R > 3) { constexpr int S_ = 3; CALL; } break; \
+    case 4: if constexpr (R > 4) { constexpr int S_ = 4; CALL; } break; \
+    case 5: if constexpr (R > 5) { constexpr int S_ = 5; CALL; } break; \
+    default: break;                                                  \
+    }
+
+template <int R, int S1, int N>
+__device__ __forceinline__ void cz_reg_reg(float2 (&v)[N], int s2) {
+    switch (s2) {
+    case 0: if constexpr (S1 != 0) neg_slot2<S1, 0>(v); break;
+    case 1: if constexpr (R > 1 && S1 != 1) neg_slot2<S1, 1>(v); break;
+    case 2: if constexpr (R > 2 && S1 != 2) neg_slot2<S1, 2>(v); break;
+    case 3: if constexpr (R > 3 && S1 != 3) neg_slot2<S1, 3>(v); break;
+    case 4: if constexpr (R > 4 && S1 != 4) neg_slot2<S1, 4>(v); break;
+    case 5: if constexpr (R > 5 && S1 != 5) neg_slot2<S1, 5>(v); break;
+    default: break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused tile pass.
+//
+// One workgroup of 2^T threads owns one tile of 2^(R+T) amplitudes: slot
+// coordinate x = j | t << R (j = register index, t = thread index) sits at
+// physical index base | sum_{s: x_s = 1} 2^{phys[s]}.  Loads and stores are
+// 16-byte (two amplitudes: register slot 0 is physical bit 0) and the thread
+// slots 0..c-2 hold physical bits 1..c-1, so each wave access is made of
+// contiguous runs of 2^c amplitudes.  XCHG permutes slot bits through LDS
+// (write at padded old coordinate, read at padded new coordinate; one pad
+// element per 2^R keeps the 64 lanes of a wave on distinct banks).
+// ---------------------------------------------------------------------------
+template <int R, int T>
+__global__ void __launch_bounds__(1 << T)
+k_fused(float2 *__restrict__ amps, const PassProg P, uint64_t branch, uint64_t tile0) {
+    constexpr int N = 1 << R;
+    extern __shared__ float2 lds[];
+    const uint32_t t = threadIdx.x;
+    const uint64_t tile = tile0 + blockIdx.x;
+
+    uint64_t base = 0;
+    for (int i = 0; i < P.n_glob; ++i) base |= ((tile >> i) & 1ull) << P.glob_bits[i];
+
+    float2 v[N];
+    {
+        uint64_t toff = 0;
+#pragma unroll
+        for (int u = 0; u < T; ++u)
+            if ((t >> u) & 1u) toff |= 1ull << P.ld_phys[R + u];
+        const float2 *src = amps + (base | toff);
+#pragma unroll
+        for (int j = 0; j < N; j += 2) {
+            uint64_t roff = 0;
+#pragma unroll
+            for (int s = 1; s < R; ++s)
+                if ((j >> s) & 1) roff |= 1ull << P.ld_phys[s];
+            const v4f w = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(src + roff));
+            v[j] = f2(w.x, w.y);
+            v[j + 1] = f2(w.z, w.w);
+        }
+    }
+
+    auto pred = [&](uint32_t loc) -> uint32_t {
+        if (loc & 0x80u) return uint32_t((base >> (loc & 0x7fu)) & 1ull);
+        return (t >> (loc - R)) & 1u;
+    };
+
+    for (int pc = 0; pc < P.n_ops; ++pc) {
+        const uint64_t op = P.ops[pc];
+        const uint32_t code = uint32_t(op) & 0xffu;
+        const uint32_t a = uint32_t(op >> 8) & 0xffu;
+        const uint32_t b = uint32_t(op >> 16) & 0xffu;
+        const uint32_t c = uint32_t(op >> 24) & 0xffu;
+        switch (code) {
+        case 1: QSV_SLOT_DISPATCH(a, (bf_h<S_, N>(v))); break;
+        case 2: QSV_SLOT_DISPATCH(a, (bf_sx<S_, N>(v))); break;
+        case 3: QSV_SLOT_DISPATCH(a, (bf_sy<S_, N>(v))); break;
+        case 4: QSV_SLOT_DISPATCH(a, (bf_sxdg<S_, N>(v))); break;
+        case 5: QSV_SLOT_DISPATCH(a, (bf_sydg<S_, N>(v))); break;
+        case 8: {  // PHASE
+            const float cr = c_wr[b], ci = c_wi[b];
+            if (a < uint32_t(R)) {
+                QSV_SLOT_DISPATCH(a, (ph_slot<S_, N>(v, cr, ci)));
+            } else if (pred(a)) {
+#pragma unroll
+                for (int j = 0; j < N; ++j) v[j] = cmul(v[j], cr, ci);
+            }
+            break;
+        }
+        case 9: {  // CZ
+            uint32_t x = a, y = b;
+            if (x >= uint32_t(R) && y < uint32_t(R)) { uint32_t tmp = x; x = y; y = tmp; }
+            if (x < uint32_t(R) && y < uint32_t(R)) {
+                QSV_SLOT_DISPATCH(x, (cz_reg_reg<R, S_, N>(v, int(y))));
+            } else if (x < uint32_t(R)) {
+                if (pred(y)) { QSV_SLOT_DISPATCH(x, (neg_slot<S_, N>(v))); }
+            } else if (pred(x) & pred(y)) {
+#pragma unroll
+                for (int j = 0; j < N; ++j) v[j] = f2(-v[j].x, -v[j].y);
+            }
+            break;
+        }
+        case 10: {  // PROJ
+            const int l = c ? int((branch >> b) & 1ull) : int(b);
+            if (a < uint32_t(R)) {
+                QSV_SLOT_DISPATCH(a, (proj_slot<S_, N>(v, l)));
+            } else if (int(pred(a)) != l) {
+#pragma unroll
+                for (int j = 0; j < N; ++j) v[j] = f2(0.f, 0.f);
+            }
+            break;
+        }
+        case 11: {  // ZB
+            if ((branch >> b) & 1ull) {
+                if (a < uint32_t(R)) {
+                    QSV_SLOT_DISPATCH(a, (neg_slot<S_, N>(v)));
+                } else if (pred(a)) {
+#pragma unroll
+                    for (int j = 0; j < N; ++j) v[j] = f2(-v[j].x, -v[j].y);
+                }
+            }
+            break;
+        }
+        case 12: {  // XCHG: new slot s takes old slot perm[s]
+            const uint64_t pw = P.ops[++pc];
+            __syncthreads();  // earlier reads of LDS are complete
+            const uint32_t wt = (t << R) + t;  // padded old coordinate of (t, 0)
+#pragma unroll
+            for (int j = 0; j < N; ++j) lds[wt + j] = v[j];
+            uint32_t yt = 0;
+#pragma unroll
+            for (int u = 0; u < T; ++u)
+                if ((t >> u) & 1u) yt |= 1u << ((pw >> (4 * (R + u))) & 0xf);
+            const uint32_t rt = yt + (yt >> R);
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                uint32_t yj = 0;
+#pragma unroll
+                for (int s = 0; s < R; ++s)
+                    if ((j >> s) & 1) yj |= 1u << ((pw >> (4 * s)) & 0xf);
+                v[j] = lds[rt + yj + (yj >> R)];
+            }
+            break;
+        }
+        case 13: {  // SCALE
+            const float cr = P.scale_re, ci = P.scale_im;
+            if (ci == 0.f) {
+#pragma unroll
+                for (int j = 0; j < N; ++j) v[j] = f2(v[j].x * cr, v[j].y * cr);
+            } else {
+#pragma unroll
+                for (int j = 0; j < N; ++j) v[j] = cmul(v[j], cr, ci);
+            }
+            break;
+        }
+        default:
+            break;
+        }
+    }
+
+    {
+        uint64_t toff = 0;
+#pragma unroll
+        for (int u = 0; u < T; ++u)
+            if ((t >> u) & 1u) toff |= 1ull << P.st_phys[R + u];
+        float2 *dst = amps + (base | toff);
+#pragma unroll
+        for (int j = 0; j < N; j += 2) {
+            uint64_t roff = 0;
+#pragma unroll
+            for (int s = 1; s < R; ++s)
+                if ((j >> s) & 1) roff |= 1ull << P.st_phys[s];
+            const v4f w = {v[j].x, v[j].y, v[j + 1].x, v[j + 1].y};
+            __builtin_nontemporal_store(w, reinterpret_cast<v4f *>(dst + roff));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plain (unfused) gate kernels: one launch per gate.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t insert_zero(uint64_t i, int q) {
+    const uint64_t lo = i & ((1ull << q) - 1);
+    return ((i >> q) << (q + 1)) | lo;
+}
+
+// General single-qubit gate, pair rule of Section 2 (preliminaries).
+__global__ void __launch_bounds__(256)
+k_plain_1q(float2 *__restrict__ a, uint64_t pairs, int q, float m0r, float m0i, float m1r,
+           float m1i, float m2r, float m2i, float m3r, float m3i) {
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < pairs; i += stride) {
+        const uint64_t lo = insert_zero(i, q), hi = lo | (1ull << q);
+        const float2 x = a[lo], y = a[hi];
+        a[lo] = f2(m0r * x.x - m0i * x.y + m1r * y.x - m1i * y.y,
+                   m0r * x.y + m0i * x.x + m1r * y.y + m1i * y.x);
+        a[hi] = f2(m2r * x.x - m2i * x.y + m3r * y.x - m3i * y.y,
+                   m2r * x.y + m2i * x.x + m3r * y.y + m3i * y.x);
+    }
+}
+
+// Multiply amplitudes with bit q = 1 by (cr, ci): touches half the state.
+__global__ void __launch_bounds__(256)
+k_plain_phase(float2 *__restrict__ a, uint64_t count, int q, float cr, float ci) {
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) {
+        const uint64_t k = insert_zero(i, q) | (1ull << q);
+        a[k] = cmul(a[k], cr, ci);
+    }
+}
+
+// Negate amplitudes with bits q0 and q1 set (q0 < q1): a quarter of the state.
+__global__ void __launch_bounds__(256)
+k_plain_cz(float2 *__restrict__ a, uint64_t count, int q0, int q1) {
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) {
+        const uint64_t k = insert_zero(insert_zero(i, q0), q1) | (1ull << q0) | (1ull << q1);
+        const float2 x = a[k];
+        a[k] = f2(-x.x, -x.y);
+    }
+}
+
+// Zero amplitudes whose bit q is != l (projector P_l): write-only, half the state.
+__global__ void __launch_bounds__(256)
+k_plain_zero(float2 *__restrict__ a, uint64_t count, int q, int l) {
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) {
+        const uint64_t k = insert_zero(i, q) | (uint64_t(1 - l) << q);
+        a[k] = f2(0.f, 0.f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation, gather, norm, branch combine.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256)
+k_init(v4f *__restrict__ a, uint64_t quads, float val, int kind, uint64_t basis) {
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < quads; i += stride) {
+        v4f w;
+        if (kind == 1) {
+            w = v4f{val, 0.f, val, 0.f};
+        } else {
+            w = v4f{0.f, 0.f, 0.f, 0.f};
+            if ((basis >> 1) == i) {
+                if (basis & 1) w.z = 1.f; else w.x = 1.f;
+            }
+        }
+        __builtin_nontemporal_store(w, a + i);
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_init_small(float2 *__restrict__ a, uint64_t dim, float val, int kind, uint64_t basis) {
+    const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= dim) return;
+    if (kind == 1) a[i] = f2(val, 0.f);
+    else a[i] = f2(i == basis ? 1.f : 0.f, 0.f);
+}
+
+__global__ void __launch_bounds__(256)
+k_gather(const float2 *__restrict__ a, uint64_t dim, const uint64_t *__restrict__ xs, uint64_t m,
+         void *__restrict__ out, int c128) {
+    const uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const uint64_t x = xs[k];
+    float2 v;
+    if (x < dim) v = a[x];
+    else v = f2(__builtin_nanf(""), __builtin_nanf(""));
+    if (c128) reinterpret_cast<double2 *>(out)[k] = make_double2(double(v.x), double(v.y));
+    else reinterpret_cast<float2 *>(out)[k] = v;
+}
+
+// Block b sums |a_i|^2 over its contiguous chunk in FP64 (products of FP32
+// values are exact in FP64); fixed thread-then-tree order.
+__global__ void __launch_bounds__(256)
+k_norm_partial(const float4 *__restrict__ a, uint64_t quads_per_block, double *__restrict__ part) {
+    __shared__ double s[256];
+    const uint64_t start = uint64_t(blockIdx.x) * quads_per_block;
+    double acc = 0.0;
+    for (uint64_t i = threadIdx.x; i < quads_per_block; i += 256) {
+        const float4 w = a[start + i];
+        const double x0 = w.x, y0 = w.y, x1 = w.z, y1 = w.w;
+        acc += (x0 * x0 + y0 * y0) + (x1 * x1 + y1 * y1);
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (int(threadIdx.x) < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+// Pairwise sum of count partials (count <= 65536) by one block.
+__global__ void __launch_bounds__(256)
+k_sum_partials(const double *__restrict__ part, int count, double *__restrict__ out) {
+    __shared__ double s[256];
+    // each thread sums a strided subset pairwise-by-level
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < count; i += 256) acc += part[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (int(threadIdx.x) < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+__global__ void __launch_bounds__(256)
+k_norm_small(const float2 *__restrict__ a, uint64_t dim, double *__restrict__ out) {
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (uint64_t i = threadIdx.x; i < dim; i += 256) {
+        const double x = a[i].x, y = a[i].y;
+        acc += x * x + y * y;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (int(threadIdx.x) < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+// out[x] = sign[x] * sum_b A[b][x] * B[b][x]: 64 outputs per block, four
+// branch groups of 64 lanes each; FP64 products and sums, fixed order.
+__global__ void __launch_bounds__(256)
+k_branch_combine(const float2 *__restrict__ A, const float2 *__restrict__ B, uint64_t nb,
+                 uint64_t m, const int8_t *__restrict__ sign, double2 *__restrict__ out) {
+    __shared__ double sr[4][64], si[4][64];
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const uint64_t x = uint64_t(blockIdx.x) * 64 + lane;
+    double ar = 0.0, ai = 0.0;
+    if (x < m) {
+        for (uint64_t b = grp; b < nb; b += 4) {
+            const float2 p = A[b * m + x], q = B[b * m + x];
+            const double pr = p.x, pi = p.y, qr = q.x, qi = q.y;
+            ar += pr * qr - pi * qi;
+            ai += pr * qi + pi * qr;
+        }
+    }
+    sr[grp][lane] = ar;
+    si[grp][lane] = ai;
+    __syncthreads();
+    if (grp == 0 && x < m) {
+        double r = (sr[0][lane] + sr[1][lane]) + (sr[2][lane] + sr[3][lane]);
+        double i = (si[0][lane] + si[1][lane]) + (si[2][lane] + si[3][lane]);
+        if (sign && sign[x] < 0) { r = -r; i = -i; }
+        out[x] = make_double2(r, i);
+    }
+}
+
+unsigned grid_for(uint64_t work, unsigned per_block = 256, unsigned cap = 1u << 20) {
+    uint64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return unsigned(g);
+}
+
+template <int R, int T>
+hipError_t launch_fused_t(float2 *amps, int n, const PassProg &p, uint64_t branch, hipStream_t s) {
+    constexpr int L = R + T;
+    const size_t lds = (size_t(1) << L) * sizeof(float2) + (size_t(1) << T) * sizeof(float2);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fused<R, T>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const uint64_t tiles = 1ull << (n - L);
+    const uint64_t chunk = 1ull << 30;  // blocks per launch
+    for (uint64_t t0 = 0; t0 < tiles; t0 += chunk) {
+        const uint64_t cnt = (tiles - t0 < chunk) ? tiles - t0 : chunk;
+        hipLaunchKernelGGL((k_fused<R, T>), dim3(unsigned(cnt)), dim3(1 << T), lds, s, amps, p,
+                           branch, t0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+bool fused_shape_supported(int R, int T) {
+    switch (R * 16 + T) {
+    case 5 * 16 + 8: case 5 * 16 + 7: case 4 * 16 + 7: case 4 * 16 + 6: case 3 * 16 + 6:
+    case 3 * 16 + 4: case 2 * 16 + 3: case 4 * 16 + 8: case 6 * 16 + 8: case 5 * 16 + 9:
+    case 4 * 16 + 9: case 6 * 16 + 7:
+        return true;
+    default:
+        return false;
+    }
+}
+
+hipError_t launch_fused(float2 *amps, int n, int R, int T, const PassProg &p, uint64_t branch,
+                        hipStream_t s) {
+    switch (R * 16 + T) {
+    case 5 * 16 + 8: return launch_fused_t<5, 8>(amps, n, p, branch, s);
+    case 5 * 16 + 7: return launch_fused_t<5, 7>(amps, n, p, branch, s);
+    case 4 * 16 + 7: return launch_fused_t<4, 7>(amps, n, p, branch, s);
+    case 4 * 16 + 6: return launch_fused_t<4, 6>(amps, n, p, branch, s);
+    case 3 * 16 + 6: return launch_fused_t<3, 6>(amps, n, p, branch, s);
+    case 3 * 16 + 4: return launch_fused_t<3, 4>(amps, n, p, branch, s);
+    case 2 * 16 + 3: return launch_fused_t<2, 3>(amps, n, p, branch, s);
+    case 4 * 16 + 8: return launch_fused_t<4, 8>(amps, n, p, branch, s);
+    case 6 * 16 + 8: return launch_fused_t<6, 8>(amps, n, p, branch, s);
+    case 5 * 16 + 9: return launch_fused_t<5, 9>(amps, n, p, branch, s);
+    case 4 * 16 + 9: return launch_fused_t<4, 9>(amps, n, p, branch, s);
+    case 6 * 16 + 7: return launch_fused_t<6, 7>(amps, n, p, branch, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_plain_1q(float2 *amps, int n, int q, const float m[8], hipStream_t s) {
+    const uint64_t pairs = 1ull << (n - 1);
+    hipLaunchKernelGGL(k_plain_1q, dim3(grid_for(pairs)), dim3(256), 0, s, amps, pairs, q, m[0],
+                       m[1], m[2], m[3], m[4], m[5], m[6], m[7]);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_phase(float2 *amps, int n, int q, float cr, float ci, hipStream_t s) {
+    const uint64_t cnt = 1ull << (n - 1);
+    hipLaunchKernelGGL(k_plain_phase, dim3(grid_for(cnt)), dim3(256), 0, s, amps, cnt, q, cr, ci);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_cz(float2 *amps, int n, int q0, int q1, hipStream_t s) {
+    if (q0 > q1) { int t = q0; q0 = q1; q1 = t; }
+    const uint64_t cnt = 1ull << (n - 2);
+    hipLaunchKernelGGL(k_plain_cz, dim3(grid_for(cnt)), dim3(256), 0, s, amps, cnt, q0, q1);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_zero(float2 *amps, int n, int q, int l, hipStream_t s) {
+    const uint64_t cnt = 1ull << (n - 1);
+    hipLaunchKernelGGL(k_plain_zero, dim3(grid_for(cnt)), dim3(256), 0, s, amps, cnt, q, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(float2 *amps, int n, int kind, uint64_t basis, hipStream_t s) {
+    const uint64_t dim = 1ull << n;
+    const float val = float(1.0 / __builtin_sqrt(double(dim)));
+    if (n >= 1) {
+        const uint64_t quads = dim / 2;
+        hipLaunchKernelGGL(k_init, dim3(grid_for(quads)), dim3(256), 0, s,
+                           reinterpret_cast<v4f *>(amps), quads, val, kind, basis);
+    } else {
+        hipLaunchKernelGGL(k_init_small, dim3(1), dim3(256), 0, s, amps, dim, val, kind, basis);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const float2 *amps, int n, const uint64_t *xs, uint64_t m, void *out,
+                         int c128, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(m, 256, 1u << 30)), dim3(256), 0, s, amps,
+                       1ull << n, xs, m, out, c128);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm(const float2 *amps, int n, double *out, double *partials, hipStream_t s) {
+    const uint64_t dim = 1ull << n;
+    if (n < 14) {
+        hipLaunchKernelGGL(k_norm_small, dim3(1), dim3(256), 0, s, amps, dim, out);
+        return hipGetLastError();
+    }
+    // at most 65536 blocks; each block a contiguous chunk of >= 2^13 quads
+    int lb = n - 1 - 10;           // log2(blocks) so that each block has 1024 quads
+    if (lb > 16) lb = 16;
+    const unsigned blocks = 1u << lb;
+    const uint64_t qpb = (dim / 2) >> lb;
+    hipLaunchKernelGGL(k_norm_partial, dim3(blocks), dim3(256), 0, s,
+                       reinterpret_cast<const float4 *>(amps), qpb, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, int(blocks), out);
+    return hipGetLastError();
+}
+
+hipError_t launch_branch_combine(const float2 *A, const float2 *B, uint64_t nb, uint64_t m,
+                                 const int8_t *sign, double2 *out, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_branch_combine, dim3(unsigned((m + 63) / 64)), dim3(256), 0, s, A, B, nb,
+                       m, sign, out);
+    return hipGetLastError();
+}
+
+}  // namespace qsv

@@ -1,0 +1,454 @@
+// Pass planner: groups the gates of a layer range into full-state passes.
+//
+// Section 2.4 observes that a chunk of the state held in fast local memory
+// can absorb every gate on the chunk's "local" qubits before it is written
+// back, that diagonal gates (T, CZ) can be applied on any qubit, and that
+// qubit reordering makes this repeatable.  Here a pass streams the whole
+// state once in tiles of 2^(R+T) amplitudes: R qubits live in each thread's
+// registers, T qubits across the threads of a workgroup, and the remaining
+// index bits select the tile.  A non-diagonal gate needs its qubit in a
+// register slot; slot contents are permuted through LDS by XCHG ops (the
+// analogue of the paper's rank swaps, done per tile instead of as a separate
+// transpose of the whole state).  Diagonal gates read the bit of a thread
+// slot from the thread index and the bit of a non-resident qubit from the
+// tile index.
+//
+// Scalar factors are pulled out of the non-diagonal gates: H, SX, SY (and
+// adjoints) are applied as sum/difference butterflies and each pass ends by
+// multiplying the state with the product of the removed factors, so the
+// state is exact (up to rounding) after every pass.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "qsv_internal.h"
+
+namespace qsv {
+
+void gates_in_range(const qsv_circuit &c, int lb, int le, std::vector<int> &idx) {
+    idx.clear();
+    for (size_t i = 0; i < c.gates.size(); ++i) {
+        int l = c.gates[i].layer;
+        if (l >= lb && (le < 0 || l < le)) idx.push_back(int(i));
+    }
+}
+
+TileShape default_shape(int n) {
+    // (R, T) of the compiled kernels, largest tile first; the tuner may pick
+    // another one.  c low bits stay resident so every access is a run of
+    // 2^c amplitudes (2^c * 8 bytes).
+    static const int shapes[][2] = {{5, 8}, {5, 7}, {4, 7}, {4, 6}, {3, 6}, {3, 4}, {2, 3}};
+    for (auto &s : shapes) {
+        if (s[0] + s[1] <= n) {
+            int c = std::min(5, s[1] + 1);
+            return {s[0], s[1], c};
+        }
+    }
+    return {0, 0, 0};
+}
+
+namespace {
+
+struct G {
+    uint8_t kind;
+    int q0, q1;   // q1 = -1 for single-qubit gates
+    int arg;
+    bool nd;      // non-diagonal
+};
+
+struct DepGraph {
+    std::vector<G> g;
+    std::vector<std::vector<int>> succ;
+    std::vector<int> npred;
+};
+
+DepGraph build_deps(const qsv_circuit &c, const std::vector<int> &idx) {
+    DepGraph d;
+    const int n = c.n;
+    d.g.resize(idx.size());
+    d.succ.resize(idx.size());
+    d.npred.assign(idx.size(), 0);
+    std::vector<int> last_nd(n, -1);
+    std::vector<std::vector<int>> since(n);
+    for (size_t i = 0; i < idx.size(); ++i) {
+        const qsv_gate &x = c.gates[idx[i]];
+        G &y = d.g[i];
+        y.kind = x.kind;
+        y.q0 = x.q0;
+        y.q1 = (x.kind == QSV_CZ) ? x.q1 : -1;
+        y.arg = x.arg;
+        y.nd = !gate_is_diagonal(x.kind);
+        std::vector<int> pre;
+        int qs[2] = {y.q0, y.q1};
+        for (int k = 0; k < 2; ++k) {
+            int q = qs[k];
+            if (q < 0) continue;
+            if (y.nd) {
+                for (int p : since[q]) pre.push_back(p);
+                if (last_nd[q] >= 0) pre.push_back(last_nd[q]);
+            } else if (last_nd[q] >= 0) {
+                pre.push_back(last_nd[q]);
+            }
+        }
+        std::sort(pre.begin(), pre.end());
+        pre.erase(std::unique(pre.begin(), pre.end()), pre.end());
+        for (int p : pre) d.succ[p].push_back(int(i));
+        d.npred[i] = int(pre.size());
+        for (int k = 0; k < 2; ++k) {
+            int q = qs[k];
+            if (q < 0) continue;
+            if (y.nd) {
+                last_nd[q] = int(i);
+                since[q].clear();
+            } else {
+                since[q].push_back(int(i));
+            }
+        }
+    }
+    return d;
+}
+
+// Gates (in a valid order) that one pass with resident set `res` can apply,
+// given the current done flags and pending-predecessor counts.
+int simulate_pass(const DepGraph &d, const std::vector<char> &done, const std::vector<int> &pend,
+                  uint64_t res, std::vector<int> *order) {
+    std::vector<int> p = pend;
+    std::vector<char> dn = done;
+    // process in index order with a min-heap of ready gates
+    std::vector<int> ready;
+    for (size_t i = 0; i < d.g.size(); ++i)
+        if (!dn[i] && p[i] == 0) ready.push_back(int(i));
+    std::make_heap(ready.begin(), ready.end(), std::greater<int>());
+    int count = 0;
+    std::vector<int> blocked;
+    while (!ready.empty()) {
+        std::pop_heap(ready.begin(), ready.end(), std::greater<int>());
+        int i = ready.back();
+        ready.pop_back();
+        const G &x = d.g[i];
+        if (x.nd && !((res >> x.q0) & 1)) continue;  // blocked for this pass
+        dn[i] = 1;
+        ++count;
+        if (order) order->push_back(i);
+        for (int s : d.succ[i]) {
+            if (--p[s] == 0) {
+                ready.push_back(s);
+                std::push_heap(ready.begin(), ready.end(), std::greater<int>());
+            }
+        }
+    }
+    return count;
+}
+
+int first_pending_nd(const DepGraph &d, const std::vector<char> &done, int q) {
+    for (size_t i = 0; i < d.g.size(); ++i)
+        if (!done[i] && d.g[i].nd && d.g[i].q0 == q) return int(i);
+    return 1 << 30;
+}
+
+uint64_t choose_resident(const DepGraph &d, const std::vector<char> &done,
+                         const std::vector<int> &pend, int n, int L, uint64_t forced) {
+    uint64_t S = forced;
+    int size = __builtin_popcountll(S);
+    std::vector<int> first(n);
+    for (int q = 0; q < n; ++q) first[q] = first_pending_nd(d, done, q);
+    while (size < L) {
+        int best_q = -1, best_gain = -1, best_first = 0;
+        for (int q = 0; q < n; ++q) {
+            if ((S >> q) & 1) continue;
+            int gain = simulate_pass(d, done, pend, S | (1ull << q), nullptr);
+            if (gain > best_gain || (gain == best_gain && first[q] < best_first)) {
+                best_gain = gain;
+                best_q = q;
+                best_first = first[q];
+            }
+        }
+        S |= 1ull << best_q;
+        ++size;
+    }
+    // hill climbing: swap one non-forced member for one outsider
+    int cur = simulate_pass(d, done, pend, S, nullptr);
+    for (int iter = 0; iter < 4; ++iter) {
+        bool improved = false;
+        for (int a = 0; a < n && !improved; ++a) {
+            if (!((S >> a) & 1) || ((forced >> a) & 1)) continue;
+            for (int b = 0; b < n; ++b) {
+                if ((S >> b) & 1) continue;
+                uint64_t S2 = (S & ~(1ull << a)) | (1ull << b);
+                int v = simulate_pass(d, done, pend, S2, nullptr);
+                if (v > cur) {
+                    S = S2;
+                    cur = v;
+                    improved = true;
+                    break;
+                }
+            }
+        }
+        if (!improved) break;
+    }
+    return S;
+}
+
+// Slot bookkeeping of one tile during a pass.
+struct Slots {
+    int R, T, L;
+    int occ[kMaxSlots];   // qubit held by slot
+    int where[64];        // slot of a resident qubit, -1 otherwise
+    void set(int s, int q) { occ[s] = q; where[q] = s; }
+};
+
+struct ProgBuilder {
+    std::vector<uint64_t> ops;
+    void op(uint64_t w) { ops.push_back(w); }
+    // permutation: new slot s takes old slot perm[s]
+    void xchg(const int *perm, int L) {
+        uint64_t w = 0;
+        for (int s = 0; s < L; ++s) w |= uint64_t(perm[s] & 0xf) << (4 * s);
+        ops.push_back(make_op(OP_XCHG));
+        ops.push_back(w);
+    }
+};
+
+uint8_t locator(const Slots &sl, int q) {
+    int s = sl.where[q];
+    return s >= 0 ? uint8_t(s) : uint8_t(kLocGlobal | q);
+}
+
+}  // namespace
+
+qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Plan &out) {
+    const int n = c.n;
+    const int R = shape.R, T = shape.T, L = R + T, cl = shape.c;
+    if (R < 1 || T < 1 || L > n || L > kMaxSlots || cl < 1 || cl - 1 > T || cl > L)
+        return fail(QSV_EUNSUPPORTED, "tile shape does not fit the circuit");
+    out = Plan();
+    out.n = n; out.R = R; out.T = T; out.c = cl;
+    gates_in_range(c, lb, le, out.gate_range);
+    const std::vector<int> &idx = out.gate_range;
+    DepGraph d = build_deps(c, idx);
+    const size_t NG = idx.size();
+    std::vector<char> done(NG, 0);
+    std::vector<int> pend = d.npred;
+    size_t n_done = 0;
+    // The low cl index bits are resident in every pass (contiguous runs).
+    const uint64_t forced = (cl >= 64) ? ~0ull : ((1ull << cl) - 1);
+    int total_phase = 0;  // exponent of w = e^{i pi/4} removed so far
+    int carry_half = 0;   // removed factors of 2^{-1/2} not yet applied
+
+    while (n_done < NG) {
+        uint64_t S = choose_resident(d, done, pend, n, L, forced);
+        // --- slot assignment at load time -----------------------------------
+        // slot 0 <- qubit 0 (physical bit 0, the pair inside one 16-byte load);
+        // thread slots 0..cl-2 <- qubits 1..cl-1; the other resident qubits go
+        // to register slots first by their first non-diagonal use in the pass.
+        std::vector<int> porder;
+        simulate_pass(d, done, pend, S, &porder);
+        std::vector<int> first_use(n, 1 << 30);
+        for (size_t k = 0; k < porder.size(); ++k) {
+            const G &x = d.g[porder[k]];
+            if (x.nd && first_use[x.q0] == (1 << 30)) first_use[x.q0] = int(k);
+        }
+        Slots sl;
+        sl.R = R; sl.T = T; sl.L = L;
+        std::fill(sl.where, sl.where + 64, -1);
+        std::fill(sl.occ, sl.occ + kMaxSlots, -1);
+        sl.set(0, 0);
+        for (int u = 0; u < cl - 1; ++u) sl.set(R + u, u + 1);
+        std::vector<int> rest;
+        for (int q = cl; q < n; ++q)
+            if ((S >> q) & 1) rest.push_back(q);
+        std::stable_sort(rest.begin(), rest.end(),
+                         [&](int a, int b) { return first_use[a] < first_use[b]; });
+        {
+            size_t k = 0;
+            for (int s = 1; s < R && k < rest.size(); ++s) sl.set(s, rest[k++]);
+            for (int u = cl - 1; u < T && k < rest.size(); ++u) sl.set(R + u, rest[k++]);
+        }
+        Pass pass;
+        PassProg &P = pass.prog;
+        std::memset(&P, 0, sizeof(P));
+        pass.resident_logical = S;
+        for (int s = 0; s < L; ++s) P.ld_phys[s] = uint8_t(sl.occ[s]);
+        {
+            int k = 0;
+            for (int q = 0; q < n; ++q)
+                if (!((S >> q) & 1)) P.glob_bits[k++] = uint8_t(q);
+            P.n_glob = k;
+        }
+
+        // --- list scheduling with register-slot exchanges -------------------
+        std::vector<char> dn = done;
+        std::vector<int> pd = pend;
+        std::vector<char> in_pass(NG, 0);
+        for (int i : porder) in_pass[i] = 1;
+        ProgBuilder pb;
+        const int budget = kMaxOps - 3 - 2;  // keep room for a final XCHG and SCALE
+        int m_nd = 0, phase = 0;
+        std::vector<int> sched;
+        size_t remaining = porder.size();
+        while (remaining > 0) {
+            bool progress = true;
+            while (progress) {
+                progress = false;
+                for (size_t k = 0; k < porder.size(); ++k) {
+                    int i = porder[k];
+                    if (dn[i] || pd[i] != 0) continue;
+                    const G &x = d.g[i];
+                    if (x.nd && !(sl.where[x.q0] >= 0 && sl.where[x.q0] < R)) continue;
+                    if (int(pb.ops.size()) + 1 > budget) break;
+                    // emit
+                    switch (x.kind) {
+                    case QSV_H: pb.op(make_op(OP_H, sl.where[x.q0])); ++m_nd; break;
+                    case QSV_SX: pb.op(make_op(OP_SX, sl.where[x.q0])); ++m_nd; phase += 1; break;
+                    case QSV_SY: pb.op(make_op(OP_SY, sl.where[x.q0])); ++m_nd; phase += 1; break;
+                    case QSV_SXDG: pb.op(make_op(OP_SXDG, sl.where[x.q0])); ++m_nd; phase += 7; break;
+                    case QSV_SYDG: pb.op(make_op(OP_SYDG, sl.where[x.q0])); ++m_nd; phase += 7; break;
+                    case QSV_T: pb.op(make_op(OP_PHASE, locator(sl, x.q0), 1)); break;
+                    case QSV_TDG: pb.op(make_op(OP_PHASE, locator(sl, x.q0), 7)); break;
+                    case QSV_Z: pb.op(make_op(OP_PHASE, locator(sl, x.q0), 4)); break;
+                    case QSV_CZ: pb.op(make_op(OP_CZ, locator(sl, x.q0), locator(sl, x.q1))); break;
+                    case QSV_P0: pb.op(make_op(OP_PROJ, locator(sl, x.q0), 0, 0)); break;
+                    case QSV_P1: pb.op(make_op(OP_PROJ, locator(sl, x.q0), 1, 0)); break;
+                    case QSV_PB: pb.op(make_op(OP_PROJ, locator(sl, x.q0), x.arg, 1)); break;
+                    case QSV_ZB: pb.op(make_op(OP_ZB, locator(sl, x.q0), x.arg)); break;
+                    default: return fail(QSV_EINTERNAL, "planner: unknown gate kind");
+                    }
+                    dn[i] = 1;
+                    --remaining;
+                    sched.push_back(i);
+                    for (int s : d.succ[i]) --pd[s];
+                    progress = true;
+                }
+                if (int(pb.ops.size()) + 1 > budget) break;
+            }
+            if (remaining == 0 || int(pb.ops.size()) + 3 > budget) break;
+            // Stuck: bring the qubits of ready non-diagonal gates into registers.
+            std::vector<int> want;
+            std::vector<int> next_use(n, 1 << 30);
+            for (size_t k = 0; k < porder.size(); ++k) {
+                int i = porder[k];
+                if (dn[i]) continue;
+                const G &x = d.g[i];
+                if (!x.nd) continue;
+                if (next_use[x.q0] == (1 << 30)) next_use[x.q0] = int(k);
+                if (pd[i] == 0 && sl.where[x.q0] >= R &&
+                    std::find(want.begin(), want.end(), x.q0) == want.end())
+                    want.push_back(x.q0);
+            }
+            if (want.empty()) break;  // should not happen: some gate is ready
+            // fill the remaining register capacity with the next-needed thread qubits
+            std::vector<int> cand;
+            for (int q = 0; q < n; ++q)
+                if (sl.where[q] >= R && next_use[q] < (1 << 30) &&
+                    std::find(want.begin(), want.end(), q) == want.end())
+                    cand.push_back(q);
+            std::sort(cand.begin(), cand.end(),
+                      [&](int a, int b) { return next_use[a] < next_use[b]; });
+            // victims: register slots ordered by furthest next use
+            std::vector<int> regs(R);
+            std::iota(regs.begin(), regs.end(), 0);
+            std::sort(regs.begin(), regs.end(), [&](int a, int b) {
+                return next_use[sl.occ[a]] > next_use[sl.occ[b]];
+            });
+            int perm[kMaxSlots];
+            for (int s = 0; s < L; ++s) perm[s] = s;
+            int k = 0;
+            std::vector<int> incoming = want;
+            for (int q : cand) incoming.push_back(q);
+            for (int q : incoming) {
+                if (k >= R) break;
+                int vs = regs[k];
+                // only evict a register qubit that is needed later than q
+                if (k >= int(want.size()) && next_use[sl.occ[vs]] <= next_use[q]) break;
+                int ts = sl.where[q];
+                perm[vs] = ts;
+                perm[ts] = vs;
+                ++k;
+            }
+            pb.xchg(perm, L);
+            int occ_old[kMaxSlots];
+            std::copy(sl.occ, sl.occ + L, occ_old);
+            for (int s = 0; s < L; ++s) sl.set(s, occ_old[perm[s]]);
+        }
+        // --- restore the coalesced layout of qubits 0..cl-1 for the store ---
+        {
+            bool ok = sl.occ[0] == 0;
+            for (int u = 0; u < cl - 1; ++u) ok = ok && sl.occ[R + u] == u + 1;
+            if (!ok) {
+                int target[kMaxSlots];   // new slot -> qubit
+                for (int s = 0; s < L; ++s) target[s] = -1;
+                target[0] = 0;
+                for (int u = 0; u < cl - 1; ++u) target[R + u] = u + 1;
+                std::vector<int> others;
+                for (int s = 0; s < L; ++s)
+                    if (sl.occ[s] >= cl) others.push_back(sl.occ[s]);
+                // keep others in place where possible
+                std::vector<char> used(L, 0);
+                for (int s = 0; s < L; ++s)
+                    if (target[s] >= 0) used[s] = 1;
+                std::vector<int> homeless;
+                for (int q : others) {
+                    int s = sl.where[q];
+                    if (!used[s]) { target[s] = q; used[s] = 1; }
+                    else homeless.push_back(q);
+                }
+                size_t h = 0;
+                for (int s = 0; s < L; ++s)
+                    if (!used[s]) { target[s] = homeless[h++]; used[s] = 1; }
+                int perm[kMaxSlots];
+                for (int s = 0; s < L; ++s) perm[s] = sl.where[target[s]];
+                pb.xchg(perm, L);
+                int occ_old[kMaxSlots];
+                std::copy(sl.occ, sl.occ + L, occ_old);
+                for (int s = 0; s < L; ++s) sl.set(s, occ_old[perm[s]]);
+            }
+        }
+        for (int s = 0; s < L; ++s) P.st_phys[s] = uint8_t(sl.occ[s]);
+        if (sched.empty())
+            return fail(QSV_EINTERNAL, "planner made no progress");
+        // commit the scheduled gates
+        for (int i : sched) {
+            done[i] = 1;
+            ++n_done;
+            for (int s : d.succ[i]) --pend[s];
+        }
+        total_phase = (total_phase + phase) & 7;
+        // Intermediate passes apply the exact power of two of the removed
+        // 2^{-m/2}; an odd half power is carried to the call's last pass, which
+        // also applies the accumulated phase, so at most one inexact factor
+        // is rounded per call.
+        carry_half += m_nd;
+        double mag;
+        if (n_done == NG) {
+            mag = std::pow(2.0, -0.5 * carry_half);
+            carry_half = 0;
+        } else {
+            mag = std::ldexp(1.0, -(carry_half / 2));
+            carry_half &= 1;
+        }
+        double sr = mag, si = 0.0;
+        if (n_done == NG) {
+            double ang = M_PI / 4.0 * total_phase;
+            sr = mag * std::cos(ang);
+            si = mag * std::sin(ang);
+            if (total_phase % 2 == 0) {  // exact multiples of i
+                const double re[4] = {1, 0, -1, 0}, im[4] = {0, 1, 0, -1};
+                sr = mag * re[total_phase / 2];
+                si = mag * im[total_phase / 2];
+            }
+        }
+        P.scale_re = float(sr);
+        P.scale_im = float(si);
+        if (!(sr == 1.0 && si == 0.0)) pb.op(make_op(OP_SCALE));
+        if (pb.ops.size() > size_t(kMaxOps))
+            return fail(QSV_EINTERNAL, "planner: program too long");
+        std::copy(pb.ops.begin(), pb.ops.end(), P.ops);
+        P.n_ops = int(pb.ops.size());
+        for (int i : sched) pass.gates.push_back(idx[i]);
+        out.passes.push_back(std::move(pass));
+    }
+    return QSV_OK;
+}
+
+}  // namespace qsv

@@ -1,0 +1,107 @@
+// Internal declarations of the qsv library (host side).
+#pragma once
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/qsv.h"
+
+namespace qsv {
+
+constexpr int kMaxQubits = 34;   // 2^34 complex64 = 128 GiB per state
+constexpr int kMaxSlots = 16;    // register + thread slots of one tile
+constexpr int kMaxOps = 192;     // op words per pass program (kernel argument)
+
+// Opcodes of a pass program.  Each op is one 64-bit word; XCHG is followed by
+// one extra word holding the slot permutation.
+enum Opcode : uint32_t {
+    OP_END = 0,
+    OP_H = 1,      // a = register slot: (x, y) -> (x + y, x - y)
+    OP_SX = 2,     // (x, y) -> (x - i y, y - i x)
+    OP_SY = 3,     // (x, y) -> (x - y, x + y)
+    OP_SXDG = 4,   // (x, y) -> (x + i y, y + i x)
+    OP_SYDG = 5,   // (x, y) -> (x + y, y - x)
+    OP_PHASE = 8,  // a = locator, b = k: multiply amplitudes with bit = 1 by w^k, w = e^{i pi/4}
+    OP_CZ = 9,     // a, b = locators: negate amplitudes with both bits = 1
+    OP_PROJ = 10,  // a = locator, b = value l, c = 1 -> l is branch bit b: zero amplitudes with bit != l
+    OP_ZB = 11,    // a = locator, b = branch bit j: negate amplitudes with bit = 1 if branch bit j is 1
+    OP_XCHG = 12,  // next word: new slot s takes the data of old slot perm[s] (4 bits each)
+    OP_SCALE = 13, // multiply every amplitude by the pass scale
+};
+
+// Locator byte: < 0x80 -> slot index (register slots 0..R-1, thread slots
+// R..R+T-1); 0x80 | p -> non-resident physical index bit p.
+constexpr uint8_t kLocGlobal = 0x80;
+
+inline uint64_t make_op(uint32_t code, uint32_t a = 0, uint32_t b = 0, uint32_t c = 0) {
+    return uint64_t(code) | (uint64_t(a & 0xff) << 8) | (uint64_t(b & 0xff) << 16) |
+           (uint64_t(c & 0xff) << 24);
+}
+
+// Kernel argument block of one fused pass.  Plain old data, copied by value
+// into the kernel argument segment at launch.
+struct PassProg {
+    uint64_t ops[kMaxOps];
+    uint8_t ld_phys[kMaxSlots];   // physical bit of each slot when loading
+    uint8_t st_phys[kMaxSlots];   // physical bit of each slot when storing
+    uint8_t glob_bits[48];        // non-resident physical bits, tile index bit i -> glob_bits[i]
+    float scale_re, scale_im;
+    int32_t n_ops;
+    int32_t n_glob;
+};
+
+struct Pass {
+    PassProg prog;
+    std::vector<int> gates;       // circuit gate indices, in program order
+    uint64_t resident_logical;    // logical qubits resident in this pass
+};
+
+struct PlanKey {
+    int lb, le, R, T, c;
+    bool operator<(const PlanKey &o) const {
+        return std::tie(lb, le, R, T, c) < std::tie(o.lb, o.le, o.R, o.T, o.c);
+    }
+};
+
+struct Plan {
+    int n = 0, R = 0, T = 0, c = 0;
+    std::vector<Pass> passes;
+    std::vector<int> gate_range;  // indices of the gates in the layer range
+};
+
+}  // namespace qsv
+
+struct qsv_circuit {
+    int n = 0;
+    int depth = 0;
+    std::vector<qsv_gate> gates;
+    std::mutex mu;
+    std::map<qsv::PlanKey, std::shared_ptr<qsv::Plan>> plans;
+};
+
+namespace qsv {
+
+// error reporting (capi.cpp)
+qsv_status fail(qsv_status s, const std::string &msg);
+
+// circuit.cpp
+bool gate_is_diagonal(uint8_t kind);
+bool gate_is_single(uint8_t kind);
+qsv_status generate_lattice_circuit(int rows, int cols, const uint8_t *present, int depth,
+                                    uint64_t seed, qsv_circuit *out);
+
+// planner.cpp
+struct TileShape { int R, T, c; };
+qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Plan &out);
+TileShape default_shape(int n);
+void gates_in_range(const qsv_circuit &c, int lb, int le, std::vector<int> &idx);
+
+// emulate.cpp
+void emulate_pass(const PassProg &p, int n, int R, int T, uint64_t branch, float *amps);
+
+}  // namespace qsv

@@ -1,0 +1,247 @@
+"""Thin ctypes binding of libqsv.so (argument marshalling only).
+
+Every function mirrors the C entry point of the same name in include/qsv.h.
+Device buffers may be given as torch tensors (their data_ptr() is used) or as
+integer device addresses; `stream` defaults to torch's current stream.  The
+library must be built (paper_1804_04797_amd/build.py); importing this module
+without it raises, so no code path silently runs without the HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqsv.so")
+
+GATE_DTYPE = np.dtype([("kind", "u1"), ("q0", "u1"), ("q1", "u1"), ("arg", "u1"),
+                       ("layer", "<u2"), ("reserved", "<u2")])
+KIND = {"H": 0, "T": 1, "SX": 2, "SY": 3, "CZ": 4, "P0": 5, "P1": 6, "Z": 7, "TDG": 8,
+        "SXDG": 9, "SYDG": 10, "PB": 11, "ZB": 12}
+KIND_NAME = {v: k for k, v in KIND.items()}
+INIT_ZERO, INIT_PLUS, INIT_BASIS = 0, 1, 2
+STATUS = {0: "QSV_OK", 1: "QSV_EINVAL", 2: "QSV_ERANGE", 3: "QSV_ENOMEM", 4: "QSV_EHIP",
+          5: "QSV_EUNSUPPORTED", 6: "QSV_EINTERNAL"}
+
+EXPORTS = ["circuit_create", "circuit_destroy", "circuit_info", "circuit_gates",
+           "circuit_split", "sv_init", "sv_apply_fused", "sv_apply_plain", "sv_amplitudes",
+           "sv_norm_fp64", "sv_branch_combine", "sv_batch_create", "sv_batch_run",
+           "sv_batch_destroy", "sv_plan_info", "sv_debug_emulate", "qsv_last_error",
+           "qsv_version"]
+
+
+class QsvError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class FuseOpts(ctypes.Structure):
+    _fields_ = [("reg_qubits", ctypes.c_int), ("thread_qubits", ctypes.c_int),
+                ("low_qubits", ctypes.c_int), ("plain", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1804_04797_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, u64, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_int
+    st = ctypes.c_int
+    P = ctypes.POINTER
+    sig = {
+        "circuit_create": (st, [i32, i32, vp, i32, u64, vp, sz, P(vp)]),
+        "circuit_destroy": (None, [vp]),
+        "circuit_info": (st, [vp, P(i32), P(i32), P(sz)]),
+        "circuit_gates": (st, [vp, vp, sz, P(sz)]),
+        "circuit_split": (st, [vp, u64, P(vp), P(vp), P(i32), vp, vp, sz, P(sz)]),
+        "sv_init": (st, [vp, i32, i32, u64, vp]),
+        "sv_apply_fused": (st, [vp, vp, u64, i32, i32, vp, vp]),
+        "sv_apply_plain": (st, [vp, vp, u64, i32, i32, vp]),
+        "sv_amplitudes": (st, [vp, i32, vp, sz, vp, i32, vp]),
+        "sv_norm_fp64": (st, [vp, i32, vp, vp]),
+        "sv_branch_combine": (st, [vp, vp, sz, sz, vp, vp, vp]),
+        "sv_batch_create": (st, [vp, vp, sz, vp, P(vp)]),
+        "sv_batch_run": (st, [vp, vp, i32, vp, sz, vp, vp]),
+        "sv_batch_destroy": (None, [vp]),
+        "sv_plan_info": (st, [vp, i32, i32, vp, P(i32), vp, vp, sz, vp, sz]),
+        "sv_debug_emulate": (st, [vp, vp, u64, i32, i32, vp]),
+        "qsv_last_error": (ctypes.c_char_p, []),
+        "qsv_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != 0:
+        raise QsvError(status, lib().qsv_last_error().decode())
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError(f"cannot take a device pointer of {type(x)}")
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream if isinstance(stream, int) else getattr(stream, "cuda_stream", stream)
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+def _opts(opts):
+    if opts is None:
+        return None
+    if isinstance(opts, FuseOpts):
+        return ctypes.byref(opts)
+    o = FuseOpts(**opts)
+    return ctypes.byref(o)
+
+
+class Circuit:
+    """Owning handle of a qsv_circuit."""
+
+    def __init__(self, handle):
+        self.handle = ctypes.c_void_p(handle)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.circuit_destroy(h)
+            self.handle = None
+
+    @property
+    def _as_parameter_(self):
+        return self.handle
+
+    def info(self):
+        return circuit_info(self)
+
+    @property
+    def n(self):
+        return circuit_info(self)[0]
+
+    def gates(self):
+        return circuit_gates(self)
+
+
+def circuit_create(rows, cols, present=None, depth=0, seed=0, gates=None) -> Circuit:
+    L = lib()
+    pres = None
+    if present is not None:
+        pres = np.ascontiguousarray(np.asarray(present, dtype=np.uint8).reshape(-1))
+    g = None
+    ng = 0
+    if gates is not None:
+        g = np.ascontiguousarray(np.asarray(gates, dtype=GATE_DTYPE))
+        ng = g.size
+    out = ctypes.c_void_p()
+    _check(L.circuit_create(rows, cols, _ptr(pres) if pres is not None else None, depth,
+                            ctypes.c_uint64(seed), _ptr(g) if g is not None else None, ng,
+                            ctypes.byref(out)))
+    return Circuit(out.value)
+
+
+def circuit_info(c):
+    n, d, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+    _check(lib().circuit_info(c, ctypes.byref(n), ctypes.byref(d), ctypes.byref(g)))
+    return n.value, d.value, g.value
+
+
+def circuit_gates(c) -> np.ndarray:
+    _, _, ng = circuit_info(c)
+    out = np.zeros(ng, GATE_DTYPE)
+    k = ctypes.c_size_t()
+    _check(lib().circuit_gates(c, _ptr(out), ng, ctypes.byref(k)))
+    return out[: k.value]
+
+
+def circuit_split(c, side_a_mask: int):
+    ha, hb = ctypes.c_void_p(), ctypes.c_void_p()
+    ceff = ctypes.c_int()
+    nf = ctypes.c_size_t()
+    cap = 4096
+    fa = np.zeros(cap, np.int32)
+    fb = np.zeros(cap, np.int32)
+    _check(lib().circuit_split(c, ctypes.c_uint64(side_a_mask), ctypes.byref(ha),
+                               ctypes.byref(hb), ctypes.byref(ceff), _ptr(fa), _ptr(fb), cap,
+                               ctypes.byref(nf)))
+    k = min(nf.value, cap)
+    return Circuit(ha.value), Circuit(hb.value), ceff.value, list(zip(fa[:k].tolist(),
+                                                                        fb[:k].tolist()))
+
+
+def sv_init(amps, n_qubits, kind=INIT_ZERO, basis=0, stream=None):
+    _check(lib().sv_init(_ptr(amps), n_qubits, kind, ctypes.c_uint64(basis), _stream(stream)))
+
+
+def sv_apply_fused(amps, c, branch=0, layer_begin=0, layer_end=-1, opts=None, stream=None):
+    _check(lib().sv_apply_fused(_ptr(amps), c, ctypes.c_uint64(branch), layer_begin, layer_end,
+                                _opts(opts), _stream(stream)))
+
+
+def sv_apply_plain(amps, c, branch=0, layer_begin=0, layer_end=-1, stream=None):
+    _check(lib().sv_apply_plain(_ptr(amps), c, ctypes.c_uint64(branch), layer_begin, layer_end,
+                                _stream(stream)))
+
+
+def sv_amplitudes(amps, n_qubits, bitstrings, out, c128=False, stream=None):
+    m = out.numel() if hasattr(out, "numel") else len(bitstrings)
+    _check(lib().sv_amplitudes(_ptr(amps), n_qubits, _ptr(bitstrings), m, _ptr(out),
+                               1 if c128 else 0, _stream(stream)))
+
+
+def sv_norm_fp64(amps, n_qubits, out, stream=None):
+    _check(lib().sv_norm_fp64(_ptr(amps), n_qubits, _ptr(out), _stream(stream)))
+
+
+def sv_branch_combine(a_tab, b_tab, n_branches, m, sign, out, stream=None):
+    _check(lib().sv_branch_combine(_ptr(a_tab), _ptr(b_tab), n_branches, m, _ptr(sign),
+                                   _ptr(out), _stream(stream)))
+
+
+def sv_plan_info(c, layer_begin=0, layer_end=-1, opts=None):
+    n, _, ng = circuit_info(c)
+    npass = ctypes.c_int()
+    pog = np.zeros(ng, np.int32)
+    oip = np.zeros(ng, np.int32)
+    res = np.zeros(4096, np.uint64)
+    _check(lib().sv_plan_info(c, layer_begin, layer_end, _opts(opts), ctypes.byref(npass),
+                              _ptr(pog), _ptr(oip), ng, _ptr(res), res.size))
+    return {"n_passes": npass.value, "pass_of_gate": pog, "order_in_pass": oip,
+            "resident": [int(x) for x in res[: npass.value]]}
+
+
+def sv_debug_emulate(amps_host: np.ndarray, c, branch=0, layer_begin=0, layer_end=-1,
+                     opts=None):
+    assert amps_host.dtype == np.complex64 and amps_host.flags.c_contiguous
+    _check(lib().sv_debug_emulate(_ptr(amps_host), c, ctypes.c_uint64(branch), layer_begin,
+                                  layer_end, _opts(opts)))
+
+
+def version() -> str:
+    return lib().qsv_version().decode()

@@ -1,0 +1,43 @@
+"""Write oracle amplitudes for the 30-qubit workload (calls only oracle/).
+
+Output: tests/golden/5x6-d20_amplitudes.txt, one line per sampled bitstring:
+"<bitstring> <re> <im>" with %.17g doubles, plus a header with the workload,
+the oracle norm and the oracle's own timing.  The 4096 bitstrings are the
+seeded uniform sample of paper_1804_04797_amd.workloads.bitstrings.
+Needs about 17 GiB of host memory and several minutes.
+"""
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import circuit as OC  # noqa: E402
+from oracle import sim  # noqa: E402
+from paper_1804_04797_amd import workloads  # noqa: E402
+
+
+def main(name="5x6-d20", m=4096):
+    spec = workloads.WORKLOADS[name]
+    lat = OC.Lattice(spec["rows"], spec["cols"], workloads.present_grid(spec))
+    gates = OC.random_circuit(lat, spec["depth"], spec["seed"])
+    xs = workloads.bitstrings(lat.n, m, workloads.BITSTRING_SEED_BASE + 2)
+    t0 = time.time()
+    psi = sim.simulate(gates, lat.n)
+    dt = time.time() - t0
+    nrm = sim.norm2(psi)
+    out = os.path.join(HERE, f"{name}_amplitudes.txt")
+    with open(out, "w") as f:
+        f.write(f"# workload {name}: n={lat.n} depth={spec['depth']} seed={spec['seed']:#x} "
+                f"gates={len(gates)} bitstring_seed={workloads.BITSTRING_SEED_BASE + 2:#x}\n")
+        f.write(f"# oracle complex128 norm2={nrm:.17g} time_s={dt:.1f} threads={sim.threads()}\n")
+        for x in xs.tolist():
+            a = psi[x]
+            f.write(f"{x} {a.real:.17g} {a.imag:.17g}\n")
+    print(out, dt)
+
+
+if __name__ == "__main__":
+    main()

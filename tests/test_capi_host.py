@@ -1,0 +1,250 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library must load and export every entry point of include/qsv.h; the
+C++ circuit generator and split must agree gate by gate with the oracle's
+independent generator; argument errors must return a status; the pass
+planner's grouping must respect gate semantics; and the host emulation of
+the pass programs must reproduce the oracle state.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import circuit as OC
+from oracle import sim
+from paper_1804_04797_amd import qsv, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_every_header_symbol():
+    hdr = open(os.path.join(ROOT, "include", "qsv.h")).read()
+    names = set(re.findall(r"^(?:qsv_status|void|const char \*)\s*\**\s*(\w+)\s*\(", hdr, re.M))
+    assert names, "no declarations parsed"
+    L = qsv.lib()
+    for nm in sorted(names):
+        assert hasattr(L, nm), nm
+    assert names == set(qsv.EXPORTS)
+
+
+def _to_oracle(gates):
+    out = []
+    for g in gates:
+        name = qsv.KIND_NAME[int(g["kind"])]
+        out.append((name, int(g["q0"]), int(g["q1"]) if name == "CZ" else -1, int(g["layer"])))
+    return out
+
+
+def _oracle_lattice(spec):
+    return OC.Lattice(spec["rows"], spec["cols"], workloads.present_grid(spec))
+
+
+@pytest.mark.parametrize("name", list(workloads.WORKLOADS))
+def test_generator_matches_oracle(name):
+    spec = workloads.WORKLOADS[name]
+    c = qsv.circuit_create(spec["rows"], spec["cols"], workloads.present_mask(spec),
+                           spec["depth"], spec["seed"])
+    n, d, ng = c.info()
+    lat = _oracle_lattice(spec)
+    want = OC.random_circuit(lat, spec["depth"], spec["seed"])
+    assert n == lat.n == spec["n"] and d == spec["depth"] and ng == len(want)
+    assert _to_oracle(c.gates()) == want
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed", [(4, 7, 50, 1), (3, 3, 40, 9), (1, 6, 12, 3),
+                                                  (7, 7, 40, 3), (2, 2, 9, 0)])
+def test_generator_matches_oracle_more(rows, cols, depth, seed):
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    want = OC.random_circuit(OC.Lattice(rows, cols), depth, seed)
+    assert _to_oracle(c.gates()) == want
+
+
+def test_generator_uneven_lattices():
+    for n, d, s in workloads.uneven_batch(24):
+        rows, cols, pres = workloads.lattice_for_qubits(n)
+        c = qsv.circuit_create(rows, cols, pres, d, s)
+        lat = OC.Lattice.for_qubits(n)
+        assert _to_oracle(c.gates()) == OC.random_circuit(lat, d, s)
+
+
+def test_explicit_gate_list_roundtrip():
+    g = np.zeros(3, qsv.GATE_DTYPE)
+    g[0] = (qsv.KIND["H"], 0, 0, 0, 0, 0)
+    g[1] = (qsv.KIND["CZ"], 0, 1, 0, 1, 0)
+    g[2] = (qsv.KIND["T"], 1, 0, 0, 2, 0)
+    c = qsv.circuit_create(1, 2, None, gates=g)
+    assert c.info() == (2, 2, 3)
+    assert np.array_equal(c.gates(), g)
+
+
+def test_error_statuses():
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.circuit_create(0, 5, None, 3, 1)
+    assert e.value.status == 1
+    g = np.zeros(1, qsv.GATE_DTYPE)
+    g[0] = (qsv.KIND["H"], 9, 0, 0, 0, 0)
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.circuit_create(2, 2, None, gates=g)
+    assert e.value.status == 2
+    g[0] = (99, 0, 0, 0, 0, 0)
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.circuit_create(2, 2, None, gates=g)
+    assert e.value.status == 1
+    c = qsv.circuit_create(2, 3, None, 4, 1)
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.circuit_split(c, 0)
+    assert e.value.status == 1
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.circuit_split(c, 1 << 40)
+    assert e.value.status == 2
+    # state pointer checks happen before any device call
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.sv_apply_fused(0, c)
+    assert e.value.status == 1
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.sv_init(8, 5, 0)          # misaligned pointer
+    assert e.value.status == 1
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.sv_init(256, 40, 0)       # n too large
+    assert e.value.status == 2
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.sv_apply_fused(256, c, opts={"reg_qubits": 7, "thread_qubits": 8,
+                                         "low_qubits": 0, "plain": 0})
+    assert e.value.status == 5
+
+
+@pytest.mark.parametrize("after_col", [1, 2])
+def test_split_matches_oracle(after_col):
+    rows, cols, depth, seed = 3, 4, 12, 21
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    mask = workloads.column_cut_mask(rows, cols, after_col)
+    ha, hb, ceff, folded = qsv.circuit_split(c, mask)
+    side_a = [q for q in range(rows * cols) if (mask >> q) & 1]
+    info = sim.split_circuit(OC.random_circuit(OC.Lattice(rows, cols), depth, seed),
+                             rows * cols, side_a)
+    assert ceff == len(info["cuts"])
+    assert folded == [(a, b) for a, b, _ in info["folded"]]
+    # PB/ZB with branch bit j must equal the oracle's P_l / Z^l for every l
+    ga, gb = ha.gates(), hb.gates()
+    for br in range(min(1 << ceff, 64)):
+        l = tuple((br >> j) & 1 for j in range(ceff))
+        oa, ob = info["half"](l)
+        mine_a, mine_b = [], []
+        for g in ga:
+            k = qsv.KIND_NAME[int(g["kind"])]
+            if k == "PB":
+                k = "P1" if l[int(g["arg"])] else "P0"
+            mine_a.append((k, int(g["q0"]), int(g["q1"]) if k == "CZ" else -1, int(g["layer"])))
+        for g in gb:
+            k = qsv.KIND_NAME[int(g["kind"])]
+            if k == "ZB":
+                if not l[int(g["arg"])]:
+                    continue
+                k = "Z"
+            mine_b.append((k, int(g["q0"]), int(g["q1"]) if k == "CZ" else -1, int(g["layer"])))
+        assert mine_a == oa and mine_b == ob
+
+
+def _random_explicit(n, count, seed, kinds=("H", "T", "SX", "SY", "CZ", "TDG", "SXDG", "SYDG",
+                                            "Z", "P0", "P1")):
+    rng = np.random.default_rng(seed)
+    g = np.zeros(count, qsv.GATE_DTYPE)
+    for i in range(count):
+        k = kinds[rng.integers(len(kinds))]
+        q0 = int(rng.integers(n))
+        q1 = q0
+        while k == "CZ" and q1 == q0:
+            q1 = int(rng.integers(n))
+        g[i] = (qsv.KIND[k], q0, q1 if k == "CZ" else 0, 0, i // 4, 0)
+    return g
+
+
+SHAPES = [None, dict(reg_qubits=3, thread_qubits=4, low_qubits=3, plain=0),
+          dict(reg_qubits=4, thread_qubits=6, low_qubits=5, plain=0),
+          dict(reg_qubits=2, thread_qubits=3, low_qubits=2, plain=0)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_plan_respects_dependencies(shape):
+    spec = workloads.WORKLOADS["4x5-d10"]
+    c = qsv.circuit_create(spec["rows"], spec["cols"], None, 24, 77)
+    info = qsv.sv_plan_info(c, opts=shape)
+    gates = _to_oracle(c.gates())
+    pog, oip = info["pass_of_gate"], info["order_in_pass"]
+    assert (pog >= 0).all()
+    # every non-diagonal gate runs in a pass where its qubit is resident
+    for i, g in enumerate(gates):
+        if g[0] not in OC.DIAGONAL:
+            assert (info["resident"][pog[i]] >> g[1]) & 1
+    # executing in (pass, position) order gives the in-order state
+    order = sorted(range(len(gates)), key=lambda i: (pog[i], oip[i]))
+    re = sim.simulate([gates[i] for i in order], 20)
+    ref = sim.simulate(gates, 20)
+    assert np.max(np.abs(re - ref)) < 1e-12
+    assert 1 <= info["n_passes"] <= 25
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_emulated_plan_matches_oracle(shape):
+    spec = workloads.WORKLOADS["4x5-d10"]
+    c = qsv.circuit_create(spec["rows"], spec["cols"], None, spec["depth"], spec["seed"])
+    psi = np.zeros(1 << 20, np.complex64)
+    psi[0] = 1
+    qsv.sv_debug_emulate(psi, c, opts=shape)
+    ref = sim.simulate(_to_oracle(c.gates()), 20)
+    assert np.max(np.abs(psi - ref)) < 1e-6
+    p64 = psi.astype(np.complex128)
+    fid = abs(np.vdot(ref, p64)) ** 2 / (np.vdot(p64, p64).real * np.vdot(ref, ref).real)
+    assert 1 - fid < 1e-9
+    assert abs(np.vdot(p64, p64).real - 1) < 1e-5
+
+
+def test_emulated_explicit_gates_all_kinds():
+    n = 12
+    g = _random_explicit(n, 300, 5)
+    c = qsv.circuit_create(3, 4, None, gates=g)
+    for shape in SHAPES:
+        psi = np.zeros(1 << n, np.complex64)
+        psi[0] = 1
+        qsv.sv_debug_emulate(psi, c, opts=shape)
+        ref = sim.simulate(_to_oracle(c.gates()), n)
+        assert np.max(np.abs(psi - ref)) < 1e-5
+
+
+def test_emulated_layer_ranges_compose():
+    spec = workloads.WORKLOADS["4x5-d10"]
+    c = qsv.circuit_create(spec["rows"], spec["cols"], None, 16, 3)
+    psi = np.zeros(1 << 20, np.complex64)
+    psi[0] = 1
+    for lb, le in ((0, 3), (3, 4), (4, 11), (11, -1)):
+        qsv.sv_debug_emulate(psi, c, layer_begin=lb, layer_end=le)
+    ref = sim.simulate(_to_oracle(c.gates()), 20)
+    assert np.max(np.abs(psi - ref)) < 1e-6
+
+
+def test_emulated_split_branches():
+    rows, cols, depth, seed = 3, 4, 10, 4
+    n = rows * cols
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    mask = workloads.column_cut_mask(rows, cols, 1)
+    ha, hb, ceff, folded = qsv.circuit_split(c, mask)
+    na, nb = ha.n, hb.n
+    qa = [q for q in range(n) if (mask >> q) & 1]
+    qb = [q for q in range(n) if not (mask >> q) & 1]
+    opts = dict(reg_qubits=2, thread_qubits=3, low_qubits=2, plain=0)
+    total = np.zeros(1 << n, np.complex128)
+    xs = np.arange(1 << n)
+    xa = np.array([sim.sub_index(int(x), qa) for x in xs])
+    xb = np.array([sim.sub_index(int(x), qb) for x in xs])
+    for br in range(1 << ceff):
+        A = np.zeros(1 << na, np.complex64); A[0] = 1
+        B = np.zeros(1 << nb, np.complex64); B[0] = 1
+        qsv.sv_debug_emulate(A, ha, branch=br, opts=opts)
+        qsv.sv_debug_emulate(B, hb, branch=br, opts=opts)
+        total += A[xa].astype(np.complex128) * B[xb]
+    sign = np.array([sim.fold_sign(int(x), [(a, b, 0) for a, b in folded]) for x in xs])
+    total *= sign
+    ref = sim.simulate(OC.random_circuit(OC.Lattice(rows, cols), depth, seed), n)
+    assert np.max(np.abs(total - ref)) < 1e-5

@@ -1,0 +1,372 @@
+"""GPU parity tests: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances: complex64 state with FP32 arithmetic against the complex128
+oracle -> max |delta amp| <= 1e-5 (absolute), plus the size-independent
+scaled error eps_s = max|delta| * 2^{n/2} <= 1e-4 and 1 - F <= 1e-9 where the
+full state is available; FP64 paths (norm, branch combine) on identical
+complex64 inputs -> 1e-12.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import circuit as OC  # noqa: E402
+from oracle import sim  # noqa: E402
+from paper_1804_04797_amd import qsv, workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEV = "cuda:0"
+TOL = 1e-5
+TOL_SCALED = 1e-4
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _oracle_gates(c):
+    out = []
+    for g in c.gates():
+        name = qsv.KIND_NAME[int(g["kind"])]
+        out.append((name, int(g["q0"]), int(g["q1"]) if name == "CZ" else -1, int(g["layer"])))
+    return out
+
+
+def _state(n, kind=qsv.INIT_ZERO, basis=0):
+    a = torch.empty(1 << n, dtype=torch.complex64, device=DEV)
+    qsv.sv_init(a, n, kind, basis)
+    return a
+
+
+def _check_full(psi_dev, ref, n):
+    got = psi_dev.cpu().numpy().astype(np.complex128)
+    d = np.max(np.abs(got - ref))
+    fid = abs(np.vdot(ref, got)) ** 2 / (np.vdot(got, got).real * np.vdot(ref, ref).real)
+    assert d <= TOL, d
+    assert d * 2 ** (n / 2) <= TOL_SCALED, d * 2 ** (n / 2)
+    assert 1 - fid <= 1e-9, 1 - fid
+    return d
+
+
+def _lattice_circuit(name):
+    spec = workloads.WORKLOADS[name]
+    c = qsv.circuit_create(spec["rows"], spec["cols"], workloads.present_mask(spec),
+                           spec["depth"], spec["seed"])
+    lat = OC.Lattice(spec["rows"], spec["cols"], workloads.present_grid(spec))
+    return spec, c, lat
+
+
+def test_library_reports_gfx950():
+    _gpu()
+    assert "gfx950" in qsv.version()
+    assert "gfx950" in torch.cuda.get_device_properties(0).gcnArchName
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 10, 21])
+def test_init_kinds(n):
+    _gpu()
+    a = _state(n, qsv.INIT_ZERO)
+    want = np.zeros(1 << n, np.complex64)
+    want[0] = 1
+    assert np.array_equal(a.cpu().numpy(), want)
+    qsv.sv_init(a, n, qsv.INIT_PLUS)
+    assert np.allclose(a.cpu().numpy(), 2.0 ** (-n / 2), rtol=0, atol=1e-7 * 2.0 ** (-n / 2))
+    b = (1 << n) - 1
+    qsv.sv_init(a, n, qsv.INIT_BASIS, b)
+    want[:] = 0
+    want[b] = 1
+    assert np.array_equal(a.cpu().numpy(), want)
+
+
+def test_plain_path_4x5():
+    _gpu()
+    spec, c, lat = _lattice_circuit("4x5-d10")
+    a = _state(lat.n)
+    qsv.sv_apply_plain(a, c)
+    _check_full(a, sim.simulate(_oracle_gates(c), lat.n), lat.n)
+
+
+SHAPES = [None, (5, 8, 5), (5, 7, 5), (4, 7, 5), (4, 6, 5), (3, 6, 4), (3, 4, 3), (2, 3, 2),
+          (4, 8, 6), (6, 8, 5), (5, 9, 7), (4, 9, 5), (6, 7, 3)]
+
+
+def _opts(shape):
+    if shape is None:
+        return None
+    return dict(reg_qubits=shape[0], thread_qubits=shape[1], low_qubits=shape[2], plain=0)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fused_4x5_all_shapes(shape):
+    _gpu()
+    spec, c, lat = _lattice_circuit("4x5-d10")
+    ref = sim.simulate(_oracle_gates(c), lat.n)
+    a = _state(lat.n)
+    qsv.sv_apply_fused(a, c, opts=_opts(shape))
+    _check_full(a, ref, lat.n)
+
+
+def test_fused_init_plus_skips_layer0():
+    _gpu()
+    spec, c, lat = _lattice_circuit("4x5-d10")
+    ref = sim.simulate(_oracle_gates(c), lat.n)
+    a = _state(lat.n, qsv.INIT_PLUS)
+    qsv.sv_apply_fused(a, c, layer_begin=1)
+    _check_full(a, ref, lat.n)
+
+
+def test_fused_explicit_gates_all_kinds():
+    _gpu()
+    n = 16
+    rng = np.random.default_rng(8)
+    kinds = ["H", "T", "SX", "SY", "CZ", "TDG", "SXDG", "SYDG", "Z", "P0", "P1"]
+    g = np.zeros(400, qsv.GATE_DTYPE)
+    for i in range(g.size):
+        k = kinds[rng.integers(len(kinds))] if i >= n else "H"
+        q0 = int(rng.integers(n)) if i >= n else i
+        q1 = q0
+        while k == "CZ" and q1 == q0:
+            q1 = int(rng.integers(n))
+        g[i] = (qsv.KIND[k], q0, q1 if k == "CZ" else 0, 0, i // 8, 0)
+    c = qsv.circuit_create(4, 4, None, gates=g)
+    ref = sim.simulate(_oracle_gates(c), n)
+    for shape in (None, (3, 6, 4), (5, 9, 7), (6, 8, 5)):
+        a = _state(n)
+        qsv.sv_apply_fused(a, c, opts=_opts(shape))
+        got = a.cpu().numpy()
+        assert np.max(np.abs(got - ref)) <= TOL
+    a = _state(n)
+    qsv.sv_apply_plain(a, c)
+    assert np.max(np.abs(a.cpu().numpy() - ref)) <= TOL
+
+
+def test_layer_ranges_compose_and_empty_range():
+    _gpu()
+    spec, c, lat = _lattice_circuit("4x5-d10")
+    ref = sim.simulate(_oracle_gates(c), lat.n)
+    a = _state(lat.n)
+    for lb, le in ((0, 2), (2, 2), (2, 5), (5, 6), (6, -1)):
+        qsv.sv_apply_fused(a, c, layer_begin=lb, layer_end=le)
+    _check_full(a, ref, lat.n)
+
+
+def test_tiny_states_use_plain_kernels():
+    _gpu()
+    for rows, cols in ((1, 2), (2, 2), (1, 4)):
+        c = qsv.circuit_create(rows, cols, None, 12, 5)
+        n = rows * cols
+        a = _state(n)
+        qsv.sv_apply_fused(a, c)
+        assert np.max(np.abs(a.cpu().numpy() - sim.simulate(_oracle_gates(c), n))) <= TOL
+
+
+def _golden(name):
+    path = os.path.join(HERE, "golden", f"{name}_amplitudes.txt")
+    xs, amps = [], []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#"):
+                continue
+            x, re, im = line.split()
+            xs.append(int(x))
+            amps.append(complex(float(re), float(im)))
+    return np.array(xs, np.uint64), np.array(amps)
+
+
+def test_5x6_d20_full_size_sampled():
+    """30 qubits (8 GiB state) in the benchmark's launch shape, 4096 sampled
+    amplitudes against oracle values stored by tests/golden/make_golden.py."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("5x6-d20")
+    xs, ref = _golden("5x6-d20")
+    assert np.array_equal(xs, workloads.bitstrings(30, 4096, workloads.BITSTRING_SEED_BASE + 2))
+    a = _state(30, qsv.INIT_PLUS)
+    qsv.sv_apply_fused(a, c, layer_begin=1)
+    bits = torch.from_numpy(xs.view(np.int64)).to(DEV)
+    out = torch.empty(xs.size, dtype=torch.complex128, device=DEV)
+    qsv.sv_amplitudes(a, 30, bits, out, c128=True)
+    got = out.cpu().numpy()
+    d = np.max(np.abs(got - ref))
+    assert d <= TOL and d * 2 ** 15 <= TOL_SCALED, d
+    nrm = torch.zeros(1, dtype=torch.float64, device=DEV)
+    qsv.sv_norm_fp64(a, 30, nrm)
+    assert abs(nrm.item() - 1) < 1e-4
+    # the plain comparator gives the same amplitudes
+    qsv.sv_init(a, 30, qsv.INIT_PLUS)
+    qsv.sv_apply_plain(a, c, layer_begin=1)
+    qsv.sv_amplitudes(a, 30, bits, out, c128=True)
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= TOL
+
+
+def _diag_only(gates):
+    n = max(g[1] for g in gates) + 1
+    return [g for g in gates if g[0] in ("H", "T", "CZ") and (g[0] != "H" or g[3] == 0)], n
+
+
+def _closed_form_graph(gates, n, xs):
+    # alpha_x = 2^{-n/2} w^{#T(x)} (-1)^{#CZ(x)} after H on all + diagonal gates
+    k = np.zeros(xs.size, np.int64)
+    s = np.zeros(xs.size, np.int64)
+    x = xs.astype(np.uint64)
+    for name, a, b, _ in gates:
+        bit = ((x >> np.uint64(a)) & np.uint64(1)).astype(np.int64)
+        if name == "T":
+            k += bit
+        elif name == "CZ":
+            s += bit & ((x >> np.uint64(b)) & np.uint64(1)).astype(np.int64)
+    return 2.0 ** (-n / 2) * np.exp(1j * np.pi / 4 * k) * (-1.0) ** s
+
+
+@pytest.mark.parametrize("name", ["5x6-d20", "6x6m2-d30"])
+def test_closed_form_full_size(name):
+    """H layer + every CZ and T of the workload circuit, at its real size
+    (n = 30 and n = 34: 128 GiB): amplitudes have the closed form
+    2^{-n/2} w^{#T(x)} (-1)^{#CZ(x)}, checked on 4096 sampled bitstrings."""
+    _gpu()
+    spec, c, lat = _lattice_circuit(name)
+    gates = _oracle_gates(c)
+    keep = [g for g in gates if g[0] in ("CZ", "T") or g[3] == 0]
+    arr = np.zeros(len(keep), qsv.GATE_DTYPE)
+    for i, (nm, a, b, layer) in enumerate(keep):
+        arr[i] = (qsv.KIND[nm], a, b if b >= 0 else 0, 0, layer, 0)
+    n = lat.n
+    cd = qsv.circuit_create(spec["rows"], spec["cols"], workloads.present_mask(spec), gates=arr)
+    xs = workloads.bitstrings(n, 4096, 77)
+    a = _state(n)
+    qsv.sv_apply_fused(a, cd)
+    bits = torch.from_numpy(xs.view(np.int64)).to(DEV)
+    out = torch.empty(xs.size, dtype=torch.complex128, device=DEV)
+    qsv.sv_amplitudes(a, n, bits, out, c128=True)
+    want = _closed_form_graph(keep, n, xs)
+    d = np.max(np.abs(out.cpu().numpy() - want))
+    assert d * 2 ** (n / 2) <= TOL_SCALED, d
+    del a
+    torch.cuda.empty_cache()
+
+
+def test_product_state_full_size_n34():
+    """Only the single-qubit gates of the 34-qubit circuit: a product state,
+    alpha_x = prod_q v_q[x_q], checked on sampled bitstrings."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("6x6m2-d30")
+    gates = [g for g in _oracle_gates(c) if g[0] != "CZ"]
+    n = lat.n
+    arr = np.zeros(len(gates), qsv.GATE_DTYPE)
+    for i, (nm, a, b, layer) in enumerate(gates):
+        arr[i] = (qsv.KIND[nm], a, 0, 0, layer, 0)
+    cd = qsv.circuit_create(spec["rows"], spec["cols"], workloads.present_mask(spec), gates=arr)
+    vs = [np.array([1, 0], np.complex128) for _ in range(n)]
+    for nm, q, _, _ in gates:
+        vs[q] = np.array(OC.gate_matrix(nm)) @ vs[q]
+    xs = workloads.bitstrings(n, 4096, 78)
+    want = np.ones(xs.size, np.complex128)
+    for q in range(n):
+        want *= vs[q][((xs >> np.uint64(q)) & np.uint64(1)).astype(np.int64)]
+    a = _state(n)
+    qsv.sv_apply_fused(a, cd)
+    bits = torch.from_numpy(xs.view(np.int64)).to(DEV)
+    out = torch.empty(xs.size, dtype=torch.complex128, device=DEV)
+    qsv.sv_amplitudes(a, n, bits, out, c128=True)
+    d = np.max(np.abs(out.cpu().numpy() - want))
+    assert d * 2 ** (n / 2) <= TOL_SCALED, d
+    del a
+    torch.cuda.empty_cache()
+
+
+def test_unitarity_circuit_then_adjoint():
+    _gpu()
+    rows, cols, depth = 4, 6, 24
+    c = qsv.circuit_create(rows, cols, None, depth, 99)
+    gates = _oracle_gates(c)
+    inv = OC.inverse_circuit(gates)
+    allg = gates + [(nm, a, b, depth + 1 + i // 50) for i, (nm, a, b, _) in enumerate(inv)]
+    arr = np.zeros(len(allg), qsv.GATE_DTYPE)
+    for i, (nm, a, b, layer) in enumerate(allg):
+        arr[i] = (qsv.KIND[nm], a, b if b >= 0 else 0, 0, layer, 0)
+    cu = qsv.circuit_create(rows, cols, None, gates=arr)
+    n = rows * cols
+    a = _state(n)
+    qsv.sv_apply_fused(a, cu)
+    got = a.cpu().numpy()
+    e0 = np.zeros_like(got)
+    e0[0] = 1
+    assert np.max(np.abs(got - e0)) <= 1e-5
+
+
+def test_norm_fp64_identical_inputs():
+    _gpu()
+    for n in (8, 14, 22, 26):
+        g = torch.Generator().manual_seed(n)
+        v = torch.randn(1 << n, dtype=torch.complex64, generator=g)
+        want = sim.norm2(v.numpy().astype(np.complex128))
+        out = torch.zeros(1, dtype=torch.float64, device=DEV)
+        qsv.sv_norm_fp64(v.to(DEV), n, out)
+        assert abs(out.item() - want) <= 1e-12 * want
+
+
+def test_branch_combine_identical_inputs():
+    _gpu()
+    rng = np.random.default_rng(3)
+    for nb, m in ((1, 5), (2048, 1024), (37, 130)):
+        a = (rng.standard_normal((nb, m)) + 1j * rng.standard_normal((nb, m))).astype(np.complex64)
+        b = (rng.standard_normal((nb, m)) + 1j * rng.standard_normal((nb, m))).astype(np.complex64)
+        sg = rng.choice([-1, 1], m).astype(np.int8)
+        want = sim.combine(a, b, sg)
+        out = torch.empty(m, dtype=torch.complex128, device=DEV)
+        qsv.sv_branch_combine(torch.from_numpy(a).to(DEV), torch.from_numpy(b).to(DEV), nb, m,
+                              torch.from_numpy(sg).to(DEV), out)
+        assert np.max(np.abs(out.cpu().numpy() - want)) <= 1e-12 * max(1.0, math.sqrt(nb))
+
+
+def test_gather_out_of_range_is_nan():
+    _gpu()
+    a = _state(10, qsv.INIT_PLUS)
+    xs = torch.tensor([0, 1023, 1024, 5000], dtype=torch.int64, device=DEV)
+    out = torch.empty(4, dtype=torch.complex64, device=DEV)
+    qsv.sv_amplitudes(a, 10, xs, out)
+    o = out.cpu().numpy()
+    assert np.allclose(o[:2], 2 ** -5) and np.isnan(o[2:].real).all()
+
+
+def test_split_end_to_end_gpu():
+    """Schmidt split on the GPU: every branch of both halves swept by the
+    fused kernels, FP64 combine, against the full oracle state."""
+    _gpu()
+    rows, cols, depth, seed = 4, 5, 12, 31
+    n = rows * cols
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    mask = workloads.column_cut_mask(rows, cols, 1)
+    ha, hb, ceff, folded = qsv.circuit_split(c, mask)
+    qa = [q for q in range(n) if (mask >> q) & 1]
+    qb = [q for q in range(n) if not (mask >> q) & 1]
+    xs = workloads.bitstrings(n, 512, 5)
+    xa = torch.tensor([sim.sub_index(int(x), qa) for x in xs], dtype=torch.int64, device=DEV)
+    xb = torch.tensor([sim.sub_index(int(x), qb) for x in xs], dtype=torch.int64, device=DEV)
+    nbr = 1 << ceff
+    At = torch.empty((nbr, xs.size), dtype=torch.complex64, device=DEV)
+    Bt = torch.empty((nbr, xs.size), dtype=torch.complex64, device=DEV)
+    A = torch.empty(1 << len(qa), dtype=torch.complex64, device=DEV)
+    B = torch.empty(1 << len(qb), dtype=torch.complex64, device=DEV)
+    for br in range(nbr):
+        qsv.sv_init(A, len(qa), qsv.INIT_ZERO)
+        qsv.sv_apply_fused(A, ha, branch=br)
+        qsv.sv_amplitudes(A, len(qa), xa, At[br])
+        qsv.sv_init(B, len(qb), qsv.INIT_ZERO)
+        qsv.sv_apply_fused(B, hb, branch=br)
+        qsv.sv_amplitudes(B, len(qb), xb, Bt[br])
+    sg = torch.tensor([sim.fold_sign(int(x), [(a, b, 0) for a, b in folded]) for x in xs],
+                      dtype=torch.int8, device=DEV)
+    out = torch.empty(xs.size, dtype=torch.complex128, device=DEV)
+    qsv.sv_branch_combine(At, Bt, nbr, xs.size, sg, out)
+    ref = sim.simulate(OC.random_circuit(OC.Lattice(rows, cols), depth, seed), n)[xs]
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= TOL
+    # FP64 combine parity on identical (GPU-produced) complex64 tables
+    want = sim.combine(At.cpu().numpy(), Bt.cpu().numpy(), sg.cpu().numpy())
+    assert np.max(np.abs(out.cpu().numpy() - want)) <= 1e-12
