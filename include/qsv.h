@@ -82,12 +82,17 @@ typedef struct qsv_batch qsv_batch;      /* opaque */
  *   low_qubits     minimum number of always-resident low index bits that make
  *                  each global access a contiguous run (c, 3..8)
  *   plain          1 = one kernel per gate (the unfused comparator path)
+ *   jit            1 = compile each pass program into its own straight-line
+ *                  kernel at first use (hipRTC, cached per process); -1 = always
+ *                  use the generic pass kernel; 0 = compile for states of 2^24
+ *                  amplitudes or more
  */
 typedef struct {
     int reg_qubits;
     int thread_qubits;
     int low_qubits;
     int plain;
+    int jit;
 } qsv_fuse_opts;
 
 /*
@@ -251,6 +256,15 @@ qsv_status sv_plan_info(const qsv_circuit *c, int layer_begin, int layer_end,
  */
 qsv_status sv_debug_emulate(void *amps_host, const qsv_circuit *c, uint64_t branch,
                             int layer_begin, int layer_end, const qsv_fuse_opts *opts);
+
+/*
+ * sv_debug_jit_compile - generate and compile (no load, no device needed) the
+ * straight-line kernels of the plan sv_apply_fused would use; reports the
+ * code-object size and compile time.  A code-generation check for CPU-only
+ * test runs.
+ */
+qsv_status sv_debug_jit_compile(const qsv_circuit *c, int layer_begin, int layer_end,
+                                const qsv_fuse_opts *opts, size_t *code_bytes, double *seconds);
 
 const char *qsv_last_error(void);
 /* Library version string. */

@@ -2,10 +2,12 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
 
+#include "jit.h"
 #include "kernels.h"
 #include "qsv_internal.h"
 
@@ -103,6 +105,16 @@ qsv_status get_plan(const qsv_circuit *cc, int lb, int le, TileShape sh,
     c->plans[key] = p;
     out = p;
     return QSV_OK;
+}
+
+bool use_jit(const qsv_circuit *c, const qsv_fuse_opts *opts) {
+    int j = opts ? opts->jit : 0;
+    if (j == 0) {
+        const char *env = std::getenv("QSV_JIT");
+        if (env && env[0] == '0') return false;
+        return c->n >= 24;
+    }
+    return j > 0;
 }
 
 void gate_matrix_f32(uint8_t kind, float m[8]) {
@@ -246,6 +258,13 @@ qsv_status sv_apply_fused(void *amps, const qsv_circuit *c, uint64_t branch, int
     std::shared_ptr<Plan> plan;
     if ((st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (use_jit(c, opts)) {
+        {
+            std::lock_guard<std::mutex> g(plan->jit_mu);
+            if ((st = jit_prepare(*plan)) != QSV_OK) return st;
+        }
+        return jit_launch(*plan, amps, branch, s);
+    }
     for (const Pass &p : plan->passes) {
         hipError_t e = launch_fused(static_cast<float2 *>(amps), c->n, sh.R, sh.T, p.prog, branch, s);
         if (e != hipSuccess) return hip_fail(e, "sv_apply_fused");
@@ -336,6 +355,18 @@ qsv_status sv_debug_emulate(void *amps_host, const qsv_circuit *c, uint64_t bran
     for (const Pass &p : plan->passes)
         emulate_pass(p.prog, c->n, sh.R, sh.T, branch, static_cast<float *>(amps_host));
     return QSV_OK;
+}
+
+qsv_status sv_debug_jit_compile(const qsv_circuit *c, int layer_begin, int layer_end,
+                                const qsv_fuse_opts *opts, size_t *code_bytes, double *seconds) {
+    if (!c) return fail(QSV_EINVAL, "sv_debug_jit_compile: null circuit");
+    TileShape sh;
+    qsv_status st = resolve_shape(c, opts, sh);
+    if (st != QSV_OK) return st;
+    if (sh.R == 0) return fail(QSV_EUNSUPPORTED, "sv_debug_jit_compile: state too small for a tile");
+    std::shared_ptr<Plan> plan;
+    if ((st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) return st;
+    return jit_compile_only(*plan, code_bytes, seconds);
 }
 
 }  // extern "C"

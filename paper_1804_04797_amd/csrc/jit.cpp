@@ -1,0 +1,479 @@
+// Runtime specialisation of fused passes (hipRTC).
+//
+// The generic tile kernel interprets a pass program op by op.  For large
+// states the program of every pass is instead turned into straight-line HIP
+// source (register slots, physical bit positions, LDS permutations and gate
+// constants all become literals), compiled once for gfx950 with hipRTC and
+// cached by its source text for the life of the process.  The generated
+// kernels perform exactly the ops of the program, in order.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "jit.h"
+#include "qsv_internal.h"
+
+namespace qsv {
+
+namespace {
+
+const char *kPrelude = R"(
+typedef float v4f __attribute__((ext_vector_type(4)));
+#define F2(x, y) make_float2((x), (y))
+__device__ __forceinline__ float2 cm(float2 a, float cr, float ci) {
+    return make_float2(a.x * cr - a.y * ci, a.x * ci + a.y * cr);
+}
+__constant__ float QW[16] = {1.f, 0.70710678118654752f, 0.f, -0.70710678118654752f,
+                            -1.f, -0.70710678118654752f, 0.f, 0.70710678118654752f,
+                            0.f, 0.70710678118654752f, 1.f, 0.70710678118654752f,
+                            0.f, -0.70710678118654752f, -1.f, -0.70710678118654752f};
+__device__ __forceinline__ float2 xsign(float2 a, unsigned m) {
+    return make_float2(__uint_as_float(__float_as_uint(a.x) ^ m),
+                       __uint_as_float(__float_as_uint(a.y) ^ m));
+}
+)";
+
+std::string hex64(uint64_t v) {
+    char b[32];
+    std::snprintf(b, sizeof b, "0x%llxull", (unsigned long long)v);
+    return b;
+}
+
+std::string flt(double v) {
+    char b[48];
+    std::snprintf(b, sizeof b, "%.9ef", v);
+    return b;
+}
+
+// OR of ((src >> i0) & mask) << p0 over maximal runs where consecutive source
+// bits map to consecutive target bits.
+std::string scatter_expr(const std::string &src, const std::vector<int> &target, bool wide) {
+    std::ostringstream o;
+    const char *one = wide ? "1ull" : "1u";
+    bool first = true;
+    size_t i = 0;
+    while (i < target.size()) {
+        size_t j = i;
+        while (j + 1 < target.size() && target[j + 1] == target[j] + 1) ++j;
+        const int len = int(j - i + 1);
+        if (!first) o << " | ";
+        first = false;
+        o << "((((unsigned long long)(" << src << ") >> " << i << ") & ((" << one << " << " << len
+          << ") - 1)) << " << target[i] << ")";
+        i = j + 1;
+    }
+    if (first) o << "0ull";
+    return o.str();
+}
+
+// Code generator for one pass.
+//
+// Besides turning every op into literal code, the generator keeps two kinds
+// of phase factors out of the per-amplitude arithmetic:
+//  - a compile-time rotation i^m per register: even phases (Z, S, CZ between
+//    register qubits) only change m, and butterflies absorb m by choosing
+//    which components they add or subtract;
+//  - a per-thread run-time exponent e of w = e^{i pi/4} and a zero flag:
+//    diagonal gates whose qubits are thread or tile-index bits multiply every
+//    amplitude of a thread by the same factor, so they only update e.
+// Both are applied (one complex multiply per amplitude) before an LDS
+// exchange and together with the pass scale before the store.
+struct Gen {
+    const PassProg &P;
+    int R, T, N, L;
+    std::ostringstream o;
+    int m[64];            // pending rotation i^m of each register
+    bool e_dirty = false; // e or the zero flag may differ from (0, alive)
+    Gen(const PassProg &p, int r, int t) : P(p), R(r), T(t), N(1 << r), L(r + t) {
+        for (int j = 0; j < 64; ++j) m[j] = 0;
+    }
+
+    bool is_reg(uint32_t loc) const { return loc < uint32_t(R); }
+    bool is_glob(uint32_t loc) const { return loc & 0x80u; }
+    std::string pred(uint32_t loc) const {
+        std::ostringstream s;
+        if (is_glob(loc)) s << "unsigned((base >> " << (loc & 0x7f) << ") & 1ull)";
+        else s << "((t >> " << (loc - R) << ") & 1u)";
+        return s.str();
+    }
+
+    // component c (0 = re, 1 = im) of i^r * Z as a signed term
+    static std::string term(const char *z, int r, int c) {
+        r &= 3;
+        static const char *comp[4][2] = {{"+%s.x", "+%s.y"}, {"-%s.y", "+%s.x"},
+                                         {"-%s.x", "-%s.y"}, {"+%s.y", "-%s.x"}};
+        char b[32];
+        std::snprintf(b, sizeof b, comp[r][c], z);
+        return b;
+    }
+    // i^a * X + i^b * Y
+    static std::string sum(int a, int b) {
+        std::string re = term("x", a, 0) + term("y", b, 0);
+        std::string im = term("x", a, 1) + term("y", b, 1);
+        return "F2(" + re + "," + im + ")";
+    }
+
+    void butterfly(uint32_t code, int S) {
+        for (int j = 0; j < N; ++j) {
+            if (j & (1 << S)) continue;
+            const int k = j | (1 << S);
+            const int d = (m[k] - m[j]) & 3;
+            // outputs relative to the common factor i^{m[j]}
+            int a0 = 0, b0 = d, a1 = 0, b1 = d;  // x' = i^a0 X + i^b0 Y ; y' = i^a1 X + i^b1 Y
+            switch (code) {
+            case OP_H: b1 = d + 2; break;                       // x+y, x-y
+            case OP_SX: b0 = d + 3; a1 = 3; break;              // x-iy, -ix+y
+            case OP_SY: b0 = d + 2; break;                      // x-y, x+y
+            case OP_SXDG: b0 = d + 1; a1 = 1; break;            // x+iy, ix+y
+            case OP_SYDG: a1 = 2; break;                        // x+y, -x+y
+            }
+            o << "{const float2 x=v[" << j << "],y=v[" << k << "];v[" << j << "]=" << sum(a0, b0)
+              << ";v[" << k << "]=" << sum(a1, b1) << ";}\n";
+            m[k] = m[j];
+        }
+    }
+    void rot_reg(int j, int k) { m[j] = (m[j] + k / 2) & 3; }
+    void omega_reg(int j) {  // multiply the stored value by w = (1 + i)/sqrt2
+        o << "v[" << j << "]=F2((v[" << j << "].x-v[" << j << "].y)*" << flt(std::sqrt(0.5)) << ",(v["
+          << j << "].x+v[" << j << "].y)*" << flt(std::sqrt(0.5)) << ");\n";
+    }
+    void phase_reg(int j, int k) {
+        k &= 7;
+        rot_reg(j, k & 6);
+        if (k & 1) omega_reg(j);
+    }
+    void zero_reg(int j) {
+        o << "v[" << j << "]=F2(0.f,0.f);\n";
+        m[j] = 0;
+    }
+
+    void op_phase(uint32_t loc, int k) {
+        if (is_reg(loc)) {
+            for (int j = 0; j < N; ++j)
+                if (j & (1 << loc)) phase_reg(j, k);
+            return;
+        }
+        o << "e += " << pred(loc) << " * " << (k & 7) << "u;\n";
+        e_dirty = true;
+    }
+
+    void op_cz(uint32_t a, uint32_t b) {
+        if (!is_reg(a) && is_reg(b)) std::swap(a, b);
+        if (is_reg(a) && is_reg(b)) {
+            for (int j = 0; j < N; ++j)
+                if ((j & (1 << a)) && (j & (1 << b))) rot_reg(j, 4);
+            return;
+        }
+        if (is_reg(a)) {
+            o << "{const unsigned msk = " << pred(b) << " << 31;\n";
+            for (int j = 0; j < N; ++j)
+                if (j & (1 << a)) o << "v[" << j << "]=xsign(v[" << j << "],msk);\n";
+            o << "}\n";
+            return;
+        }
+        o << "e += (" << pred(a) << " & " << pred(b) << ") * 4u;\n";
+        e_dirty = true;
+    }
+
+    void op_proj(uint32_t loc, uint32_t b, uint32_t c) {
+        std::string l = c ? "unsigned((branch >> " + std::to_string(b) + ") & 1ull)"
+                          : std::to_string(b) + "u";
+        if (is_reg(loc)) {
+            int save[64];
+            std::copy(m, m + 64, save);
+            if (!c) {
+                for (int j = 0; j < N; ++j)
+                    if (((j >> loc) & 1) != int(b)) zero_reg(j);
+                return;
+            }
+            // branch-dependent: both arms leave the surviving registers' m unchanged
+            o << "if (" << l << ") {\n";
+            for (int j = 0; j < N; ++j)
+                if (!(j & (1 << loc))) o << "v[" << j << "]=F2(0.f,0.f);\n";
+            o << "} else {\n";
+            for (int j = 0; j < N; ++j)
+                if (j & (1 << loc)) o << "v[" << j << "]=F2(0.f,0.f);\n";
+            o << "}\n";
+            std::copy(save, save + 64, m);
+            return;
+        }
+        o << "alive &= unsigned((" << pred(loc) << ") == " << l << ");\n";
+        e_dirty = true;
+    }
+
+    void op_zb(uint32_t loc, uint32_t b) {
+        if (is_reg(loc)) {
+            o << "{const unsigned msk = unsigned((branch >> " << b << ") & 1ull) << 31;\n";
+            for (int j = 0; j < N; ++j)
+                if (j & (1 << loc)) o << "v[" << j << "]=xsign(v[" << j << "],msk);\n";
+            o << "}\n";
+            return;
+        }
+        o << "e += (unsigned((branch >> " << b << ") & 1ull) & " << pred(loc) << ") * 4u;\n";
+        e_dirty = true;
+    }
+
+    // Multiply every register by i^{m_j} * w^e * alive * (sr + i si), then
+    // reset the pending factors.
+    void materialize(double sr, double si) {
+        const bool unit = (sr == 1.0 && si == 0.0);
+        if (!e_dirty) {
+            for (int j = 0; j < N; ++j) {
+                const int r = m[j] & 3;
+                if (unit) {
+                    if (r == 0) continue;
+                    o << "{const float2 x=v[" << j << "];v[" << j << "]=F2(" << term("x", r, 0) << ","
+                      << term("x", r, 1) << ");}\n";
+                } else if (si == 0.0) {
+                    // real scale: (+-s x or +-s y) per component
+                    o << "{const float2 x=v[" << j << "];v[" << j << "]=F2((" << term("x", r, 0) << ")*"
+                      << flt(sr) << ",(" << term("x", r, 1) << ")*" << flt(sr) << ");}\n";
+                } else {
+                    // rotate the constant instead of the value
+                    double cr = sr, ci = si;
+                    for (int q = 0; q < r; ++q) { double t2 = -ci; ci = cr; cr = t2; }
+                    o << "v[" << j << "]=cm(v[" << j << "]," << flt(cr) << "," << flt(ci) << ");\n";
+                }
+                m[j] = 0;
+            }
+            return;
+        }
+        o << "{const float a0 = alive ? QW[e & 7u] : 0.f, b0 = alive ? QW[8u + (e & 7u)] : 0.f;\n";
+        o << "const float fr = a0 * " << flt(sr) << " - b0 * " << flt(si) << ", fi = a0 * " << flt(si)
+          << " + b0 * " << flt(sr) << ";\n";
+        for (int j = 0; j < N; ++j) {
+            static const char *rr[4] = {"fr", "-fi", "-fr", "fi"};
+            static const char *ri[4] = {"fi", "fr", "-fi", "-fr"};
+            const int r = m[j] & 3;
+            o << "v[" << j << "]=cm(v[" << j << "]," << rr[r] << "," << ri[r] << ");\n";
+            m[j] = 0;
+        }
+        o << "e = 0u; alive = 1u;}\n";
+        e_dirty = false;
+    }
+
+    void op_xchg(uint64_t pw) {
+        materialize(1.0, 0.0);
+        int perm[kMaxSlots];
+        for (int s = 0; s < L; ++s) perm[s] = int((pw >> (4 * s)) & 0xf);
+        // write at padded old coordinate, read at padded new coordinate
+        o << "{__syncthreads();\n";
+        for (int j = 0; j < N; ++j) o << "lds[wt+" << j << "]=v[" << j << "];\n";
+        o << "unsigned yt = 0u";
+        for (int u = 0; u < T; ++u) o << " | (((t >> " << u << ") & 1u) << " << perm[R + u] << ")";
+        o << ";\nconst unsigned rt = yt + (yt >> " << R << ");\n__syncthreads();\n";
+        for (int j = 0; j < N; ++j) {
+            unsigned yj = 0;
+            for (int s = 0; s < R; ++s)
+                if ((j >> s) & 1) yj |= 1u << perm[s];
+            o << "v[" << j << "]=lds[rt+" << (yj + (yj >> R)) << "u];\n";
+        }
+        o << "}\n";
+    }
+
+    std::string emit(const std::string &name, bool &uses_lds) {
+        uses_lds = false;
+        for (int pc = 0; pc < P.n_ops; ++pc) {
+            if ((P.ops[pc] & 0xff) == OP_XCHG) { uses_lds = true; ++pc; }
+        }
+        std::vector<int> glob(P.glob_bits, P.glob_bits + P.n_glob);
+        std::vector<int> tld, tst;
+        for (int u = 0; u < T; ++u) { tld.push_back(P.ld_phys[R + u]); tst.push_back(P.st_phys[R + u]); }
+        o << "extern \"C\" __global__ void __launch_bounds__(" << (1 << T) << ") " << name
+          << "(float2* __restrict__ a, unsigned long long branch, unsigned long long tile0) {\n";
+        if (uses_lds) o << "extern __shared__ float2 lds[];\n";
+        o << "const unsigned t = threadIdx.x;\n";
+        o << "const unsigned long long tile = tile0 + blockIdx.x;\n";
+        o << "const unsigned long long base = " << scatter_expr("tile", glob, true) << ";\n";
+        o << "unsigned e = 0u, alive = 1u;\n";
+        o << "(void)base; (void)branch; (void)e; (void)alive;\n";
+        if (uses_lds) o << "const unsigned wt = t * " << ((1 << R) + 1) << "u;\n";
+        o << "float2 v[" << N << "];\n";
+        o << "{const v4f* src = (const v4f*)(a + (base | " << scatter_expr("t", tld, true) << "));\n";
+        for (int j = 0; j < N; j += 2) {
+            uint64_t roff = 0;
+            for (int s = 1; s < R; ++s)
+                if ((j >> s) & 1) roff |= 1ull << P.ld_phys[s];
+            o << "{const v4f w = __builtin_nontemporal_load(src + " << hex64(roff / 2) << ");v[" << j
+              << "]=F2(w.x,w.y);v[" << j + 1 << "]=F2(w.z,w.w);}\n";
+        }
+        o << "}\n";
+        bool scaled = false;
+        for (int pc = 0; pc < P.n_ops; ++pc) {
+            const uint64_t op = P.ops[pc];
+            const uint32_t code = op & 0xff, a = (op >> 8) & 0xff, b = (op >> 16) & 0xff,
+                           c = (op >> 24) & 0xff;
+            switch (code) {
+            case OP_H: case OP_SX: case OP_SY: case OP_SXDG: case OP_SYDG: butterfly(code, int(a)); break;
+            case OP_PHASE: op_phase(a, int(b)); break;
+            case OP_CZ: op_cz(a, b); break;
+            case OP_PROJ: op_proj(a, b, c); break;
+            case OP_ZB: op_zb(a, b); break;
+            case OP_XCHG: op_xchg(P.ops[++pc]); break;
+            case OP_SCALE: materialize(P.scale_re, P.scale_im); scaled = true; break;
+            default: break;
+            }
+        }
+        if (!scaled) materialize(1.0, 0.0);
+        o << "{v4f* dst = (v4f*)(a + (base | " << scatter_expr("t", tst, true) << "));\n";
+        for (int j = 0; j < N; j += 2) {
+            uint64_t roff = 0;
+            for (int s = 1; s < R; ++s)
+                if ((j >> s) & 1) roff |= 1ull << P.st_phys[s];
+            o << "{const v4f w = {v[" << j << "].x,v[" << j << "].y,v[" << j + 1 << "].x,v[" << j + 1
+              << "].y};__builtin_nontemporal_store(w, dst + " << hex64(roff / 2) << ");}\n";
+        }
+        o << "}\n}\n";
+        return o.str();
+    }
+};
+
+struct CacheEntry {
+    hipModule_t mod = nullptr;
+    std::vector<hipFunction_t> fns;
+    std::vector<size_t> lds;
+    double compile_s = 0;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, std::string>, std::shared_ptr<CacheEntry>> g_cache;
+double g_total_compile_s = 0;
+
+qsv_status compile_source(const std::string &src, std::vector<char> &code, std::string &log) {
+    if (const char *dump = std::getenv("QSV_JIT_DUMP")) {  // debugging aid: keep the source
+        if (FILE *f = std::fopen(dump, "w")) {
+            std::fwrite(src.data(), 1, src.size(), f);
+            std::fclose(f);
+        }
+    }
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "qsv_pass.hip", 0, nullptr, nullptr) !=
+        HIPRTC_SUCCESS)
+        return fail(QSV_EINTERNAL, "hiprtcCreateProgram failed");
+    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17",
+                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                          "-mllvm", "-simplifycfg-sink-common=false"};
+    hiprtcResult r = hiprtcCompileProgram(prog, int(sizeof(opts) / sizeof(opts[0])), opts);
+    size_t ls = 0;
+    hiprtcGetProgramLogSize(prog, &ls);
+    log.assign(ls, '\0');
+    if (ls) hiprtcGetProgramLog(prog, &log[0]);
+    if (r != HIPRTC_SUCCESS) {
+        hiprtcDestroyProgram(&prog);
+        return fail(QSV_EINTERNAL, "hipRTC compile failed: " + log.substr(0, 2000));
+    }
+    size_t cs = 0;
+    hiprtcGetCodeSize(prog, &cs);
+    code.resize(cs);
+    hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    return QSV_OK;
+}
+
+}  // namespace
+
+std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes) {
+    std::string src = kPrelude;
+    for (size_t p = 0; p < plan.passes.size(); ++p) {
+        Gen g(plan.passes[p].prog, plan.R, plan.T);
+        bool uses_lds = false;
+        src += g.emit("qsv_pass_" + std::to_string(p), uses_lds);
+        if (lds_bytes)
+            lds_bytes->push_back(uses_lds ? ((size_t(1) << (plan.R + plan.T)) + (size_t(1) << plan.T)) *
+                                                8
+                                          : 0);
+    }
+    return src;
+}
+
+qsv_status jit_compile_only(const Plan &plan, size_t *code_bytes, double *seconds) {
+    std::vector<size_t> lds;
+    std::string src = jit_source(plan, &lds);
+    std::vector<char> code;
+    std::string log;
+    auto t0 = std::chrono::steady_clock::now();
+    qsv_status st = compile_source(src, code, log);
+    if (st != QSV_OK) return st;
+    if (seconds)
+        *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (code_bytes) *code_bytes = code.size();
+    return QSV_OK;
+}
+
+qsv_status jit_prepare(Plan &plan) {
+    if (plan.jit) return QSV_OK;
+    int dev = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) return fail(QSV_EHIP, "hipGetDevice failed");
+    std::vector<size_t> lds;
+    std::string src = jit_source(plan, &lds);
+    std::lock_guard<std::mutex> g(g_mu);
+    auto key = std::make_pair(dev, src);
+    auto it = g_cache.find(key);
+    if (it == g_cache.end()) {
+        auto e = std::make_shared<CacheEntry>();
+        std::vector<char> code;
+        std::string log;
+        auto t0 = std::chrono::steady_clock::now();
+        qsv_status st = compile_source(src, code, log);
+        if (st != QSV_OK) return st;
+        he = hipModuleLoadData(&e->mod, code.data());
+        if (he != hipSuccess)
+            return fail(QSV_EHIP, std::string("hipModuleLoadData: ") + hipGetErrorString(he));
+        for (size_t p = 0; p < plan.passes.size(); ++p) {
+            hipFunction_t f;
+            he = hipModuleGetFunction(&f, e->mod, ("qsv_pass_" + std::to_string(p)).c_str());
+            if (he != hipSuccess)
+                return fail(QSV_EHIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(he));
+            e->fns.push_back(f);
+        }
+        e->lds = lds;
+        e->compile_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        g_total_compile_s += e->compile_s;
+        it = g_cache.emplace(key, e).first;
+    }
+    plan.jit = it->second;
+    return QSV_OK;
+}
+
+qsv_status jit_launch(const Plan &plan, void *amps, uint64_t branch, hipStream_t s) {
+    const CacheEntry &e = *static_cast<const CacheEntry *>(plan.jit.get());
+    const int L = plan.R + plan.T;
+    const uint64_t tiles = 1ull << (plan.n - L);
+    const uint64_t chunk = 1ull << 30;
+    for (size_t p = 0; p < plan.passes.size(); ++p) {
+        for (uint64_t t0 = 0; t0 < tiles; t0 += chunk) {
+            const uint64_t cnt = (tiles - t0 < chunk) ? tiles - t0 : chunk;
+            void *args[] = {&amps, &branch, const_cast<uint64_t *>(&t0)};
+            unsigned long long br = branch, tt = t0;
+            void *a = amps;
+            args[0] = &a;
+            args[1] = &br;
+            args[2] = &tt;
+            hipError_t he = hipModuleLaunchKernel(e.fns[p], unsigned(cnt), 1, 1, 1u << plan.T, 1, 1,
+                                                  unsigned(e.lds[p]), s, args, nullptr);
+            if (he != hipSuccess)
+                return fail(QSV_EHIP, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(he));
+        }
+    }
+    return QSV_OK;
+}
+
+double jit_total_compile_seconds() {
+    std::lock_guard<std::mutex> g(g_mu);
+    return g_total_compile_s;
+}
+
+}  // namespace qsv

@@ -222,7 +222,9 @@ qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Pla
     const int R = shape.R, T = shape.T, L = R + T, cl = shape.c;
     if (R < 1 || T < 1 || L > n || L > kMaxSlots || cl < 1 || cl - 1 > T || cl > L)
         return fail(QSV_EUNSUPPORTED, "tile shape does not fit the circuit");
-    out = Plan();
+    out.passes.clear();
+    out.gate_range.clear();
+    out.jit.reset();
     out.n = n; out.R = R; out.T = T; out.c = cl;
     gates_in_range(c, lb, le, out.gate_range);
     const std::vector<int> &idx = out.gate_range;

@@ -28,8 +28,8 @@ STATUS = {0: "QSV_OK", 1: "QSV_EINVAL", 2: "QSV_ERANGE", 3: "QSV_ENOMEM", 4: "QS
 EXPORTS = ["circuit_create", "circuit_destroy", "circuit_info", "circuit_gates",
            "circuit_split", "sv_init", "sv_apply_fused", "sv_apply_plain", "sv_amplitudes",
            "sv_norm_fp64", "sv_branch_combine", "sv_batch_create", "sv_batch_run",
-           "sv_batch_destroy", "sv_plan_info", "sv_debug_emulate", "qsv_last_error",
-           "qsv_version"]
+           "sv_batch_destroy", "sv_plan_info", "sv_debug_emulate", "sv_debug_jit_compile",
+           "qsv_last_error", "qsv_version"]
 
 
 class QsvError(RuntimeError):
@@ -40,7 +40,7 @@ class QsvError(RuntimeError):
 
 class FuseOpts(ctypes.Structure):
     _fields_ = [("reg_qubits", ctypes.c_int), ("thread_qubits", ctypes.c_int),
-                ("low_qubits", ctypes.c_int), ("plain", ctypes.c_int)]
+                ("low_qubits", ctypes.c_int), ("plain", ctypes.c_int), ("jit", ctypes.c_int)]
 
 
 _lib = None
@@ -73,6 +73,7 @@ def lib():
         "sv_batch_destroy": (None, [vp]),
         "sv_plan_info": (st, [vp, i32, i32, vp, P(i32), vp, vp, sz, vp, sz]),
         "sv_debug_emulate": (st, [vp, vp, u64, i32, i32, vp]),
+        "sv_debug_jit_compile": (st, [vp, i32, i32, vp, P(sz), P(ctypes.c_double)]),
         "qsv_last_error": (ctypes.c_char_p, []),
         "qsv_version": (ctypes.c_char_p, []),
     }
@@ -118,7 +119,7 @@ def _opts(opts):
         return None
     if isinstance(opts, FuseOpts):
         return ctypes.byref(opts)
-    o = FuseOpts(**opts)
+    o = FuseOpts(**{"jit": 0, **opts})
     return ctypes.byref(o)
 
 
@@ -241,6 +242,14 @@ def sv_debug_emulate(amps_host: np.ndarray, c, branch=0, layer_begin=0, layer_en
     assert amps_host.dtype == np.complex64 and amps_host.flags.c_contiguous
     _check(lib().sv_debug_emulate(_ptr(amps_host), c, ctypes.c_uint64(branch), layer_begin,
                                   layer_end, _opts(opts)))
+
+
+def sv_debug_jit_compile(c, layer_begin=0, layer_end=-1, opts=None):
+    nb = ctypes.c_size_t()
+    sec = ctypes.c_double()
+    _check(lib().sv_debug_jit_compile(c, layer_begin, layer_end, _opts(opts), ctypes.byref(nb),
+                                      ctypes.byref(sec)))
+    return nb.value, sec.value
 
 
 def version() -> str:

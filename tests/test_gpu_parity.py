@@ -97,19 +97,22 @@ SHAPES = [None, (5, 8, 5), (5, 7, 5), (4, 7, 5), (4, 6, 5), (3, 6, 4), (3, 4, 3)
           (4, 8, 6), (6, 8, 5), (5, 9, 7), (4, 9, 5), (6, 7, 3)]
 
 
-def _opts(shape):
+def _opts(shape, jit=0):
     if shape is None:
-        return None
-    return dict(reg_qubits=shape[0], thread_qubits=shape[1], low_qubits=shape[2], plain=0)
+        return None if jit == 0 else dict(reg_qubits=0, thread_qubits=0, low_qubits=0, plain=0,
+                                          jit=jit)
+    return dict(reg_qubits=shape[0], thread_qubits=shape[1], low_qubits=shape[2], plain=0, jit=jit)
 
 
+@pytest.mark.parametrize("jit", [-1, 1])
 @pytest.mark.parametrize("shape", SHAPES)
-def test_fused_4x5_all_shapes(shape):
+def test_fused_4x5_all_shapes(shape, jit):
+    """Generic pass kernel (jit=-1) and per-pass compiled kernels (jit=1)."""
     _gpu()
     spec, c, lat = _lattice_circuit("4x5-d10")
     ref = sim.simulate(_oracle_gates(c), lat.n)
     a = _state(lat.n)
-    qsv.sv_apply_fused(a, c, opts=_opts(shape))
+    qsv.sv_apply_fused(a, c, opts=_opts(shape, jit))
     _check_full(a, ref, lat.n)
 
 
@@ -138,10 +141,11 @@ def test_fused_explicit_gates_all_kinds():
     c = qsv.circuit_create(4, 4, None, gates=g)
     ref = sim.simulate(_oracle_gates(c), n)
     for shape in (None, (3, 6, 4), (5, 9, 7), (6, 8, 5)):
-        a = _state(n)
-        qsv.sv_apply_fused(a, c, opts=_opts(shape))
-        got = a.cpu().numpy()
-        assert np.max(np.abs(got - ref)) <= TOL
+        for jit in (-1, 1):
+            a = _state(n)
+            qsv.sv_apply_fused(a, c, opts=_opts(shape, jit))
+            got = a.cpu().numpy()
+            assert np.max(np.abs(got - ref)) <= TOL, (shape, jit)
     a = _state(n)
     qsv.sv_apply_plain(a, c)
     assert np.max(np.abs(a.cpu().numpy() - ref)) <= TOL
@@ -189,6 +193,7 @@ def test_5x6_d20_full_size_sampled():
     assert np.array_equal(xs, workloads.bitstrings(30, 4096, workloads.BITSTRING_SEED_BASE + 2))
     a = _state(30, qsv.INIT_PLUS)
     qsv.sv_apply_fused(a, c, layer_begin=1)
+    torch.cuda.synchronize()
     bits = torch.from_numpy(xs.view(np.int64)).to(DEV)
     out = torch.empty(xs.size, dtype=torch.complex128, device=DEV)
     qsv.sv_amplitudes(a, 30, bits, out, c128=True)
@@ -198,7 +203,11 @@ def test_5x6_d20_full_size_sampled():
     nrm = torch.zeros(1, dtype=torch.float64, device=DEV)
     qsv.sv_norm_fp64(a, 30, nrm)
     assert abs(nrm.item() - 1) < 1e-4
-    # the plain comparator gives the same amplitudes
+    # the generic pass kernel and the plain comparator give the same amplitudes
+    qsv.sv_init(a, 30, qsv.INIT_PLUS)
+    qsv.sv_apply_fused(a, c, layer_begin=1, opts=_opts(None, -1))
+    qsv.sv_amplitudes(a, 30, bits, out, c128=True)
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= TOL
     qsv.sv_init(a, 30, qsv.INIT_PLUS)
     qsv.sv_apply_plain(a, c, layer_begin=1)
     qsv.sv_amplitudes(a, 30, bits, out, c128=True)
@@ -355,11 +364,12 @@ def test_split_end_to_end_gpu():
     A = torch.empty(1 << len(qa), dtype=torch.complex64, device=DEV)
     B = torch.empty(1 << len(qb), dtype=torch.complex64, device=DEV)
     for br in range(nbr):
+        jit = 1 if br % 2 else -1   # both pass-kernel flavours
         qsv.sv_init(A, len(qa), qsv.INIT_ZERO)
-        qsv.sv_apply_fused(A, ha, branch=br)
+        qsv.sv_apply_fused(A, ha, branch=br, opts=_opts(None, jit))
         qsv.sv_amplitudes(A, len(qa), xa, At[br])
         qsv.sv_init(B, len(qb), qsv.INIT_ZERO)
-        qsv.sv_apply_fused(B, hb, branch=br)
+        qsv.sv_apply_fused(B, hb, branch=br, opts=_opts(None, jit))
         qsv.sv_amplitudes(B, len(qb), xb, Bt[br])
     sg = torch.tensor([sim.fold_sign(int(x), [(a, b, 0) for a, b in folded]) for x in xs],
                       dtype=torch.int8, device=DEV)
