@@ -41,6 +41,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="run one 1 GiB device copy first (counter calibration)")
     return p.parse_args()
 
 
@@ -104,6 +106,12 @@ def main():
         opts = dict(reg_qubits=a.reg, thread_qubits=a.thr, low_qubits=a.low, plain=0)
     pres = workloads.present_mask(spec)
 
+    if a.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     amps = torch.empty(1 << n, dtype=torch.complex64, device=dev)
     xs_np, ref = golden(a.workload)
     if xs_np is None:
@@ -153,7 +161,8 @@ def main():
     if a.traffic_json and os.path.exists(a.traffic_json):
         tj = json.load(open(a.traffic_json))
         t = tj.get(a.workload)
-        if t and t.get("reg") == a.reg and t.get("thr") == a.thr and t.get("low") == a.low:
+        if (t and t.get("reg") == a.reg and t.get("thr") == a.thr and t.get("low") == a.low
+                and t.get("kernel_rev") == qsv.version()):
             traffic = t.get("bytes_per_launch")
 
     got = out.cpu().numpy()
