@@ -175,6 +175,21 @@ qsv_status sv_apply_fused(void *amps, const qsv_circuit *c, uint64_t branch,
                           void *stream);
 
 /*
+ * sv_simulate - the whole sweep of one circuit in one call: initial state,
+ * layers [layer_begin, layer_end), FP64 norm, gather.  Same result as
+ * sv_init + sv_apply_fused + sv_norm_fp64 + sv_amplitudes, but on the
+ * compiled-pass path the initial state (kind and basis as in sv_init) is
+ * generated in registers by the first pass instead of being written and read
+ * back, and the last pass accumulates the FP64 norm of the tiles it stores,
+ * saving two full-state sweeps.  norm_out_dev (device double[1]) may be NULL;
+ * with m = 0 nothing is gathered.  opts->plain selects the unfused path.
+ */
+qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int init_kind,
+                       uint64_t basis, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
+                       double *norm_out_dev, const uint64_t *bitstrings_dev, size_t m,
+                       void *amps_out_dev, int out_c128, void *stream);
+
+/*
  * sv_apply_plain - the unfused comparator: one full-state (or, for diagonal
  * gates, partial) kernel per gate, the gate-by-gate method that Section 2.4
  * and Table "28qubit" measure their speedup against.  Same arguments and

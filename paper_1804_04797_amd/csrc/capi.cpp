@@ -47,18 +47,29 @@ qsv_status check_device() {
     return QSV_OK;
 }
 
-// FP64 partial-sum buffer of the norm kernel, one per device, kept for the
-// life of the process.
-qsv_status norm_partials(double **out) {
+// FP64 partial-sum buffer of the norm reductions, one per device, grown on
+// demand and kept for the life of the process.
+qsv_status norm_partials(size_t count, double **out) {
     static std::mutex mu;
     static double *buf[64] = {nullptr};
+    static size_t cap[64] = {0};
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(QSV_EUNSUPPORTED, "device ordinal out of range");
     std::lock_guard<std::mutex> g(mu);
-    if (!buf[dev]) {
-        e = hipMalloc(reinterpret_cast<void **>(&buf[dev]), 65536 * sizeof(double));
+    if (cap[dev] < count) {
+        size_t want = std::max<size_t>(count, 65536);
+        double *p = nullptr;
+        e = hipMalloc(reinterpret_cast<void **>(&p), want * sizeof(double));
         if (e != hipSuccess) return fail(QSV_ENOMEM, "norm partials: hipMalloc failed");
+        if (buf[dev]) {
+            // the old buffer may still be read by queued work: synchronise first
+            hipDeviceSynchronize();
+            hipFree(buf[dev]);
+        }
+        buf[dev] = p;
+        cap[dev] = want;
     }
     *out = buf[dev];
     return QSV_OK;
@@ -139,7 +150,7 @@ using namespace qsv;
 extern "C" {
 
 const char *qsv_last_error(void) { return g_err.c_str(); }
-const char *qsv_version(void) { return "qsv 0.1 gfx950"; }
+const char *qsv_version(void) { return "qsv 0.2 gfx950"; }
 
 qsv_status circuit_create(int rows, int cols, const uint8_t *present, int depth, uint64_t seed,
                           const qsv_gate *gates, size_t n_gates, qsv_circuit **out) {
@@ -261,9 +272,9 @@ qsv_status sv_apply_fused(void *amps, const qsv_circuit *c, uint64_t branch, int
     if (use_jit(c, opts)) {
         {
             std::lock_guard<std::mutex> g(plan->jit_mu);
-            if ((st = jit_prepare(*plan)) != QSV_OK) return st;
+            if ((st = jit_prepare(*plan, kJitPlain)) != QSV_OK) return st;
         }
-        return jit_launch(*plan, amps, branch, s);
+        return jit_launch(*plan, kJitPlain, amps, branch, 0, nullptr, s);
     }
     for (const Pass &p : plan->passes) {
         hipError_t e = launch_fused(static_cast<float2 *>(amps), c->n, sh.R, sh.T, p.prog, branch, s);
@@ -289,7 +300,7 @@ qsv_status sv_norm_fp64(const void *amps, int n_qubits, double *out_dev, void *s
     if (!out_dev) return fail(QSV_EINVAL, "sv_norm_fp64: null output");
     if ((st = check_device()) != QSV_OK) return st;
     double *part = nullptr;
-    if ((st = norm_partials(&part)) != QSV_OK) return st;
+    if ((st = norm_partials(65536, &part)) != QSV_OK) return st;
     hipError_t e = launch_norm(static_cast<const float2 *>(amps), n_qubits, out_dev, part,
                                static_cast<hipStream_t>(stream));
     return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_norm_fp64");
@@ -307,6 +318,64 @@ qsv_status sv_branch_combine(const void *a_tab, const void *b_tab, size_t n_bran
                                          static_cast<double2 *>(out_dev),
                                          static_cast<hipStream_t>(stream));
     return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_branch_combine");
+}
+
+qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int init_kind,
+                       uint64_t basis, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
+                       double *norm_out_dev, const uint64_t *bitstrings_dev, size_t m,
+                       void *amps_out_dev, int out_c128, void *stream) {
+    if (!c) return fail(QSV_EINVAL, "sv_simulate: null circuit");
+    qsv_status st = check_state(amps, c->n);
+    if (st != QSV_OK) return st;
+    if (init_kind < 0 || init_kind > 2) return fail(QSV_EINVAL, "sv_simulate: unknown init kind");
+    if (init_kind == QSV_INIT_BASIS && basis >= (1ull << c->n))
+        return fail(QSV_ERANGE, "sv_simulate: basis index >= 2^n");
+    if (init_kind == QSV_INIT_ZERO) basis = 0;
+    if (layer_begin < 0) return fail(QSV_EINVAL, "sv_simulate: layer_begin < 0");
+    if (m && (!bitstrings_dev || !amps_out_dev)) return fail(QSV_EINVAL, "sv_simulate: null gather buffer");
+    if ((st = check_device()) != QSV_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TileShape sh;
+    bool fused = !(opts && opts->plain);
+    if (fused) {
+        if ((st = resolve_shape(c, opts, sh)) != QSV_OK) return st;
+        fused = sh.R != 0;
+    }
+    std::shared_ptr<Plan> plan;
+    if (fused && (st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) return st;
+    bool done_norm = false;
+    if (fused && use_jit(c, opts) && !plan->passes.empty()) {
+        // initial state generated by the first pass, norm by the last
+        const int variant = kJitInit | init_kind | (norm_out_dev ? kJitNorm : 0);
+        {
+            std::lock_guard<std::mutex> g(plan->jit_mu);
+            if ((st = jit_prepare(*plan, variant)) != QSV_OK) return st;
+        }
+        double *part = nullptr;
+        const uint64_t tiles = 1ull << (c->n - sh.R - sh.T);
+        if (norm_out_dev && (st = norm_partials(tiles, &part)) != QSV_OK) return st;
+        if ((st = jit_launch(*plan, variant, amps, branch, basis, part, s)) != QSV_OK) return st;
+        if (norm_out_dev) {
+            hipError_t e = launch_sum_partials(part, tiles, norm_out_dev, s);
+            if (e != hipSuccess) return hip_fail(e, "sv_simulate");
+            done_norm = true;
+        }
+    } else {
+        hipError_t e = launch_init(static_cast<float2 *>(amps), c->n, init_kind, basis, s);
+        if (e != hipSuccess) return hip_fail(e, "sv_simulate");
+        st = fused ? sv_apply_fused(amps, c, branch, layer_begin, layer_end, opts, stream)
+                   : sv_apply_plain(amps, c, branch, layer_begin, layer_end, stream);
+        if (st != QSV_OK) return st;
+    }
+    if (norm_out_dev && !done_norm) {
+        if ((st = sv_norm_fp64(amps, c->n, norm_out_dev, stream)) != QSV_OK) return st;
+    }
+    if (m) {
+        hipError_t e = launch_gather(static_cast<const float2 *>(amps), c->n, bitstrings_dev, m,
+                                     amps_out_dev, out_c128 ? 1 : 0, s);
+        if (e != hipSuccess) return hip_fail(e, "sv_simulate");
+    }
+    return QSV_OK;
 }
 
 qsv_status sv_plan_info(const qsv_circuit *c, int layer_begin, int layer_end,

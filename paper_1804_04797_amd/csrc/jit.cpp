@@ -283,7 +283,11 @@ struct Gen {
         o << "}\n";
     }
 
-    std::string emit(const std::string &name, bool &uses_lds) {
+    // init_kind: -1 = load the state; 0/1/2 = generate |0>, |+>^n or |basis>
+    // in registers (first pass of sv_simulate).  norm: accumulate the FP64
+    // sum of |amp|^2 of the tile into part[tile] after the store.
+    std::string emit(const std::string &name, bool &uses_lds, int init_kind = -1,
+                     bool norm = false, int n = 0) {
         uses_lds = false;
         for (int pc = 0; pc < P.n_ops; ++pc) {
             if ((P.ops[pc] & 0xff) == OP_XCHG) { uses_lds = true; ++pc; }
@@ -292,24 +296,39 @@ struct Gen {
         std::vector<int> tld, tst;
         for (int u = 0; u < T; ++u) { tld.push_back(P.ld_phys[R + u]); tst.push_back(P.st_phys[R + u]); }
         o << "extern \"C\" __global__ void __launch_bounds__(" << (1 << T) << ") " << name
-          << "(float2* __restrict__ a, unsigned long long branch, unsigned long long tile0) {\n";
+          << "(float2* __restrict__ a, unsigned long long branch, unsigned long long tile0, "
+             "unsigned long long basis, double* __restrict__ part) {\n";
         if (uses_lds) o << "extern __shared__ float2 lds[];\n";
-        o << "const unsigned t = threadIdx.x;\n";
+        o << "const unsigned t = threadIdx.x;\n(void)basis; (void)part;\n";
         o << "const unsigned long long tile = tile0 + blockIdx.x;\n";
         o << "const unsigned long long base = " << scatter_expr("tile", glob, true) << ";\n";
         o << "unsigned e = 0u, alive = 1u;\n";
         o << "(void)base; (void)branch; (void)e; (void)alive;\n";
         if (uses_lds) o << "const unsigned wt = t * " << ((1 << R) + 1) << "u;\n";
         o << "float2 v[" << N << "];\n";
-        o << "{const v4f* src = (const v4f*)(a + (base | " << scatter_expr("t", tld, true) << "));\n";
-        for (int j = 0; j < N; j += 2) {
-            uint64_t roff = 0;
-            for (int s = 1; s < R; ++s)
-                if ((j >> s) & 1) roff |= 1ull << P.ld_phys[s];
-            o << "{const v4f w = __builtin_nontemporal_load(src + " << hex64(roff / 2) << ");v[" << j
-              << "]=F2(w.x,w.y);v[" << j + 1 << "]=F2(w.z,w.w);}\n";
+        if (init_kind == 1) {
+            const std::string val = flt(std::pow(2.0, -0.5 * n));
+            for (int j = 0; j < N; ++j) o << "v[" << j << "]=F2(" << val << ",0.f);\n";
+        } else if (init_kind == 0 || init_kind == 2) {
+            o << "{const unsigned long long me = base | " << scatter_expr("t", tld, true) << ";\n";
+            for (int j = 0; j < N; ++j) {
+                uint64_t roff = 0;
+                for (int s = 0; s < R; ++s)
+                    if ((j >> s) & 1) roff |= 1ull << P.ld_phys[s];
+                o << "v[" << j << "]=F2((me | " << hex64(roff) << ") == basis ? 1.f : 0.f, 0.f);\n";
+            }
+            o << "}\n";
+        } else {
+            o << "{const v4f* src = (const v4f*)(a + (base | " << scatter_expr("t", tld, true) << "));\n";
+            for (int j = 0; j < N; j += 2) {
+                uint64_t roff = 0;
+                for (int s = 1; s < R; ++s)
+                    if ((j >> s) & 1) roff |= 1ull << P.ld_phys[s];
+                o << "{const v4f w = __builtin_nontemporal_load(src + " << hex64(roff / 2) << ");v[" << j
+                  << "]=F2(w.x,w.y);v[" << j + 1 << "]=F2(w.z,w.w);}\n";
+            }
+            o << "}\n";
         }
-        o << "}\n";
         bool scaled = false;
         for (int pc = 0; pc < P.n_ops; ++pc) {
             const uint64_t op = P.ops[pc];
@@ -335,7 +354,26 @@ struct Gen {
             o << "{const v4f w = {v[" << j << "].x,v[" << j << "].y,v[" << j + 1 << "].x,v[" << j + 1
               << "].y};__builtin_nontemporal_store(w, dst + " << hex64(roff / 2) << ");}\n";
         }
-        o << "}\n}\n";
+        o << "}\n";
+        if (norm) {
+            // FP64 |amp|^2: products of FP32 values are exact in FP64; fixed
+            // order: registers, then an xor butterfly over the wave, then the
+            // waves of the workgroup in index order.
+            o << "{double acc = 0.0;\n";
+            for (int j = 0; j < N; ++j)
+                o << "acc += (double)v[" << j << "].x*(double)v[" << j << "].x + (double)v[" << j
+                  << "].y*(double)v[" << j << "].y;\n";
+            const int waves = (1 << T) >= 64 ? (1 << T) / 64 : 1;
+            const int width = (1 << T) >= 64 ? 64 : (1 << T);
+            for (int off = width / 2; off >= 1; off /= 2)
+                o << "acc += __shfl_xor(acc, " << off << ", " << width << ");\n";
+            o << "__shared__ double red[" << waves << "];\n";
+            o << "if ((t & " << (width - 1) << "u) == 0u) red[t / " << width << "u] = acc;\n";
+            o << "__syncthreads();\nif (t == 0u) {double s = 0.0;\n";
+            for (int w = 0; w < waves; ++w) o << "s += red[" << w << "];\n";
+            o << "part[tile] = s;}\n}\n";
+        }
+        o << "}\n";
         return o.str();
     }
 };
@@ -384,12 +422,15 @@ qsv_status compile_source(const std::string &src, std::vector<char> &code, std::
 
 }  // namespace
 
-std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes) {
+std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int variant) {
+    const int init_kind = (variant & 4) ? (variant & 3) : -1;
+    const bool norm = (variant & 8) != 0;
     std::string src = kPrelude;
     for (size_t p = 0; p < plan.passes.size(); ++p) {
         Gen g(plan.passes[p].prog, plan.R, plan.T);
         bool uses_lds = false;
-        src += g.emit("qsv_pass_" + std::to_string(p), uses_lds);
+        src += g.emit("qsv_pass_" + std::to_string(p), uses_lds, p == 0 ? init_kind : -1,
+                      norm && p + 1 == plan.passes.size(), plan.n);
         if (lds_bytes)
             lds_bytes->push_back(uses_lds ? ((size_t(1) << (plan.R + plan.T)) + (size_t(1) << plan.T)) *
                                                 8
@@ -400,7 +441,7 @@ std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes) {
 
 qsv_status jit_compile_only(const Plan &plan, size_t *code_bytes, double *seconds) {
     std::vector<size_t> lds;
-    std::string src = jit_source(plan, &lds);
+    std::string src = jit_source(plan, &lds, 4 | 1 | 8);
     std::vector<char> code;
     std::string log;
     auto t0 = std::chrono::steady_clock::now();
@@ -412,13 +453,13 @@ qsv_status jit_compile_only(const Plan &plan, size_t *code_bytes, double *second
     return QSV_OK;
 }
 
-qsv_status jit_prepare(Plan &plan) {
-    if (plan.jit) return QSV_OK;
+qsv_status jit_prepare(Plan &plan, int variant) {
+    if (plan.jit_variants.count(variant)) return QSV_OK;
     int dev = 0;
     hipError_t he = hipGetDevice(&dev);
     if (he != hipSuccess) return fail(QSV_EHIP, "hipGetDevice failed");
     std::vector<size_t> lds;
-    std::string src = jit_source(plan, &lds);
+    std::string src = jit_source(plan, &lds, variant);
     std::lock_guard<std::mutex> g(g_mu);
     auto key = std::make_pair(dev, src);
     auto it = g_cache.find(key);
@@ -444,24 +485,25 @@ qsv_status jit_prepare(Plan &plan) {
         g_total_compile_s += e->compile_s;
         it = g_cache.emplace(key, e).first;
     }
-    plan.jit = it->second;
+    plan.jit_variants[variant] = it->second;
     return QSV_OK;
 }
 
-qsv_status jit_launch(const Plan &plan, void *amps, uint64_t branch, hipStream_t s) {
-    const CacheEntry &e = *static_cast<const CacheEntry *>(plan.jit.get());
+qsv_status jit_launch(const Plan &plan, int variant, void *amps, uint64_t branch, uint64_t basis,
+                      double *part, hipStream_t s) {
+    auto vit = plan.jit_variants.find(variant);
+    if (vit == plan.jit_variants.end()) return fail(QSV_EINTERNAL, "jit variant not prepared");
+    const CacheEntry &e = *static_cast<const CacheEntry *>(vit->second.get());
     const int L = plan.R + plan.T;
     const uint64_t tiles = 1ull << (plan.n - L);
     const uint64_t chunk = 1ull << 30;
     for (size_t p = 0; p < plan.passes.size(); ++p) {
         for (uint64_t t0 = 0; t0 < tiles; t0 += chunk) {
             const uint64_t cnt = (tiles - t0 < chunk) ? tiles - t0 : chunk;
-            void *args[] = {&amps, &branch, const_cast<uint64_t *>(&t0)};
-            unsigned long long br = branch, tt = t0;
+            unsigned long long br = branch, tt = t0, bs = basis;
             void *a = amps;
-            args[0] = &a;
-            args[1] = &br;
-            args[2] = &tt;
+            double *pt = part;
+            void *args[] = {&a, &br, &tt, &bs, &pt};
             hipError_t he = hipModuleLaunchKernel(e.fns[p], unsigned(cnt), 1, 1, 1u << plan.T, 1, 1,
                                                   unsigned(e.lds[p]), s, args, nullptr);
             if (he != hipSuccess)

@@ -10,12 +10,20 @@
 
 namespace qsv {
 
+// Kernel variants: bit 2 set -> the first pass generates the initial state
+// of kind (variant & 3) instead of loading it; bit 3 set -> the last pass
+// writes the FP64 norm partial of every tile.
+constexpr int kJitPlain = 0;
+constexpr int kJitInit = 4;
+constexpr int kJitNorm = 8;
+
 // HIP source of every pass of the plan as kernels qsv_pass_<p>.
-std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes);
+std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int variant);
 // Compile (cached by source text and device) and attach the kernels to plan.
-qsv_status jit_prepare(Plan &plan);
+qsv_status jit_prepare(Plan &plan, int variant);
 // Launch all passes of a prepared plan on stream s.
-qsv_status jit_launch(const Plan &plan, void *amps, uint64_t branch, hipStream_t s);
+qsv_status jit_launch(const Plan &plan, int variant, void *amps, uint64_t branch, uint64_t basis,
+                      double *part, hipStream_t s);
 // Compile without loading (no device needed).
 qsv_status jit_compile_only(const Plan &plan, size_t *code_bytes, double *seconds);
 double jit_total_compile_seconds();

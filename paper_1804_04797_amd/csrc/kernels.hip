@@ -407,16 +407,22 @@ k_norm_partial(const float4 *__restrict__ a, uint64_t quads_per_block, double *_
     if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
-// Pairwise sum of count partials (count <= 65536) by one block.
-__global__ void __launch_bounds__(256)
-k_sum_partials(const double *__restrict__ part, int count, double *__restrict__ out) {
-    __shared__ double s[256];
-    // each thread sums a strided subset pairwise-by-level
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < count; i += 256) acc += part[i];
-    s[threadIdx.x] = acc;
+// Sum of count partials by one block of 1024 threads: each thread keeps
+// eight independent accumulators over a fixed strided subset, then a fixed
+// tree over the threads.
+__global__ void __launch_bounds__(1024)
+k_sum_partials(const double *__restrict__ part, uint64_t count, double *__restrict__ out) {
+    __shared__ double s[1024];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint64_t i = threadIdx.x;
+    for (; i + 7 * 1024 < count; i += 8 * 1024) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] += part[i + k * 1024];
+    }
+    for (int k = 0; i < count; i += 1024, ++k) acc[k & 7] += part[i];
+    s[threadIdx.x] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = 512; h > 0; h >>= 1) {
         if (int(threadIdx.x) < h) s[threadIdx.x] += s[threadIdx.x + h];
         __syncthreads();
     }
@@ -590,7 +596,12 @@ hipError_t launch_norm(const float2 *amps, int n, double *out, double *partials,
     const uint64_t qpb = (dim / 2) >> lb;
     hipLaunchKernelGGL(k_norm_partial, dim3(blocks), dim3(256), 0, s,
                        reinterpret_cast<const float4 *>(amps), qpb, partials);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, int(blocks), out);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, partials, uint64_t(blocks), out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double *part, uint64_t count, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, part, count, out);
     return hipGetLastError();
 }
 

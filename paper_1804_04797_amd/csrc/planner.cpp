@@ -224,7 +224,7 @@ qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Pla
         return fail(QSV_EUNSUPPORTED, "tile shape does not fit the circuit");
     out.passes.clear();
     out.gate_range.clear();
-    out.jit.reset();
+    out.jit_variants.clear();
     out.n = n; out.R = R; out.T = T; out.c = cl;
     gates_in_range(c, lb, le, out.gate_range);
     const std::vector<int> &idx = out.gate_range;

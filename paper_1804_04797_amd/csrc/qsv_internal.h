@@ -72,7 +72,7 @@ struct Plan {
     int n = 0, R = 0, T = 0, c = 0;
     std::vector<Pass> passes;
     std::vector<int> gate_range;  // indices of the gates in the layer range
-    std::shared_ptr<void> jit;    // compiled straight-line kernels (jit.cpp), if any
+    std::map<int, std::shared_ptr<void>> jit_variants;  // compiled kernels (jit.cpp)
     std::mutex jit_mu;
 };
 

@@ -380,3 +380,57 @@ def test_split_end_to_end_gpu():
     # FP64 combine parity on identical (GPU-produced) complex64 tables
     want = sim.combine(At.cpu().numpy(), Bt.cpu().numpy(), sg.cpu().numpy())
     assert np.max(np.abs(out.cpu().numpy() - want)) <= 1e-12
+
+
+@pytest.mark.parametrize("jit", [-1, 1])
+@pytest.mark.parametrize("kind,basis,lb", [(qsv.INIT_ZERO, 0, 0), (qsv.INIT_PLUS, 0, 1),
+                                           (qsv.INIT_BASIS, 0xABCDE, 0)])
+def test_simulate_entry(kind, basis, lb, jit):
+    """sv_simulate: initial state generated in the first pass, FP64 norm from
+    the last pass, gather; against the oracle started from the same state."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("4x5-d10")
+    n = lat.n
+    gates = _oracle_gates(c)
+    psi0 = np.zeros(1 << n, np.complex128)
+    if kind == qsv.INIT_PLUS:
+        psi0[:] = 2.0 ** (-n / 2)
+    else:
+        psi0[basis] = 1
+    ref = sim.run(psi0, n, [g for g in gates if g[3] >= lb])
+    xs = workloads.bitstrings(n, 300, 11)
+    a = torch.empty(1 << n, dtype=torch.complex64, device=DEV)
+    nrm = torch.zeros(1, dtype=torch.float64, device=DEV)
+    bits = torch.from_numpy(xs.view(np.int64)).to(DEV)
+    out = torch.empty(xs.size, dtype=torch.complex128, device=DEV)
+    qsv.sv_simulate(a, c, init_kind=kind, basis=basis, layer_begin=lb, opts=_opts(None, jit),
+                    norm_out=nrm, bitstrings=bits, amps_out=out, c128=True)
+    _check_full(a, ref, n)
+    assert np.max(np.abs(out.cpu().numpy() - ref[xs])) <= TOL
+    # the epilogue norm equals the norm kernel on the same stored state
+    n2 = torch.zeros(1, dtype=torch.float64, device=DEV)
+    qsv.sv_norm_fp64(a, n, n2)
+    assert abs(nrm.item() - n2.item()) <= 1e-12
+    assert abs(nrm.item() - 1) <= 1e-5
+
+
+def test_simulate_full_size_5x6_d20():
+    """The benchmark's step (30 qubits, |+> folded into the first pass, norm
+    folded into the last) against the stored oracle amplitudes."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("5x6-d20")
+    xs, ref = _golden("5x6-d20")
+    a = torch.empty(1 << 30, dtype=torch.complex64, device=DEV)
+    nrm = torch.zeros(1, dtype=torch.float64, device=DEV)
+    bits = torch.from_numpy(xs.view(np.int64)).to(DEV)
+    out = torch.empty(xs.size, dtype=torch.complex128, device=DEV)
+    qsv.sv_simulate(a, c, init_kind=qsv.INIT_PLUS, layer_begin=1, norm_out=nrm, bitstrings=bits,
+                    amps_out=out, c128=True)
+    d = np.max(np.abs(out.cpu().numpy() - ref))
+    assert d <= TOL and d * 2 ** 15 <= TOL_SCALED, d
+    n2 = torch.zeros(1, dtype=torch.float64, device=DEV)
+    qsv.sv_norm_fp64(a, 30, n2)
+    assert abs(nrm.item() - n2.item()) <= 1e-12
+    assert abs(nrm.item() - 1) <= 1e-4
+    del a
+    torch.cuda.empty_cache()
