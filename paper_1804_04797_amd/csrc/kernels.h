@@ -10,6 +10,11 @@ namespace qsv {
 bool fused_shape_supported(int R, int T);
 hipError_t launch_fused(float2 *amps, int n, int R, int T, const PassProg &p, uint64_t branch,
                         hipStream_t s);
+hipError_t launch_fused_batch(int R, int T, const BatchSeg *segs, int nseg, const BatchEntry *ents,
+                              const PassProg *progs, int round, uint64_t blocks, int init_plus,
+                              hipStream_t s);
+hipError_t launch_gather_batch(const BatchEntry *ents, uint64_t count, const uint64_t *xs,
+                               uint64_t m, float2 *out, hipStream_t s);
 hipError_t launch_plain_1q(float2 *amps, int n, int q, const float m[8], hipStream_t s);
 hipError_t launch_plain_phase(float2 *amps, int n, int q, float cr, float ci, hipStream_t s);
 hipError_t launch_plain_cz(float2 *amps, int n, int q0, int q1, hipStream_t s);

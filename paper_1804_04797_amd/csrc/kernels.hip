@@ -105,33 +105,44 @@ template <int S, int N> __device__ __forceinline__ void proj_slot(float2 (&v)[N]
     }
 }
 
-// Dispatch a runtime register-slot index to a compile-time template.
-#define QSV_SLOT_DISPATCH(s, CALL)                                   \
-    switch (s) {                                                     \
-    case 0: { constexpr int S_ = 0; CALL; } break;                   \
-    case 1: if constexpr (R > 1) { constexpr int S_ = 1; CALL; } break; \
-    case 2: if constexpr (R > 2) { constexpr int S_ = 2; CALL; } break; \
-    case 3: if constexpr (R > 3) { constexpr int S_ = 3; CALL; } break; \
-    case 4: if constexpr (R > 4) { constexpr int S_ = 4; CALL; } break; \
-    case 5: if constexpr (R > 5) { constexpr int S_ = 5; CALL; } break; \
-    default: break;                                                  \
+// Dispatch a runtime register-slot index to a compile-time template.  The
+// last slot is the default so that every path of the switch computes: an
+// empty path would make the register allocator copy the whole amplitude
+// array at the merge.
+#define QSV_SLOT_DISPATCH(s, CALL)                                                  \
+    switch (s) {                                                                    \
+    case 0: if constexpr (R - 1 > 0) { constexpr int S_ = 0; CALL; break; } [[fallthrough]]; \
+    case 1: if constexpr (R - 1 > 1) { constexpr int S_ = 1; CALL; break; } [[fallthrough]]; \
+    case 2: if constexpr (R - 1 > 2) { constexpr int S_ = 2; CALL; break; } [[fallthrough]]; \
+    case 3: if constexpr (R - 1 > 3) { constexpr int S_ = 3; CALL; break; } [[fallthrough]]; \
+    case 4: if constexpr (R - 1 > 4) { constexpr int S_ = 4; CALL; break; } [[fallthrough]]; \
+    default: { constexpr int S_ = R - 1; CALL; } break;                             \
     }
 
-template <int R, int S1, int N>
-__device__ __forceinline__ void cz_reg_reg(float2 (&v)[N], int s2) {
-    switch (s2) {
-    case 0: if constexpr (S1 != 0) neg_slot2<S1, 0>(v); break;
-    case 1: if constexpr (R > 1 && S1 != 1) neg_slot2<S1, 1>(v); break;
-    case 2: if constexpr (R > 2 && S1 != 2) neg_slot2<S1, 2>(v); break;
-    case 3: if constexpr (R > 3 && S1 != 3) neg_slot2<S1, 3>(v); break;
-    case 4: if constexpr (R > 4 && S1 != 4) neg_slot2<S1, 4>(v); break;
-    case 5: if constexpr (R > 5 && S1 != 5) neg_slot2<S1, 5>(v); break;
-    default: break;
+// negate amplitudes with slot bit S = 1 when m has the sign bit set
+template <int S, int N> __device__ __forceinline__ void xneg_slot(float2 (&v)[N], uint32_t m) {
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        if (j & (1 << S))
+            v[j] = f2(__uint_as_float(__float_as_uint(v[j].x) ^ m),
+                      __uint_as_float(__float_as_uint(v[j].y) ^ m));
+}
+// zero amplitudes whose slot bit S differs from l (branch-free)
+template <int S, int N> __device__ __forceinline__ void proj_sel(float2 (&v)[N], uint32_t l) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const bool z = (uint32_t((j >> S) & 1) != l);
+        v[j] = z ? f2(0.f, 0.f) : v[j];
     }
+}
+template <int R, int S1, int N>
+__device__ __forceinline__ void cz_reg_reg(float2 (&v)[N], uint32_t s2) {
+    // the slot pair is distinct by construction; S1 == S2 cannot occur
+    QSV_SLOT_DISPATCH(s2, (neg_slot2<S1, S_, N>(v)));
 }
 
 // ---------------------------------------------------------------------------
-// Fused tile pass.
+// Fused tile pass (generic: interprets a pass program).
 //
 // One workgroup of 2^T threads owns one tile of 2^(R+T) amplitudes: slot
 // coordinate x = j | t << R (j = register index, t = thread index) sits at
@@ -141,20 +152,27 @@ __device__ __forceinline__ void cz_reg_reg(float2 (&v)[N], int s2) {
 // contiguous runs of 2^c amplitudes.  XCHG permutes slot bits through LDS
 // (write at padded old coordinate, read at padded new coordinate; one pad
 // element per 2^R keeps the 64 lanes of a wave on distinct banks).
+// Diagonal gates whose qubit is a thread or tile-index bit multiply every
+// amplitude of a thread by the same power of w = e^{i pi/4}: they only add to
+// the per-thread exponent e, applied before an XCHG (when the op says so) and
+// by the closing SCALE.
+// init: 0 = load the tile, 1 = every amplitude = init_val (|+>^n).
 // ---------------------------------------------------------------------------
 template <int R, int T>
-__global__ void __launch_bounds__(1 << T)
-k_fused(float2 *__restrict__ amps, const PassProg P, uint64_t branch, uint64_t tile0) {
+__device__ __forceinline__ void fused_tile(float2 *__restrict__ amps, const PassProg &P,
+                                           uint64_t branch, uint64_t tile, int init,
+                                           float init_val, float2 *lds) {
     constexpr int N = 1 << R;
-    extern __shared__ float2 lds[];
     const uint32_t t = threadIdx.x;
-    const uint64_t tile = tile0 + blockIdx.x;
 
     uint64_t base = 0;
     for (int i = 0; i < P.n_glob; ++i) base |= ((tile >> i) & 1ull) << P.glob_bits[i];
 
     float2 v[N];
-    {
+    if (init) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[j] = f2(init_val, 0.f);
+    } else {
         uint64_t toff = 0;
 #pragma unroll
         for (int u = 0; u < T; ++u)
@@ -176,8 +194,10 @@ k_fused(float2 *__restrict__ amps, const PassProg P, uint64_t branch, uint64_t t
         if (loc & 0x80u) return uint32_t((base >> (loc & 0x7fu)) & 1ull);
         return (t >> (loc - R)) & 1u;
     };
+    uint32_t e = 0, alive = 1;
 
-    for (int pc = 0; pc < P.n_ops; ++pc) {
+    int pc = 0;
+    do {
         const uint64_t op = P.ops[pc];
         const uint32_t code = uint32_t(op) & 0xffu;
         const uint32_t a = uint32_t(op >> 8) & 0xffu;
@@ -190,12 +210,11 @@ k_fused(float2 *__restrict__ amps, const PassProg P, uint64_t branch, uint64_t t
         case 4: QSV_SLOT_DISPATCH(a, (bf_sxdg<S_, N>(v))); break;
         case 5: QSV_SLOT_DISPATCH(a, (bf_sydg<S_, N>(v))); break;
         case 8: {  // PHASE
-            const float cr = c_wr[b], ci = c_wi[b];
             if (a < uint32_t(R)) {
+                const float cr = c_wr[b], ci = c_wi[b];
                 QSV_SLOT_DISPATCH(a, (ph_slot<S_, N>(v, cr, ci)));
-            } else if (pred(a)) {
-#pragma unroll
-                for (int j = 0; j < N; ++j) v[j] = cmul(v[j], cr, ci);
+            } else {
+                e += pred(a) * b;
             }
             break;
         }
@@ -203,38 +222,44 @@ k_fused(float2 *__restrict__ amps, const PassProg P, uint64_t branch, uint64_t t
             uint32_t x = a, y = b;
             if (x >= uint32_t(R) && y < uint32_t(R)) { uint32_t tmp = x; x = y; y = tmp; }
             if (x < uint32_t(R) && y < uint32_t(R)) {
-                QSV_SLOT_DISPATCH(x, (cz_reg_reg<R, S_, N>(v, int(y))));
+                QSV_SLOT_DISPATCH(x, (cz_reg_reg<R, S_, N>(v, y)));
             } else if (x < uint32_t(R)) {
-                if (pred(y)) { QSV_SLOT_DISPATCH(x, (neg_slot<S_, N>(v))); }
-            } else if (pred(x) & pred(y)) {
-#pragma unroll
-                for (int j = 0; j < N; ++j) v[j] = f2(-v[j].x, -v[j].y);
+                const uint32_t m = pred(y) << 31;
+                QSV_SLOT_DISPATCH(x, (xneg_slot<S_, N>(v, m)));
+            } else {
+                e += (pred(x) & pred(y)) * 4u;
             }
             break;
         }
         case 10: {  // PROJ
-            const int l = c ? int((branch >> b) & 1ull) : int(b);
+            const uint32_t l = c ? uint32_t((branch >> b) & 1ull) : b;
             if (a < uint32_t(R)) {
-                QSV_SLOT_DISPATCH(a, (proj_slot<S_, N>(v, l)));
-            } else if (int(pred(a)) != l) {
-#pragma unroll
-                for (int j = 0; j < N; ++j) v[j] = f2(0.f, 0.f);
+                QSV_SLOT_DISPATCH(a, (proj_sel<S_, N>(v, l)));
+            } else {
+                alive &= uint32_t(pred(a) == l);
             }
             break;
         }
         case 11: {  // ZB
-            if ((branch >> b) & 1ull) {
-                if (a < uint32_t(R)) {
-                    QSV_SLOT_DISPATCH(a, (neg_slot<S_, N>(v)));
-                } else if (pred(a)) {
-#pragma unroll
-                    for (int j = 0; j < N; ++j) v[j] = f2(-v[j].x, -v[j].y);
-                }
+            const uint32_t bit = uint32_t((branch >> b) & 1ull);
+            if (a < uint32_t(R)) {
+                QSV_SLOT_DISPATCH(a, (xneg_slot<S_, N>(v, bit << 31)));
+            } else {
+                e += (bit & pred(a)) * 4u;
             }
             break;
         }
         case 12: {  // XCHG: new slot s takes old slot perm[s]
             const uint64_t pw = P.ops[++pc];
+            {   // phases accumulated on thread/tile bits are applied first
+                // (unconditionally: a skipped path would cost a full copy of v)
+                const float fr = alive ? c_wr[e & 7u] : 0.f, fi = alive ? c_wi[e & 7u] : 0.f;
+#pragma unroll
+                for (int j = 0; j < N; ++j) v[j] = cmul(v[j], fr, fi);
+                e = 0;
+                alive = 1;
+                (void)c;
+            }
             __syncthreads();  // earlier reads of LDS are complete
             const uint32_t wt = (t << R) + t;  // padded old coordinate of (t, 0)
 #pragma unroll
@@ -255,21 +280,18 @@ k_fused(float2 *__restrict__ amps, const PassProg P, uint64_t branch, uint64_t t
             }
             break;
         }
-        case 13: {  // SCALE
-            const float cr = P.scale_re, ci = P.scale_im;
-            if (ci == 0.f) {
+        default: {  // SCALE (closes every program): pass scale x w^e x alive
+            const float wr = alive ? c_wr[e & 7u] : 0.f, wi = alive ? c_wi[e & 7u] : 0.f;
+            const float cr = P.scale_re * wr - P.scale_im * wi;
+            const float ci = P.scale_re * wi + P.scale_im * wr;
 #pragma unroll
-                for (int j = 0; j < N; ++j) v[j] = f2(v[j].x * cr, v[j].y * cr);
-            } else {
-#pragma unroll
-                for (int j = 0; j < N; ++j) v[j] = cmul(v[j], cr, ci);
-            }
+            for (int j = 0; j < N; ++j) v[j] = cmul(v[j], cr, ci);
+            e = 0;
+            alive = 1;
             break;
         }
-        default:
-            break;
         }
-    }
+    } while (++pc < P.n_ops);
 
     {
         uint64_t toff = 0;
@@ -287,6 +309,47 @@ k_fused(float2 *__restrict__ amps, const PassProg P, uint64_t branch, uint64_t t
             __builtin_nontemporal_store(w, reinterpret_cast<v4f *>(dst + roff));
         }
     }
+}
+
+template <int R, int T>
+__global__ void __launch_bounds__(1 << T)
+k_fused(float2 *__restrict__ amps, const PassProg P, uint64_t branch, uint64_t tile0) {
+    extern __shared__ float2 lds[];
+    fused_tile<R, T>(amps, P, branch, tile0 + blockIdx.x, 0, 0.f, lds);
+}
+
+// One pass round of a batch: block b belongs to the segment with the largest
+// start <= b; the segment names the entry (state, branch, program) and the
+// first tile.  Entries whose round is their first pass may generate |+>^n.
+template <int R, int T>
+__global__ void __launch_bounds__(1 << T)
+k_fused_batch(const BatchSeg *__restrict__ segs, int nseg, const BatchEntry *__restrict__ ents,
+              const PassProg *__restrict__ progs, int round, int init_plus) {
+    extern __shared__ float2 lds[];
+    const uint64_t blk = blockIdx.x;
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {  // last segment with start <= blk
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].start <= blk) lo = mid; else hi = mid - 1;
+    }
+    const BatchSeg sg = segs[lo];
+    const BatchEntry en = ents[sg.entry];
+    const PassProg &P = progs[en.prog0 + round];
+    const int init = (init_plus && round == 0) ? 1 : 0;
+    fused_tile<R, T>(reinterpret_cast<float2 *>(en.amps), P, en.branch, blk - sg.start, init,
+                     en.init_val, lds);
+}
+
+// Gather for every entry of a batch: out[e*m + k] = amps_e[xs[e*m + k]].
+__global__ void __launch_bounds__(256)
+k_gather_batch(const BatchEntry *__restrict__ ents, uint64_t count, const uint64_t *__restrict__ xs,
+               uint64_t m, float2 *__restrict__ out) {
+    const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= count * m) return;
+    const BatchEntry en = ents[i / m];
+    const uint64_t x = xs[i];
+    const float2 *a = reinterpret_cast<const float2 *>(en.amps);
+    out[i] = (x < (1ull << en.n)) ? a[x] : f2(__builtin_nanf(""), __builtin_nanf(""));
 }
 
 // ---------------------------------------------------------------------------
@@ -504,7 +567,47 @@ hipError_t launch_fused_t(float2 *amps, int n, const PassProg &p, uint64_t branc
     return hipSuccess;
 }
 
+template <int R, int T>
+hipError_t launch_fused_batch_t(const BatchSeg *segs, int nseg, const BatchEntry *ents,
+                                const PassProg *progs, int round, uint64_t blocks, int init_plus,
+                                hipStream_t s) {
+    constexpr int L = R + T;
+    const size_t lds = (size_t(1) << L) * sizeof(float2) + (size_t(1) << T) * sizeof(float2);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fused_batch<R, T>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    if (blocks == 0) return hipSuccess;
+    if (blocks > (1ull << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_fused_batch<R, T>), dim3(unsigned(blocks)), dim3(1 << T), lds, s, segs,
+                       nseg, ents, progs, round, init_plus);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_fused_batch(int R, int T, const BatchSeg *segs, int nseg, const BatchEntry *ents,
+                              const PassProg *progs, int round, uint64_t blocks, int init_plus,
+                              hipStream_t s) {
+    switch (R * 16 + T) {
+    case 5 * 16 + 8: return launch_fused_batch_t<5, 8>(segs, nseg, ents, progs, round, blocks, init_plus, s);
+    case 4 * 16 + 8: return launch_fused_batch_t<4, 8>(segs, nseg, ents, progs, round, blocks, init_plus, s);
+    case 5 * 16 + 7: return launch_fused_batch_t<5, 7>(segs, nseg, ents, progs, round, blocks, init_plus, s);
+    case 4 * 16 + 7: return launch_fused_batch_t<4, 7>(segs, nseg, ents, progs, round, blocks, init_plus, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_gather_batch(const BatchEntry *ents, uint64_t count, const uint64_t *xs,
+                               uint64_t m, float2 *out, hipStream_t s) {
+    if (count * m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_batch, dim3(unsigned((count * m + 255) / 256)), dim3(256), 0, s,
+                       ents, count, xs, m, out);
+    return hipGetLastError();
+}
 
 bool fused_shape_supported(int R, int T) {
     switch (R * 16 + T) {

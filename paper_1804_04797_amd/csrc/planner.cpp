@@ -442,7 +442,9 @@ qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Pla
         }
         P.scale_re = float(sr);
         P.scale_im = float(si);
-        if (!(sr == 1.0 && si == 0.0)) pb.op(make_op(OP_SCALE));
+        // every program closes with SCALE: it also applies the phases that
+        // the generic kernel accumulated on thread and tile-index bits
+        pb.op(make_op(OP_SCALE));
         if (pb.ops.size() > size_t(kMaxOps))
             return fail(QSV_EINTERNAL, "planner: program too long");
         std::copy(pb.ops.begin(), pb.ops.end(), P.ops);

@@ -55,6 +55,21 @@ struct PassProg {
     int32_t n_glob;
 };
 
+// Device-side tables of a batch (batch.cpp).
+struct BatchEntry {
+    void *amps;         // state of the entry (complex64[2^n])
+    uint64_t branch;    // branch index of PB/ZB gates
+    uint32_t prog0;     // index of the entry's first pass program
+    uint32_t n;         // qubits
+    float init_val;     // 2^{-n/2}
+    uint32_t pad;
+};
+struct BatchSeg {
+    uint64_t start;     // first block of the segment in its round's launch
+    uint32_t entry;
+    uint32_t pad;
+};
+
 struct Pass {
     PassProg prog;
     std::vector<int> gates;       // circuit gate indices, in program order

@@ -238,6 +238,43 @@ def sv_branch_combine(a_tab, b_tab, n_branches, m, sign, out, stream=None):
                                    _ptr(out), _stream(stream)))
 
 
+class Batch:
+    """Owning handle of a qsv_batch; keeps its circuits alive."""
+
+    def __init__(self, handle, circuits):
+        self.handle = ctypes.c_void_p(handle)
+        self.circuits = list(circuits)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.sv_batch_destroy(h)
+            self.handle = None
+
+    @property
+    def _as_parameter_(self):
+        return self.handle
+
+
+def sv_batch_create(circuits, branch_ids=None, opts=None) -> Batch:
+    arr = (ctypes.c_void_p * len(circuits))(*[c.handle.value for c in circuits])
+    br = None
+    if branch_ids is not None:
+        br = np.ascontiguousarray(np.asarray(branch_ids, dtype=np.uint64))
+        assert br.size == len(circuits)
+    out = ctypes.c_void_p()
+    _check(lib().sv_batch_create(arr, _ptr(br) if br is not None else None, len(circuits),
+                                 _opts(opts), ctypes.byref(out)))
+    return Batch(out.value, circuits)
+
+
+def sv_batch_run(batch, amps_list, init_plus=False, bitstrings=None, m=0, amp_table=None,
+                 stream=None):
+    arr = (ctypes.c_void_p * len(amps_list))(*[_ptr(a) for a in amps_list])
+    _check(lib().sv_batch_run(batch, arr, 1 if init_plus else 0, _ptr(bitstrings), m,
+                              _ptr(amp_table), _stream(stream)))
+
+
 def sv_plan_info(c, layer_begin=0, layer_end=-1, opts=None):
     n, _, ng = circuit_info(c)
     npass = ctypes.c_int()

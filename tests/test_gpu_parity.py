@@ -434,3 +434,84 @@ def test_simulate_full_size_5x6_d20():
     assert abs(nrm.item() - 1) <= 1e-4
     del a
     torch.cuda.empty_cache()
+
+
+def _uneven(count, n_range, d_range, seed):
+    out = []
+    for n, d, s in workloads.uneven_batch(count, seed, n_range, d_range):
+        rows, cols, pres = workloads.lattice_for_qubits(n)
+        c = qsv.circuit_create(rows, cols, pres, d, s)
+        out.append((c, OC.random_circuit(OC.Lattice.for_qubits(n), d, s), n))
+    return out
+
+
+@pytest.mark.parametrize("init_plus", [False, True])
+def test_batch_uneven_circuits(init_plus):
+    """Independent circuits of uneven size in one graph launch: every entry's
+    full state and its gathered amplitudes against the oracle; the graph is
+    replayed with eager work in between and every replay is checked."""
+    _gpu()
+    items = _uneven(12, (12, 17), (6, 14), 123)
+    b = qsv.sv_batch_create([c for c, _, _ in items])
+    states = [torch.empty(1 << n, dtype=torch.complex64, device=DEV) for _, _, n in items]
+    m = 64
+    xs = np.concatenate([workloads.bitstrings(n, m, 7 + i) for i, (_, _, n) in enumerate(items)])
+    bits = torch.from_numpy(xs.view(np.int64)).to(DEV)
+    table = torch.empty(len(items) * m, dtype=torch.complex64, device=DEV)
+    refs = []
+    for c, gates, n in items:
+        if init_plus:
+            psi = np.full(1 << n, 2.0 ** (-n / 2), np.complex128)
+            refs.append(sim.run(psi, n, [g for g in gates if g[3] >= 1]))
+        else:
+            refs.append(sim.simulate(gates, n))
+    for rep in range(3):
+        if not init_plus:
+            for st, (_, _, n) in zip(states, items):
+                qsv.sv_init(st, n, qsv.INIT_ZERO)
+        qsv.sv_batch_run(b, states, init_plus=init_plus, bitstrings=bits, m=m, amp_table=table)
+        torch.cuda.synchronize()
+        tab = table.cpu().numpy()
+        for i, (st, ref, (_, _, n)) in enumerate(zip(states, refs, items)):
+            _check_full(st, ref, n)
+            assert np.max(np.abs(tab[i * m:(i + 1) * m] - ref[xs[i * m:(i + 1) * m]])) <= TOL
+        # eager work between replays (torch and the library)
+        for st in states:
+            st.zero_()
+        torch.cuda.synchronize()
+
+
+def test_batch_split_branches_end_to_end():
+    """Both halves of a cut circuit, every branch, one batch: gathered
+    half-amplitude tables, FP64 combine, against the full oracle state."""
+    _gpu()
+    rows, cols, depth, seed = 4, 6, 12, 77
+    n = rows * cols
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    mask = workloads.column_cut_mask(rows, cols, 2)
+    ha, hb, ceff, folded = qsv.circuit_split(c, mask)
+    qa = [q for q in range(n) if (mask >> q) & 1]
+    qb = [q for q in range(n) if not (mask >> q) & 1]
+    nbr = 1 << ceff
+    xs = workloads.bitstrings(n, 256, 9)
+    xa = np.array([sim.sub_index(int(x), qa) for x in xs], np.uint64)
+    xb = np.array([sim.sub_index(int(x), qb) for x in xs], np.uint64)
+    circs = [ha] * nbr + [hb] * nbr
+    brs = list(range(nbr)) * 2
+    b = qsv.sv_batch_create(circs, brs)
+    states = [torch.empty(1 << len(qa), dtype=torch.complex64, device=DEV) for _ in range(nbr)] + \
+             [torch.empty(1 << len(qb), dtype=torch.complex64, device=DEV) for _ in range(nbr)]
+    m = xs.size
+    bits = torch.from_numpy(np.concatenate([xa] * nbr + [xb] * nbr).view(np.int64)).to(DEV)
+    table = torch.empty(2 * nbr * m, dtype=torch.complex64, device=DEV)
+    qsv.sv_batch_run(b, states, init_plus=True, bitstrings=bits, m=m, amp_table=table)
+    sg = torch.tensor([sim.fold_sign(int(x), [(a, bb, 0) for a, bb in folded]) for x in xs],
+                      dtype=torch.int8, device=DEV)
+    out = torch.empty(m, dtype=torch.complex128, device=DEV)
+    At = table[: nbr * m].view(nbr, m)
+    Bt = table[nbr * m:].view(nbr, m)
+    qsv.sv_branch_combine(At, Bt, nbr, m, sg, out)
+    ref = sim.simulate(OC.random_circuit(OC.Lattice(rows, cols), depth, seed), n)[xs]
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= TOL
+    want = sim.combine(At.cpu().numpy(), Bt.cpu().numpy(), sg.cpu().numpy())
+    assert np.max(np.abs(out.cpu().numpy() - want)) <= 1e-12
