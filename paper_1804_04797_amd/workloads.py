@@ -8,6 +8,7 @@ synthetic workloads of the same shapes stand in for them:
   5x6-d20    30 qubits, 5x6 lattice, depth 20 (full 2^30 state, 8 GiB)
   6x6m2-d30  34 qubits, 6x6 lattice minus sites (0,0) and (5,5), depth 30
   7x7-d16    49 qubits, 7x7 lattice, depth 16, split after column 3
+  5x6-d16    30 qubits, 5x6 lattice, depth 16, split after column 2 (full check)
   uneven     512 circuits, n ~ U{14..26}, depth ~ U{8..24}
 
 Both the GPU path and the CPU oracle take their lattice, depth, seed and the
@@ -29,6 +30,8 @@ WORKLOADS = {
     "6x6m2-d30": dict(rows=6, cols=6, absent=((0, 0), (5, 5)), depth=30,
                       seed=CIRCUIT_SEED_BASE + 3, n=34),
     "7x7-d16": dict(rows=7, cols=7, absent=(), depth=16, seed=CIRCUIT_SEED_BASE + 4, n=49),
+    # reduced-size split case: cut after column 2 gives 10 cut CZs, 2^10 branch pairs
+    "5x6-d16": dict(rows=5, cols=6, absent=(), depth=16, seed=CIRCUIT_SEED_BASE + 6, n=30),
 }
 
 

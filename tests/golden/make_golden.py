@@ -1,6 +1,8 @@
 """Write oracle amplitudes for the 30-qubit workload (calls only oracle/).
 
-Output: tests/golden/5x6-d20_amplitudes.txt, one line per sampled bitstring:
+Outputs: tests/golden/<workload>_amplitudes.txt for the 30-qubit depth-20
+workload (4096 bitstrings) and the 30-qubit depth-16 workload used by the
+split check (1024 bitstrings), one line per sampled bitstring:
 "<bitstring> <re> <im>" with %.17g doubles, plus a header with the workload,
 the oracle norm and the oracle's own timing.  The 4096 bitstrings are the
 seeded uniform sample of paper_1804_04797_amd.workloads.bitstrings.
@@ -19,11 +21,11 @@ from oracle import sim  # noqa: E402
 from paper_1804_04797_amd import workloads  # noqa: E402
 
 
-def main(name="5x6-d20", m=4096):
+def main(name="5x6-d20", m=4096, bitstring_seed=workloads.BITSTRING_SEED_BASE + 2):
     spec = workloads.WORKLOADS[name]
     lat = OC.Lattice(spec["rows"], spec["cols"], workloads.present_grid(spec))
     gates = OC.random_circuit(lat, spec["depth"], spec["seed"])
-    xs = workloads.bitstrings(lat.n, m, workloads.BITSTRING_SEED_BASE + 2)
+    xs = workloads.bitstrings(lat.n, m, bitstring_seed)
     t0 = time.time()
     psi = sim.simulate(gates, lat.n)
     dt = time.time() - t0
@@ -31,7 +33,7 @@ def main(name="5x6-d20", m=4096):
     out = os.path.join(HERE, f"{name}_amplitudes.txt")
     with open(out, "w") as f:
         f.write(f"# workload {name}: n={lat.n} depth={spec['depth']} seed={spec['seed']:#x} "
-                f"gates={len(gates)} bitstring_seed={workloads.BITSTRING_SEED_BASE + 2:#x}\n")
+                f"gates={len(gates)} bitstring_seed={bitstring_seed:#x}\n")
         f.write(f"# oracle complex128 norm2={nrm:.17g} time_s={dt:.1f} threads={sim.threads()}\n")
         for x in xs.tolist():
             a = psi[x]
@@ -40,4 +42,5 @@ def main(name="5x6-d20", m=4096):
 
 
 if __name__ == "__main__":
-    main()
+    main("5x6-d20", 4096, workloads.BITSTRING_SEED_BASE + 2)
+    main("5x6-d16", 1024, workloads.BITSTRING_SEED_BASE + 6)

@@ -515,3 +515,70 @@ def test_batch_split_branches_end_to_end():
     assert np.max(np.abs(out.cpu().numpy() - ref)) <= TOL
     want = sim.combine(At.cpu().numpy(), Bt.cpu().numpy(), sg.cpu().numpy())
     assert np.max(np.abs(out.cpu().numpy() - want)) <= 1e-12
+
+
+def test_batch_split_5x6_d16_full_check():
+    """Reduced-size split at full branch count: 5x6 depth 16 cut after column
+    2 (10 cut CZs, 1024 branch pairs of 15-qubit halves) in one batch,
+    combined in FP64, against 1024 stored oracle amplitudes of the unsplit
+    30-qubit circuit."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("5x6-d16")
+    xs, ref = _golden("5x6-d16")
+    n = lat.n
+    mask = workloads.column_cut_mask(spec["rows"], spec["cols"], 2)
+    ha, hb, ceff, folded = qsv.circuit_split(c, mask)
+    assert ceff == 10 and folded == []
+    qa = [q for q in range(n) if (mask >> q) & 1]
+    qb = [q for q in range(n) if not (mask >> q) & 1]
+    nbr = 1 << ceff
+    m = xs.size
+    xa = np.array([sim.sub_index(int(x), qa) for x in xs], np.uint64)
+    xb = np.array([sim.sub_index(int(x), qb) for x in xs], np.uint64)
+    b = qsv.sv_batch_create([ha] * nbr + [hb] * nbr, list(range(nbr)) * 2)
+    states = [torch.empty(1 << 15, dtype=torch.complex64, device=DEV) for _ in range(2 * nbr)]
+    bits = torch.from_numpy(np.concatenate([xa] * nbr + [xb] * nbr).view(np.int64)).to(DEV)
+    table = torch.empty(2 * nbr * m, dtype=torch.complex64, device=DEV)
+    qsv.sv_batch_run(b, states, init_plus=True, bitstrings=bits, m=m, amp_table=table)
+    out = torch.empty(m, dtype=torch.complex128, device=DEV)
+    At = table[: nbr * m].view(nbr, m)
+    Bt = table[nbr * m:].view(nbr, m)
+    qsv.sv_branch_combine(At, Bt, nbr, m, None, out)
+    d = np.max(np.abs(out.cpu().numpy() - ref))
+    assert d <= TOL and d * 2 ** 15 <= TOL_SCALED, d
+
+
+def test_split_7x7_d16_branch_norm_identity():
+    """Full-size 49-qubit split (cut after column 3, 28|21): projector branches
+    of the 28-qubit half satisfy sum over the last cut group of |A_l|^2 =
+    |state before those projectors|^2 (complete projective measurement);
+    Z branches of the 21-qubit half stay unit vectors."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("7x7-d16")
+    mask = workloads.column_cut_mask(7, 7, 3)
+    ha, hb, ceff, folded = qsv.circuit_split(c, mask)
+    assert ceff == 11 and len(folded) == 3
+    layers = sorted({int(g["layer"]) for g in ha.gates() if qsv.KIND_NAME[int(g["kind"])] == "PB"})
+    assert layers == [5, 8, 13]
+    # branch bits 7..10 are the layer-13 cuts (bits in gate order)
+    pb_layer = [int(g["layer"]) for g in ha.gates() if qsv.KIND_NAME[int(g["kind"])] == "PB"]
+    assert pb_layer == [5] * 4 + [8] * 3 + [13] * 4
+    a = torch.empty(1 << 28, dtype=torch.complex64, device=DEV)
+    nrm = torch.zeros(1, dtype=torch.float64, device=DEV)
+    for prefix in (0b0110010, 0b1011101):
+        qsv.sv_simulate(a, ha, branch=prefix, init_kind=qsv.INIT_PLUS, layer_begin=1, layer_end=13,
+                        norm_out=nrm)
+        before = nrm.item()
+        total = 0.0
+        for suffix in range(16):
+            qsv.sv_simulate(a, ha, branch=prefix | (suffix << 7), init_kind=qsv.INIT_PLUS,
+                            layer_begin=1, norm_out=nrm)
+            total += nrm.item()
+        assert abs(total - before) <= 1e-5 * max(before, 1e-30), (total, before)
+        assert 0 < before <= 1 + 1e-5
+    bst = torch.empty(1 << 21, dtype=torch.complex64, device=DEV)
+    for br in (0, 5, 2047, 1234):
+        qsv.sv_simulate(bst, hb, branch=br, init_kind=qsv.INIT_PLUS, layer_begin=1, norm_out=nrm)
+        assert abs(nrm.item() - 1) <= 1e-5
+    del a
+    torch.cuda.empty_cache()
