@@ -251,6 +251,19 @@ qsv_status sv_batch_run(qsv_batch *b, void *const *amps_dev, int init_plus,
 void sv_batch_destroy(qsv_batch *b);
 
 /*
+ * sv_tune - autotune the fused sweep of layers [layer_begin, layer_end) of c.
+ * Candidate tile shapes (register qubits, thread qubits, always-resident low
+ * qubits) are planned; those within one pass of the fewest passes are timed
+ * on the device with sv_apply_fused on amps_scratch (device complex64[2^n],
+ * contents destroyed) and the fastest is written to *out (and its median time
+ * in ms to *best_ms, may be NULL).  The choice is remembered for this circuit
+ * content and layer range: later sv_apply_fused / sv_simulate calls with
+ * opts == NULL use it.  Synchronises the stream.
+ */
+qsv_status sv_tune(void *amps_scratch, const qsv_circuit *c, int layer_begin, int layer_end,
+                   qsv_fuse_opts *out, double *best_ms, void *stream);
+
+/*
  * Plan inspection (host only, no device needed).  For the plan that
  * sv_apply_fused would use: *n_passes, and for each gate of the layer range
  * the pass it runs in (pass_of_gate[i], -1 if outside the range) and its

@@ -83,8 +83,11 @@ qsv_status check_state(const void *amps, int n) {
     return QSV_OK;
 }
 
-qsv_status resolve_shape(const qsv_circuit *c, const qsv_fuse_opts *opts, TileShape &sh) {
+qsv_status resolve_shape(const qsv_circuit *c, const qsv_fuse_opts *opts, TileShape &sh,
+                         int lb = 0, int le = -1) {
     sh = default_shape(c->n);
+    qsv_fuse_opts tuned;
+    if (!opts && tuned_opts(c, lb, le, &tuned)) opts = &tuned;
     if (opts) {
         if (opts->reg_qubits) sh.R = opts->reg_qubits;
         if (opts->thread_qubits) sh.T = opts->thread_qubits;
@@ -263,7 +266,7 @@ qsv_status sv_apply_fused(void *amps, const qsv_circuit *c, uint64_t branch, int
     if (layer_begin < 0) return fail(QSV_EINVAL, "sv_apply_fused: layer_begin < 0");
     if (opts && opts->plain) return sv_apply_plain(amps, c, branch, layer_begin, layer_end, stream);
     TileShape sh;
-    if ((st = resolve_shape(c, opts, sh)) != QSV_OK) return st;
+    if ((st = resolve_shape(c, opts, sh, layer_begin, layer_end)) != QSV_OK) return st;
     if (sh.R == 0) return sv_apply_plain(amps, c, branch, layer_begin, layer_end, stream);
     if ((st = check_device()) != QSV_OK) return st;
     std::shared_ptr<Plan> plan;
@@ -338,7 +341,7 @@ qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int in
     TileShape sh;
     bool fused = !(opts && opts->plain);
     if (fused) {
-        if ((st = resolve_shape(c, opts, sh)) != QSV_OK) return st;
+        if ((st = resolve_shape(c, opts, sh, layer_begin, layer_end)) != QSV_OK) return st;
         fused = sh.R != 0;
     }
     std::shared_ptr<Plan> plan;
@@ -384,7 +387,7 @@ qsv_status sv_plan_info(const qsv_circuit *c, int layer_begin, int layer_end,
                         size_t pass_cap) {
     if (!c || !n_passes) return fail(QSV_EINVAL, "sv_plan_info: null argument");
     TileShape sh;
-    qsv_status st = resolve_shape(c, opts, sh);
+    qsv_status st = resolve_shape(c, opts, sh, layer_begin, layer_end);
     if (st != QSV_OK) return st;
     if (sh.R == 0) return fail(QSV_EUNSUPPORTED, "sv_plan_info: state too small for a tile");
     std::shared_ptr<Plan> plan;

@@ -118,6 +118,9 @@ qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Pla
 TileShape default_shape(int n);
 void gates_in_range(const qsv_circuit &c, int lb, int le, std::vector<int> &idx);
 
+// tune.cpp: the shape sv_tune picked for this circuit and layer range, if any
+bool tuned_opts(const qsv_circuit *c, int lb, int le, qsv_fuse_opts *out);
+
 // emulate.cpp
 void emulate_pass(const PassProg &p, int n, int R, int T, uint64_t branch, float *amps);
 

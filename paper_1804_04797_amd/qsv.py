@@ -29,7 +29,7 @@ EXPORTS = ["circuit_create", "circuit_destroy", "circuit_info", "circuit_gates",
            "circuit_split", "sv_init", "sv_apply_fused", "sv_apply_plain", "sv_amplitudes",
            "sv_norm_fp64", "sv_branch_combine", "sv_simulate", "sv_batch_create", "sv_batch_run",
            "sv_batch_destroy", "sv_plan_info", "sv_debug_emulate", "sv_debug_jit_compile",
-           "qsv_last_error", "qsv_version"]
+           "sv_tune", "qsv_last_error", "qsv_version"]
 
 
 class QsvError(RuntimeError):
@@ -75,6 +75,7 @@ def lib():
         "sv_plan_info": (st, [vp, i32, i32, vp, P(i32), vp, vp, sz, vp, sz]),
         "sv_debug_emulate": (st, [vp, vp, u64, i32, i32, vp]),
         "sv_debug_jit_compile": (st, [vp, i32, i32, vp, P(sz), P(ctypes.c_double)]),
+        "sv_tune": (st, [vp, vp, i32, i32, vp, P(ctypes.c_double), vp]),
         "qsv_last_error": (ctypes.c_char_p, []),
         "qsv_version": (ctypes.c_char_p, []),
     }
@@ -300,6 +301,16 @@ def sv_debug_jit_compile(c, layer_begin=0, layer_end=-1, opts=None):
     _check(lib().sv_debug_jit_compile(c, layer_begin, layer_end, _opts(opts), ctypes.byref(nb),
                                       ctypes.byref(sec)))
     return nb.value, sec.value
+
+
+def sv_tune(amps_scratch, c, layer_begin=0, layer_end=-1, stream=None):
+    """Autotune the tile shape; returns (opts dict, best ms)."""
+    o = FuseOpts()
+    ms = ctypes.c_double()
+    _check(lib().sv_tune(_ptr(amps_scratch), c, layer_begin, layer_end, ctypes.byref(o),
+                         ctypes.byref(ms), _stream(stream)))
+    return ({"reg_qubits": o.reg_qubits, "thread_qubits": o.thread_qubits,
+             "low_qubits": o.low_qubits, "plain": 0, "jit": 0}, ms.value)
 
 
 def version() -> str:

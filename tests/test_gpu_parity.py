@@ -582,3 +582,21 @@ def test_split_7x7_d16_branch_norm_identity():
         assert abs(nrm.item() - 1) <= 1e-5
     del a
     torch.cuda.empty_cache()
+
+
+def test_autotune_then_default_calls_use_it():
+    """sv_tune picks a tile shape by timing candidates; later calls with
+    opts=None use it (same plan as passing it explicitly) and stay exact."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("4x5-d10")
+    n = lat.n
+    a = torch.empty(1 << n, dtype=torch.complex64, device=DEV)
+    opts, ms = qsv.sv_tune(a, c, layer_begin=1)
+    assert ms > 0
+    assert (opts["reg_qubits"], opts["thread_qubits"]) in {(5, 8), (4, 8), (5, 9), (6, 8), (5, 7),
+                                                           (4, 7)}
+    assert qsv.sv_plan_info(c, layer_begin=1)["n_passes"] == \
+        qsv.sv_plan_info(c, layer_begin=1, opts=opts)["n_passes"]
+    ref = sim.simulate(_oracle_gates(c), n)
+    qsv.sv_simulate(a, c, init_kind=qsv.INIT_PLUS, layer_begin=1)
+    _check_full(a, ref, n)
