@@ -199,6 +199,20 @@ qsv_status sv_apply_plain(void *amps, const qsv_circuit *c, uint64_t branch,
                           int layer_begin, int layer_end, void *stream);
 
 /*
+ * sv_apply_dense - apply layers [layer_begin, layer_end) as dense blocks on
+ * matrix cores.  The gates are grouped into blocks that each act on k qubits
+ * (k = 4, 5 or 6); every block's 2^k x 2^k complex matrix is formed in FP64
+ * on the host (product of its gate matrices, rounded to complex64) and
+ * applied to the state in one full pass with FP32 MFMA (Y = M X, X = the
+ * columns of 2^k amplitudes that share all other index bits).  This is gate
+ * fusion in the sense of the qHiPSTER comparison of Section 2.4: cost
+ * 8 * 2^k real flops per amplitude per block.  *n_blocks (may be NULL)
+ * receives the number of blocks.  Requires n >= k + 6.
+ */
+qsv_status sv_apply_dense(void *amps, const qsv_circuit *c, uint64_t branch, int layer_begin,
+                          int layer_end, int k, int *n_blocks, void *stream);
+
+/*
  * sv_amplitudes - gather alpha_x for m bitstrings (Task 2 of Section 1).
  * bitstrings_dev: device uint64[m]; out_dev: device complex64[m]
  * (out_c128 = 0) or complex128[m] (out_c128 = 1).  A bitstring >= 2^n makes
@@ -284,6 +298,14 @@ qsv_status sv_plan_info(const qsv_circuit *c, int layer_begin, int layer_end,
  */
 qsv_status sv_debug_emulate(void *amps_host, const qsv_circuit *c, uint64_t branch,
                             int layer_begin, int layer_end, const qsv_fuse_opts *opts);
+
+/*
+ * sv_debug_emulate_dense - apply the dense blocks of sv_apply_dense on the
+ * host to a complex64[2^n] host array (n <= 24).  A block-construction check
+ * for CPU-only test runs; no product entry point calls it.
+ */
+qsv_status sv_debug_emulate_dense(void *amps_host, const qsv_circuit *c, uint64_t branch,
+                                  int layer_begin, int layer_end, int k, int *n_blocks);
 
 /*
  * sv_debug_jit_compile - generate and compile (no load, no device needed) the

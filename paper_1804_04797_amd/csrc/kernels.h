@@ -15,6 +15,8 @@ hipError_t launch_fused_batch(int R, int T, const BatchSeg *segs, int nseg, cons
                               hipStream_t s);
 hipError_t launch_gather_batch(const BatchEntry *ents, uint64_t count, const uint64_t *xs,
                                uint64_t m, float2 *out, hipStream_t s);
+hipError_t launch_dense(float2 *amps, int n, int k, const int *qubits, const float *mat_t,
+                        hipStream_t s);
 hipError_t launch_plain_1q(float2 *amps, int n, int q, const float m[8], hipStream_t s);
 hipError_t launch_plain_phase(float2 *amps, int n, int q, float cr, float ci, hipStream_t s);
 hipError_t launch_plain_cz(float2 *amps, int n, int q0, int q1, hipStream_t s);

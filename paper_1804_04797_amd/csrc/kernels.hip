@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 
 #include "kernels.h"
 
@@ -352,6 +353,158 @@ k_gather_batch(const BatchEntry *__restrict__ ents, uint64_t count, const uint64
     out[i] = (x < (1ull << en.n)) ? a[x] : f2(__builtin_nanf(""), __builtin_nanf(""));
 }
 
+
+// ---------------------------------------------------------------------------
+// Dense block on matrix cores: Y = M X for a 2^K x 2^K complex matrix M on K
+// qubits.  A tile is 2^K rows (the block's qubits) x 64 columns (the six
+// lowest other index bits); the remaining bits select the tile.  Persistent
+// workgroups keep M^T (re, im) in LDS and loop over tiles: load the tile into
+// LDS as separate re/im planes, form Yr = Mr Xr - Mi Xi and Yi = Mr Xi + Mi Xr
+// with v_mfma_f32_16x16x4_f32 (four real products; wave w owns 16-row output
+// blocks), write Y back through LDS and store it in place.
+// ---------------------------------------------------------------------------
+struct DenseArgs {
+    uint64_t tiles;
+    uint8_t glob_bits[48];     // tile index bit i -> physical bit
+    uint8_t phys[16];          // tile local bit i -> physical bit
+    uint8_t sub[16];           // position of local bit i within the row or column index
+    uint16_t rowmask;          // local bits that belong to the row index
+    int32_t n_glob;
+};
+
+template <int K>
+__global__ void __launch_bounds__(256)
+k_dense(float2 *__restrict__ amps, const float *__restrict__ mat_t, const DenseArgs A) {
+    constexpr int DIM = 1 << K;
+    constexpr int COLS = 64;
+    constexpr int XS = COLS + 4;             // padded row stride of the X planes
+    constexpr int PER = (DIM * COLS) / 256;  // elements per thread
+    constexpr int NB = DIM / 16;             // 16x16 output blocks per wave
+    __shared__ float mtr[DIM * DIM], mti[DIM * DIM];
+    __shared__ float xr[DIM * XS], xi[DIM * XS];
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+    for (uint32_t i = t; i < uint32_t(DIM * DIM); i += 256) {
+        mtr[i] = mat_t[i];
+        mti[i] = mat_t[DIM * DIM + i];
+    }
+    // thread part of the tile-local index: bits 0..7
+    uint64_t poff_t = 0;
+    uint32_t row_t = 0, col_t = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        if (!((t >> b) & 1u)) continue;
+        poff_t |= 1ull << A.phys[b];
+        if ((A.rowmask >> b) & 1u) row_t |= 1u << A.sub[b];
+        else col_t |= 1u << A.sub[b];
+    }
+    const uint32_t rb0 = (w * NB) / 4;       // row block of this wave
+    const uint32_t cb0 = (w * NB) % 4;       // first column block
+    for (uint64_t tile = blockIdx.x; tile < A.tiles; tile += gridDim.x) {
+        uint64_t base = 0;
+        for (int i = 0; i < A.n_glob; ++i) base |= ((tile >> i) & 1ull) << A.glob_bits[i];
+        __syncthreads();  // previous tile's LDS reads are complete
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            uint64_t poff = poff_t;
+            uint32_t row = row_t, col = col_t;
+#pragma unroll
+            for (int b = 8; b < K + 6; ++b) {
+                if (!((it >> (b - 8)) & 1)) continue;
+                poff |= 1ull << A.phys[b];
+                if ((A.rowmask >> b) & 1u) row |= 1u << A.sub[b];
+                else col |= 1u << A.sub[b];
+            }
+            const float2 v = amps[base | poff];
+            xr[row * XS + col] = v.x;
+            xi[row * XS + col] = v.y;
+        }
+        __syncthreads();
+        v4f ar[NB], ai[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) { ar[b] = v4f{0, 0, 0, 0}; ai[b] = v4f{0, 0, 0, 0}; }
+        const uint32_t lr = lane & 15u, lk = lane >> 4;
+#pragma unroll 4
+        for (int kk = 0; kk < DIM; kk += 4) {
+            const float a_r = mtr[(kk + lk) * DIM + rb0 * 16 + lr];
+            const float a_i = mti[(kk + lk) * DIM + rb0 * 16 + lr];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const uint32_t cb = cb0 + b;
+                const float b_r = xr[(kk + lk) * XS + cb * 16 + lr];
+                const float b_i = xi[(kk + lk) * XS + cb * 16 + lr];
+                ar[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_r, b_r, ar[b], 0, 0, 0);
+                ar[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a_i, b_i, ar[b], 0, 0, 0);
+                ai[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_r, b_i, ai[b], 0, 0, 0);
+                ai[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_i, b_r, ai[b], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // all waves are done reading X
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const uint32_t cb = cb0 + b;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t row = rb0 * 16 + 4 * lk + r, col = cb * 16 + lr;
+                xr[row * XS + col] = ar[b][r];
+                xi[row * XS + col] = ai[b][r];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            uint64_t poff = poff_t;
+            uint32_t row = row_t, col = col_t;
+#pragma unroll
+            for (int b = 8; b < K + 6; ++b) {
+                if (!((it >> (b - 8)) & 1)) continue;
+                poff |= 1ull << A.phys[b];
+                if ((A.rowmask >> b) & 1u) row |= 1u << A.sub[b];
+                else col |= 1u << A.sub[b];
+            }
+            amps[base | poff] = f2(xr[row * XS + col], xi[row * XS + col]);
+        }
+    }
+}
+
+template <int K>
+hipError_t launch_dense_t(float2 *amps, int n, const int *qubits, const float *mat_t,
+                          hipStream_t s) {
+    DenseArgs A;
+    std::memset(&A, 0, sizeof(A));
+    uint64_t qmask = 0;
+    for (int i = 0; i < K; ++i) qmask |= 1ull << qubits[i];
+    // column bits: the six lowest bits outside the block
+    uint64_t cmask = 0;
+    for (int q = 0, c = 0; q < n && c < 6; ++q)
+        if (!((qmask >> q) & 1)) { cmask |= 1ull << q; ++c; }
+    const uint64_t res = qmask | cmask;
+    int li = 0, ri = 0, ci = 0;
+    for (int q = 0; q < n; ++q) {
+        if (!((res >> q) & 1)) continue;
+        A.phys[li] = uint8_t(q);
+        if ((qmask >> q) & 1) {
+            A.rowmask |= uint16_t(1u << li);
+            // row index bit = position of q in the block's qubit list
+            int pos = 0;
+            while (qubits[pos] != q) ++pos;
+            A.sub[li] = uint8_t(pos);
+            ++ri;
+        } else {
+            A.sub[li] = uint8_t(ci++);
+        }
+        ++li;
+    }
+    int g = 0;
+    for (int q = 0; q < n; ++q)
+        if (!((res >> q) & 1)) A.glob_bits[g++] = uint8_t(q);
+    A.n_glob = g;
+    A.tiles = 1ull << (n - K - 6);
+    (void)ri;
+    const uint64_t grid = A.tiles < 1024 ? A.tiles : 1024;
+    hipLaunchKernelGGL((k_dense<K>), dim3(unsigned(grid)), dim3(256), 0, s, amps, mat_t, A);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Plain (unfused) gate kernels: one launch per gate.
 // ---------------------------------------------------------------------------
@@ -607,6 +760,16 @@ hipError_t launch_gather_batch(const BatchEntry *ents, uint64_t count, const uin
     hipLaunchKernelGGL(k_gather_batch, dim3(unsigned((count * m + 255) / 256)), dim3(256), 0, s,
                        ents, count, xs, m, out);
     return hipGetLastError();
+}
+
+hipError_t launch_dense(float2 *amps, int n, int k, const int *qubits, const float *mat_t,
+                        hipStream_t s) {
+    switch (k) {
+    case 4: return launch_dense_t<4>(amps, n, qubits, mat_t, s);
+    case 5: return launch_dense_t<5>(amps, n, qubits, mat_t, s);
+    case 6: return launch_dense_t<6>(amps, n, qubits, mat_t, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 bool fused_shape_supported(int R, int T) {

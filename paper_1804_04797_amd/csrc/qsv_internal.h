@@ -83,6 +83,28 @@ struct PlanKey {
     }
 };
 
+// Dense-block plan (dense.cpp): every block is a 2^k x 2^k complex matrix
+// on k qubits (local bit i = qubits[i]).
+struct DenseBlock {
+    std::vector<int> qubits;
+    std::vector<float> re, im;      // row-major M
+    std::vector<float> re_t, im_t;  // row-major M^T (device layout)
+    std::vector<int> gates;
+};
+struct DensePlan {
+    int n = 0, k = 0;
+    std::vector<DenseBlock> blocks;
+    float *d_mats = nullptr;        // device copy, kept for the life of the process
+    std::mutex mu;
+};
+struct DenseKey {
+    int lb, le, k;
+    uint64_t branch;
+    bool operator<(const DenseKey &o) const {
+        return std::tie(lb, le, k, branch) < std::tie(o.lb, o.le, o.k, o.branch);
+    }
+};
+
 struct Plan {
     int n = 0, R = 0, T = 0, c = 0;
     std::vector<Pass> passes;
@@ -99,6 +121,7 @@ struct qsv_circuit {
     std::vector<qsv_gate> gates;
     std::mutex mu;
     std::map<qsv::PlanKey, std::shared_ptr<qsv::Plan>> plans;
+    std::map<qsv::DenseKey, std::shared_ptr<qsv::DensePlan>> dense;
 };
 
 namespace qsv {
@@ -120,6 +143,10 @@ void gates_in_range(const qsv_circuit &c, int lb, int le, std::vector<int> &idx)
 
 // tune.cpp: the shape sv_tune picked for this circuit and layer range, if any
 bool tuned_opts(const qsv_circuit *c, int lb, int le, qsv_fuse_opts *out);
+
+// dense.cpp
+qsv_status build_dense_plan(const qsv_circuit &c, int lb, int le, int k, uint64_t branch,
+                            DensePlan &out);
 
 // emulate.cpp
 void emulate_pass(const PassProg &p, int n, int R, int T, uint64_t branch, float *amps);

@@ -29,7 +29,7 @@ EXPORTS = ["circuit_create", "circuit_destroy", "circuit_info", "circuit_gates",
            "circuit_split", "sv_init", "sv_apply_fused", "sv_apply_plain", "sv_amplitudes",
            "sv_norm_fp64", "sv_branch_combine", "sv_simulate", "sv_batch_create", "sv_batch_run",
            "sv_batch_destroy", "sv_plan_info", "sv_debug_emulate", "sv_debug_jit_compile",
-           "sv_tune", "qsv_last_error", "qsv_version"]
+           "sv_tune", "sv_apply_dense", "sv_debug_emulate_dense", "qsv_last_error", "qsv_version"]
 
 
 class QsvError(RuntimeError):
@@ -76,6 +76,8 @@ def lib():
         "sv_debug_emulate": (st, [vp, vp, u64, i32, i32, vp]),
         "sv_debug_jit_compile": (st, [vp, i32, i32, vp, P(sz), P(ctypes.c_double)]),
         "sv_tune": (st, [vp, vp, i32, i32, vp, P(ctypes.c_double), vp]),
+        "sv_apply_dense": (st, [vp, vp, u64, i32, i32, i32, P(i32), vp]),
+        "sv_debug_emulate_dense": (st, [vp, vp, u64, i32, i32, i32, P(i32)]),
         "qsv_last_error": (ctypes.c_char_p, []),
         "qsv_version": (ctypes.c_char_p, []),
     }
@@ -311,6 +313,21 @@ def sv_tune(amps_scratch, c, layer_begin=0, layer_end=-1, stream=None):
                          ctypes.byref(ms), _stream(stream)))
     return ({"reg_qubits": o.reg_qubits, "thread_qubits": o.thread_qubits,
              "low_qubits": o.low_qubits, "plain": 0, "jit": 0}, ms.value)
+
+
+def sv_apply_dense(amps, c, k, branch=0, layer_begin=0, layer_end=-1, stream=None):
+    nb = ctypes.c_int()
+    _check(lib().sv_apply_dense(_ptr(amps), c, ctypes.c_uint64(branch), layer_begin, layer_end, k,
+                                ctypes.byref(nb), _stream(stream)))
+    return nb.value
+
+
+def sv_debug_emulate_dense(amps_host, c, k, branch=0, layer_begin=0, layer_end=-1):
+    assert amps_host.dtype == np.complex64 and amps_host.flags.c_contiguous
+    nb = ctypes.c_int()
+    _check(lib().sv_debug_emulate_dense(_ptr(amps_host), c, ctypes.c_uint64(branch), layer_begin,
+                                        layer_end, k, ctypes.byref(nb)))
+    return nb.value
 
 
 def version() -> str:

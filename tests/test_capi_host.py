@@ -248,3 +248,28 @@ def test_emulated_split_branches():
     total *= sign
     ref = sim.simulate(OC.random_circuit(OC.Lattice(rows, cols), depth, seed), n)
     assert np.max(np.abs(total - ref)) < 1e-5
+
+
+@pytest.mark.parametrize("k", [4, 5, 6])
+def test_dense_blocks_emulated_match_oracle(k):
+    """Dense-block plan (FP64 block matrices rounded to complex64) applied on
+    the host reproduces the oracle state."""
+    spec = workloads.WORKLOADS["4x5-d10"]
+    c = qsv.circuit_create(spec["rows"], spec["cols"], None, spec["depth"], spec["seed"])
+    psi = np.zeros(1 << 20, np.complex64)
+    psi[0] = 1
+    nb = qsv.sv_debug_emulate_dense(psi, c, k)
+    assert 1 <= nb <= len(c.gates())
+    ref = sim.simulate(_to_oracle(c.gates()), 20)
+    assert np.max(np.abs(psi - ref)) < 1e-5
+
+
+def test_dense_blocks_all_gate_kinds():
+    n = 12
+    g = _random_explicit(n, 200, 17)
+    c = qsv.circuit_create(3, 4, None, gates=g)
+    psi = np.zeros(1 << n, np.complex64)
+    psi[0] = 1
+    qsv.sv_debug_emulate_dense(psi, c, 5)
+    ref = sim.simulate(_to_oracle(c.gates()), n)
+    assert np.max(np.abs(psi - ref)) < 1e-5

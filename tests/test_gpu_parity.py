@@ -600,3 +600,57 @@ def test_autotune_then_default_calls_use_it():
     ref = sim.simulate(_oracle_gates(c), n)
     qsv.sv_simulate(a, c, init_kind=qsv.INIT_PLUS, layer_begin=1)
     _check_full(a, ref, n)
+
+
+@pytest.mark.parametrize("k", [4, 5, 6])
+def test_dense_mfma_4x5(k):
+    """Dense blocks on matrix cores (FP32 MFMA) against the oracle state."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("4x5-d10")
+    ref = sim.simulate(_oracle_gates(c), lat.n)
+    a = _state(lat.n)
+    nb = qsv.sv_apply_dense(a, c, k)
+    assert nb >= 1
+    _check_full(a, ref, lat.n)
+    # same blocks emulated on the host
+    h = np.zeros(1 << lat.n, np.complex64)
+    h[0] = 1
+    qsv.sv_debug_emulate_dense(h, c, k)
+    assert np.max(np.abs(a.cpu().numpy() - h)) <= 1e-6
+
+
+def test_dense_mfma_explicit_kinds_and_ranges():
+    _gpu()
+    n = 16
+    rng = np.random.default_rng(21)
+    kinds = ["H", "T", "SX", "SY", "CZ", "TDG", "SXDG", "SYDG", "Z", "P0", "P1"]
+    g = np.zeros(300, qsv.GATE_DTYPE)
+    for i in range(g.size):
+        k = kinds[rng.integers(len(kinds))] if i >= n else "H"
+        q0 = int(rng.integers(n)) if i >= n else i
+        q1 = q0
+        while k == "CZ" and q1 == q0:
+            q1 = int(rng.integers(n))
+        g[i] = (qsv.KIND[k], q0, q1 if k == "CZ" else 0, 0, i // 8, 0)
+    c = qsv.circuit_create(4, 4, None, gates=g)
+    ref = sim.simulate(_oracle_gates(c), n)
+    a = _state(n)
+    qsv.sv_apply_dense(a, c, 6, layer_end=10)
+    qsv.sv_apply_dense(a, c, 5, layer_begin=10)
+    assert np.max(np.abs(a.cpu().numpy() - ref)) <= TOL
+
+
+def test_dense_mfma_full_size_5x6_d20():
+    """30 qubits at full size, k = 6, against the stored oracle amplitudes."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("5x6-d20")
+    xs, ref = _golden("5x6-d20")
+    a = _state(30, qsv.INIT_PLUS)
+    qsv.sv_apply_dense(a, c, 6, layer_begin=1)
+    bits = torch.from_numpy(xs.view(np.int64)).to(DEV)
+    out = torch.empty(xs.size, dtype=torch.complex128, device=DEV)
+    qsv.sv_amplitudes(a, 30, bits, out, c128=True)
+    d = np.max(np.abs(out.cpu().numpy() - ref))
+    assert d <= TOL and d * 2 ** 15 <= TOL_SCALED, d
+    del a
+    torch.cuda.empty_cache()
