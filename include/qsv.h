@@ -190,6 +190,18 @@ qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int in
                        void *amps_out_dev, int out_c128, void *stream);
 
 /*
+ * sv_simulate_c128 - the same sweep on a complex128 state (device
+ * complex128[2^n], 16 bytes per amplitude): the compiled pass kernels
+ * instantiated in FP64.  A precision reference for the complex64 path, not a
+ * fast path; tile shape fixed at 4 register x 8 thread qubits.  Output
+ * amplitudes are complex128[m]; norm_out_dev may be NULL.  Needs 12 <= n <= 34.
+ */
+qsv_status sv_simulate_c128(void *amps, const qsv_circuit *c, uint64_t branch, int init_kind,
+                            uint64_t basis, int layer_begin, int layer_end, double *norm_out_dev,
+                            const uint64_t *bitstrings_dev, size_t m, void *amps_out_dev,
+                            void *stream);
+
+/*
  * sv_apply_plain - the unfused comparator: one full-state (or, for diagonal
  * gates, partial) kernel per gate, the gate-by-gate method that Section 2.4
  * and Table "28qubit" measure their speedup against.  Same arguments and

@@ -381,6 +381,46 @@ qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int in
     return QSV_OK;
 }
 
+qsv_status sv_simulate_c128(void *amps, const qsv_circuit *c, uint64_t branch, int init_kind,
+                            uint64_t basis, int layer_begin, int layer_end, double *norm_out_dev,
+                            const uint64_t *bitstrings_dev, size_t m, void *amps_out_dev,
+                            void *stream) {
+    if (!c || !amps) return fail(QSV_EINVAL, "sv_simulate_c128: null argument");
+    if (reinterpret_cast<uintptr_t>(amps) % 16) return fail(QSV_EINVAL, "sv_simulate_c128: misaligned state");
+    if (c->n < 12 || c->n > kMaxQubits) return fail(QSV_EUNSUPPORTED, "sv_simulate_c128: needs 12 <= n <= 34");
+    if (init_kind < 0 || init_kind > 2) return fail(QSV_EINVAL, "sv_simulate_c128: unknown init kind");
+    if (init_kind == QSV_INIT_BASIS && basis >= (1ull << c->n))
+        return fail(QSV_ERANGE, "sv_simulate_c128: basis index >= 2^n");
+    if (init_kind == QSV_INIT_ZERO) basis = 0;
+    if (layer_begin < 0) return fail(QSV_EINVAL, "sv_simulate_c128: layer_begin < 0");
+    if (m && (!bitstrings_dev || !amps_out_dev)) return fail(QSV_EINVAL, "sv_simulate_c128: null gather buffer");
+    qsv_status st = check_device();
+    if (st != QSV_OK) return st;
+    const TileShape sh{4, 8, 4};
+    std::shared_ptr<Plan> plan;
+    if ((st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) return st;
+    if (plan->passes.empty()) return fail(QSV_EUNSUPPORTED, "sv_simulate_c128: empty layer range");
+    const int variant = kJitDouble | kJitInit | init_kind | (norm_out_dev ? kJitNorm : 0);
+    {
+        std::lock_guard<std::mutex> g(plan->jit_mu);
+        if ((st = jit_prepare(*plan, variant)) != QSV_OK) return st;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double *part = nullptr;
+    const uint64_t tiles = 1ull << (c->n - sh.R - sh.T);
+    if (norm_out_dev && (st = norm_partials(tiles, &part)) != QSV_OK) return st;
+    if ((st = jit_launch(*plan, variant, amps, branch, basis, part, s)) != QSV_OK) return st;
+    if (norm_out_dev) {
+        hipError_t e = launch_sum_partials(part, tiles, norm_out_dev, s);
+        if (e != hipSuccess) return hip_fail(e, "sv_simulate_c128");
+    }
+    if (m) {
+        hipError_t e = launch_gather_c128(amps, c->n, bitstrings_dev, m, amps_out_dev, s);
+        if (e != hipSuccess) return hip_fail(e, "sv_simulate_c128");
+    }
+    return QSV_OK;
+}
+
 qsv_status sv_plan_info(const qsv_circuit *c, int layer_begin, int layer_end,
                         const qsv_fuse_opts *opts, int *n_passes, int32_t *pass_of_gate,
                         int32_t *order_in_pass, size_t n_gate_cap, uint64_t *resident_mask,

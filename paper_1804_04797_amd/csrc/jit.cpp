@@ -43,6 +43,18 @@ __device__ __forceinline__ float2 xsign(float2 a, unsigned m) {
     return make_float2(__uint_as_float(__float_as_uint(a.x) ^ m),
                        __uint_as_float(__float_as_uint(a.y) ^ m));
 }
+typedef double v2d __attribute__((ext_vector_type(2)));
+#define D2(x, y) make_double2((x), (y))
+__device__ __forceinline__ double2 cmd(double2 a, double cr, double ci) {
+    return make_double2(a.x * cr - a.y * ci, a.x * ci + a.y * cr);
+}
+__constant__ double QWD[16] = {1.0, 0.70710678118654752440, 0.0, -0.70710678118654752440,
+                               -1.0, -0.70710678118654752440, 0.0, 0.70710678118654752440,
+                               0.0, 0.70710678118654752440, 1.0, 0.70710678118654752440,
+                               0.0, -0.70710678118654752440, -1.0, -0.70710678118654752440};
+__device__ __forceinline__ double2 xsignd(double2 a, unsigned m) {
+    return m ? make_double2(-a.x, -a.y) : a;
+}
 )";
 
 std::string hex64(uint64_t v) {
@@ -54,6 +66,12 @@ std::string hex64(uint64_t v) {
 std::string flt(double v) {
     char b[48];
     std::snprintf(b, sizeof b, "%.9ef", v);
+    return b;
+}
+
+std::string dbl(double v) {
+    char b[48];
+    std::snprintf(b, sizeof b, "%.17e", v);
     return b;
 }
 
@@ -96,9 +114,20 @@ struct Gen {
     std::ostringstream o;
     int m[64];            // pending rotation i^m of each register
     bool e_dirty = false; // e or the zero flag may differ from (0, alive)
-    Gen(const PassProg &p, int r, int t) : P(p), R(r), T(t), N(1 << r), L(r + t) {
+    bool dp;              // complex128 state (validation instantiation)
+    std::string CT, RT, MK, CM, XS, QT, ZERO;
+    Gen(const PassProg &p, int r, int t, bool double_precision = false)
+        : P(p), R(r), T(t), N(1 << r), L(r + t), dp(double_precision) {
         for (int j = 0; j < 64; ++j) m[j] = 0;
+        CT = dp ? "double2" : "float2";
+        RT = dp ? "double" : "float";
+        MK = dp ? "D2" : "F2";
+        CM = dp ? "cmd" : "cm";
+        XS = dp ? "xsignd" : "xsign";
+        QT = dp ? "QWD" : "QW";
+        ZERO = dp ? "0.0" : "0.f";
     }
+    std::string lit(double v) const { return dp ? dbl(v) : flt(v); }
 
     bool is_reg(uint32_t loc) const { return loc < uint32_t(R); }
     bool is_glob(uint32_t loc) const { return loc & 0x80u; }
@@ -119,10 +148,10 @@ struct Gen {
         return b;
     }
     // i^a * X + i^b * Y
-    static std::string sum(int a, int b) {
+    std::string sum(int a, int b) const {
         std::string re = term("x", a, 0) + term("y", b, 0);
         std::string im = term("x", a, 1) + term("y", b, 1);
-        return "F2(" + re + "," + im + ")";
+        return MK + "(" + re + "," + im + ")";
     }
 
     void butterfly(uint32_t code, int S) {
@@ -139,15 +168,15 @@ struct Gen {
             case OP_SXDG: b0 = d + 1; a1 = 1; break;            // x+iy, ix+y
             case OP_SYDG: a1 = 2; break;                        // x+y, -x+y
             }
-            o << "{const float2 x=v[" << j << "],y=v[" << k << "];v[" << j << "]=" << sum(a0, b0)
+            o << "{const " << CT << " x=v[" << j << "],y=v[" << k << "];v[" << j << "]=" << sum(a0, b0)
               << ";v[" << k << "]=" << sum(a1, b1) << ";}\n";
             m[k] = m[j];
         }
     }
     void rot_reg(int j, int k) { m[j] = (m[j] + k / 2) & 3; }
     void omega_reg(int j) {  // multiply the stored value by w = (1 + i)/sqrt2
-        o << "v[" << j << "]=F2((v[" << j << "].x-v[" << j << "].y)*" << flt(std::sqrt(0.5)) << ",(v["
-          << j << "].x+v[" << j << "].y)*" << flt(std::sqrt(0.5)) << ");\n";
+        o << "v[" << j << "]=" << MK << "((v[" << j << "].x-v[" << j << "].y)*" << lit(std::sqrt(0.5))
+          << ",(v[" << j << "].x+v[" << j << "].y)*" << lit(std::sqrt(0.5)) << ");\n";
     }
     void phase_reg(int j, int k) {
         k &= 7;
@@ -155,7 +184,7 @@ struct Gen {
         if (k & 1) omega_reg(j);
     }
     void zero_reg(int j) {
-        o << "v[" << j << "]=F2(0.f,0.f);\n";
+        o << "v[" << j << "]=" << MK << "(" << ZERO << "," << ZERO << ");\n";
         m[j] = 0;
     }
 
@@ -179,7 +208,7 @@ struct Gen {
         if (is_reg(a)) {
             o << "{const unsigned msk = " << pred(b) << " << 31;\n";
             for (int j = 0; j < N; ++j)
-                if (j & (1 << a)) o << "v[" << j << "]=xsign(v[" << j << "],msk);\n";
+                if (j & (1 << a)) o << "v[" << j << "]=" << XS << "(v[" << j << "],msk);\n";
             o << "}\n";
             return;
         }
@@ -201,10 +230,10 @@ struct Gen {
             // branch-dependent: both arms leave the surviving registers' m unchanged
             o << "if (" << l << ") {\n";
             for (int j = 0; j < N; ++j)
-                if (!(j & (1 << loc))) o << "v[" << j << "]=F2(0.f,0.f);\n";
+                if (!(j & (1 << loc))) o << "v[" << j << "]=" << MK << "(" << ZERO << "," << ZERO << ");\n";
             o << "} else {\n";
             for (int j = 0; j < N; ++j)
-                if (j & (1 << loc)) o << "v[" << j << "]=F2(0.f,0.f);\n";
+                if (j & (1 << loc)) o << "v[" << j << "]=" << MK << "(" << ZERO << "," << ZERO << ");\n";
             o << "}\n";
             std::copy(save, save + 64, m);
             return;
@@ -217,7 +246,7 @@ struct Gen {
         if (is_reg(loc)) {
             o << "{const unsigned msk = unsigned((branch >> " << b << ") & 1ull) << 31;\n";
             for (int j = 0; j < N; ++j)
-                if (j & (1 << loc)) o << "v[" << j << "]=xsign(v[" << j << "],msk);\n";
+                if (j & (1 << loc)) o << "v[" << j << "]=" << XS << "(v[" << j << "],msk);\n";
             o << "}\n";
             return;
         }
@@ -234,30 +263,32 @@ struct Gen {
                 const int r = m[j] & 3;
                 if (unit) {
                     if (r == 0) continue;
-                    o << "{const float2 x=v[" << j << "];v[" << j << "]=F2(" << term("x", r, 0) << ","
-                      << term("x", r, 1) << ");}\n";
+                    o << "{const " << CT << " x=v[" << j << "];v[" << j << "]=" << MK << "("
+                      << term("x", r, 0) << "," << term("x", r, 1) << ");}\n";
                 } else if (si == 0.0) {
                     // real scale: (+-s x or +-s y) per component
-                    o << "{const float2 x=v[" << j << "];v[" << j << "]=F2((" << term("x", r, 0) << ")*"
-                      << flt(sr) << ",(" << term("x", r, 1) << ")*" << flt(sr) << ");}\n";
+                    o << "{const " << CT << " x=v[" << j << "];v[" << j << "]=" << MK << "(("
+                      << term("x", r, 0) << ")*" << lit(sr) << ",(" << term("x", r, 1) << ")*" << lit(sr)
+                      << ");}\n";
                 } else {
                     // rotate the constant instead of the value
                     double cr = sr, ci = si;
                     for (int q = 0; q < r; ++q) { double t2 = -ci; ci = cr; cr = t2; }
-                    o << "v[" << j << "]=cm(v[" << j << "]," << flt(cr) << "," << flt(ci) << ");\n";
+                    o << "v[" << j << "]=" << CM << "(v[" << j << "]," << lit(cr) << "," << lit(ci) << ");\n";
                 }
                 m[j] = 0;
             }
             return;
         }
-        o << "{const float a0 = alive ? QW[e & 7u] : 0.f, b0 = alive ? QW[8u + (e & 7u)] : 0.f;\n";
-        o << "const float fr = a0 * " << flt(sr) << " - b0 * " << flt(si) << ", fi = a0 * " << flt(si)
-          << " + b0 * " << flt(sr) << ";\n";
+        o << "{const " << RT << " a0 = alive ? " << QT << "[e & 7u] : " << ZERO << ", b0 = alive ? " << QT
+          << "[8u + (e & 7u)] : " << ZERO << ";\n";
+        o << "const " << RT << " fr = a0 * " << lit(sr) << " - b0 * " << lit(si) << ", fi = a0 * "
+          << lit(si) << " + b0 * " << lit(sr) << ";\n";
         for (int j = 0; j < N; ++j) {
             static const char *rr[4] = {"fr", "-fi", "-fr", "fi"};
             static const char *ri[4] = {"fi", "fr", "-fi", "-fr"};
             const int r = m[j] & 3;
-            o << "v[" << j << "]=cm(v[" << j << "]," << rr[r] << "," << ri[r] << ");\n";
+            o << "v[" << j << "]=" << CM << "(v[" << j << "]," << rr[r] << "," << ri[r] << ");\n";
             m[j] = 0;
         }
         o << "e = 0u; alive = 1u;}\n";
@@ -296,26 +327,37 @@ struct Gen {
         std::vector<int> tld, tst;
         for (int u = 0; u < T; ++u) { tld.push_back(P.ld_phys[R + u]); tst.push_back(P.st_phys[R + u]); }
         o << "extern \"C\" __global__ void __launch_bounds__(" << (1 << T) << ") " << name
-          << "(float2* __restrict__ a, unsigned long long branch, unsigned long long tile0, "
+          << "(" << CT << "* __restrict__ a, unsigned long long branch, unsigned long long tile0, "
              "unsigned long long basis, double* __restrict__ part) {\n";
-        if (uses_lds) o << "extern __shared__ float2 lds[];\n";
+        if (uses_lds) o << "extern __shared__ " << CT << " lds[];\n";
         o << "const unsigned t = threadIdx.x;\n(void)basis; (void)part;\n";
         o << "const unsigned long long tile = tile0 + blockIdx.x;\n";
         o << "const unsigned long long base = " << scatter_expr("tile", glob, true) << ";\n";
         o << "unsigned e = 0u, alive = 1u;\n";
         o << "(void)base; (void)branch; (void)e; (void)alive;\n";
         if (uses_lds) o << "const unsigned wt = t * " << ((1 << R) + 1) << "u;\n";
-        o << "float2 v[" << N << "];\n";
+        o << CT << " v[" << N << "];\n";
         if (init_kind == 1) {
-            const std::string val = flt(std::pow(2.0, -0.5 * n));
-            for (int j = 0; j < N; ++j) o << "v[" << j << "]=F2(" << val << ",0.f);\n";
+            const std::string val = lit(std::pow(2.0, -0.5 * n));
+            for (int j = 0; j < N; ++j) o << "v[" << j << "]=" << MK << "(" << val << "," << ZERO << ");\n";
         } else if (init_kind == 0 || init_kind == 2) {
             o << "{const unsigned long long me = base | " << scatter_expr("t", tld, true) << ";\n";
             for (int j = 0; j < N; ++j) {
                 uint64_t roff = 0;
                 for (int s = 0; s < R; ++s)
                     if ((j >> s) & 1) roff |= 1ull << P.ld_phys[s];
-                o << "v[" << j << "]=F2((me | " << hex64(roff) << ") == basis ? 1.f : 0.f, 0.f);\n";
+                o << "v[" << j << "]=" << MK << "((me | " << hex64(roff) << ") == basis ? " << lit(1.0)
+                  << " : " << ZERO << ", " << ZERO << ");\n";
+            }
+            o << "}\n";
+        } else if (dp) {
+            o << "{const v2d* src = (const v2d*)(a + (base | " << scatter_expr("t", tld, true) << "));\n";
+            for (int j = 0; j < N; ++j) {
+                uint64_t roff = 0;
+                for (int s = 0; s < R; ++s)
+                    if ((j >> s) & 1) roff |= 1ull << P.ld_phys[s];
+                o << "{const v2d w = __builtin_nontemporal_load(src + " << hex64(roff) << ");v[" << j
+                  << "]=D2(w.x,w.y);}\n";
             }
             o << "}\n";
         } else {
@@ -346,6 +388,16 @@ struct Gen {
             }
         }
         if (!scaled) materialize(1.0, 0.0);
+        if (dp) {
+            o << "{v2d* dst = (v2d*)(a + (base | " << scatter_expr("t", tst, true) << "));\n";
+            for (int j = 0; j < N; ++j) {
+                uint64_t roff = 0;
+                for (int s = 0; s < R; ++s)
+                    if ((j >> s) & 1) roff |= 1ull << P.st_phys[s];
+                o << "{const v2d w = {v[" << j << "].x,v[" << j << "].y};__builtin_nontemporal_store(w, dst + "
+                  << hex64(roff) << ");}\n";
+            }
+        } else {
         o << "{v4f* dst = (v4f*)(a + (base | " << scatter_expr("t", tst, true) << "));\n";
         for (int j = 0; j < N; j += 2) {
             uint64_t roff = 0;
@@ -353,6 +405,7 @@ struct Gen {
                 if ((j >> s) & 1) roff |= 1ull << P.st_phys[s];
             o << "{const v4f w = {v[" << j << "].x,v[" << j << "].y,v[" << j + 1 << "].x,v[" << j + 1
               << "].y};__builtin_nontemporal_store(w, dst + " << hex64(roff / 2) << ");}\n";
+        }
         }
         o << "}\n";
         if (norm) {
@@ -425,15 +478,16 @@ qsv_status compile_source(const std::string &src, std::vector<char> &code, std::
 std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int variant) {
     const int init_kind = (variant & 4) ? (variant & 3) : -1;
     const bool norm = (variant & 8) != 0;
+    const bool dp = (variant & kJitDouble) != 0;
     std::string src = kPrelude;
     for (size_t p = 0; p < plan.passes.size(); ++p) {
-        Gen g(plan.passes[p].prog, plan.R, plan.T);
+        Gen g(plan.passes[p].prog, plan.R, plan.T, dp);
         bool uses_lds = false;
         src += g.emit("qsv_pass_" + std::to_string(p), uses_lds, p == 0 ? init_kind : -1,
                       norm && p + 1 == plan.passes.size(), plan.n);
         if (lds_bytes)
             lds_bytes->push_back(uses_lds ? ((size_t(1) << (plan.R + plan.T)) + (size_t(1) << plan.T)) *
-                                                8
+                                                (dp ? 16 : 8)
                                           : 0);
     }
     return src;
@@ -441,11 +495,14 @@ std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int var
 
 qsv_status jit_compile_only(const Plan &plan, size_t *code_bytes, double *seconds) {
     std::vector<size_t> lds;
-    std::string src = jit_source(plan, &lds, 4 | 1 | 8);
     std::vector<char> code;
     std::string log;
     auto t0 = std::chrono::steady_clock::now();
-    qsv_status st = compile_source(src, code, log);
+    // the complex128 instantiation must compile too
+    qsv_status st = compile_source(jit_source(plan, &lds, kJitDouble | kJitInit | 1 | kJitNorm), code, log);
+    if (st != QSV_OK) return st;
+    std::string src = jit_source(plan, &lds, kJitInit | 1 | kJitNorm);
+    st = compile_source(src, code, log);
     if (st != QSV_OK) return st;
     if (seconds)
         *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -16,6 +16,7 @@ namespace qsv {
 constexpr int kJitPlain = 0;
 constexpr int kJitInit = 4;
 constexpr int kJitNorm = 8;
+constexpr int kJitDouble = 16;  // complex128 state (validation instantiation)
 
 // HIP source of every pass of the plan as kernels qsv_pass_<p>.
 std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int variant);

@@ -24,6 +24,8 @@ hipError_t launch_plain_zero(float2 *amps, int n, int q, int l, hipStream_t s);
 hipError_t launch_init(float2 *amps, int n, int kind, uint64_t basis, hipStream_t s);
 hipError_t launch_gather(const float2 *amps, int n, const uint64_t *xs, uint64_t m, void *out,
                          int c128, hipStream_t s);
+hipError_t launch_gather_c128(const void *amps, int n, const uint64_t *xs, uint64_t m, void *out,
+                              hipStream_t s);
 hipError_t launch_norm(const float2 *amps, int n, double *out, double *partials, hipStream_t s);
 hipError_t launch_sum_partials(const double *part, uint64_t count, double *out, hipStream_t s);
 hipError_t launch_branch_combine(const float2 *A, const float2 *B, uint64_t nb, uint64_t m,

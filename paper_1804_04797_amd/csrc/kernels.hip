@@ -602,6 +602,15 @@ k_gather(const float2 *__restrict__ a, uint64_t dim, const uint64_t *__restrict_
     else reinterpret_cast<float2 *>(out)[k] = v;
 }
 
+__global__ void __launch_bounds__(256)
+k_gather_c128(const double2 *__restrict__ a, uint64_t dim, const uint64_t *__restrict__ xs,
+              uint64_t m, double2 *__restrict__ out) {
+    const uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const uint64_t x = xs[k];
+    out[k] = (x < dim) ? a[x] : make_double2(__builtin_nan(""), __builtin_nan(""));
+}
+
 // Block b sums |a_i|^2 over its contiguous chunk in FP64 (products of FP32
 // values are exact in FP64); fixed thread-then-tree order.
 __global__ void __launch_bounds__(256)
@@ -846,6 +855,14 @@ hipError_t launch_gather(const float2 *amps, int n, const uint64_t *xs, uint64_t
     if (m == 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather, dim3(grid_for(m, 256, 1u << 30)), dim3(256), 0, s, amps,
                        1ull << n, xs, m, out, c128);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_c128(const void *amps, int n, const uint64_t *xs, uint64_t m, void *out,
+                              hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_c128, dim3(grid_for(m, 256, 1u << 30)), dim3(256), 0, s,
+                       static_cast<const double2 *>(amps), 1ull << n, xs, m, static_cast<double2 *>(out));
     return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ STATUS = {0: "QSV_OK", 1: "QSV_EINVAL", 2: "QSV_ERANGE", 3: "QSV_ENOMEM", 4: "QS
 
 EXPORTS = ["circuit_create", "circuit_destroy", "circuit_info", "circuit_gates",
            "circuit_split", "sv_init", "sv_apply_fused", "sv_apply_plain", "sv_amplitudes",
-           "sv_norm_fp64", "sv_branch_combine", "sv_simulate", "sv_batch_create", "sv_batch_run",
+           "sv_norm_fp64", "sv_branch_combine", "sv_simulate", "sv_simulate_c128", "sv_batch_create", "sv_batch_run",
            "sv_batch_destroy", "sv_plan_info", "sv_debug_emulate", "sv_debug_jit_compile",
            "sv_tune", "sv_apply_dense", "sv_debug_emulate_dense", "qsv_last_error", "qsv_version"]
 
@@ -66,6 +66,7 @@ def lib():
         "sv_apply_fused": (st, [vp, vp, u64, i32, i32, vp, vp]),
         "sv_apply_plain": (st, [vp, vp, u64, i32, i32, vp]),
         "sv_simulate": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, vp, sz, vp, i32, vp]),
+        "sv_simulate_c128": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, sz, vp, vp]),
         "sv_amplitudes": (st, [vp, i32, vp, sz, vp, i32, vp]),
         "sv_norm_fp64": (st, [vp, i32, vp, vp]),
         "sv_branch_combine": (st, [vp, vp, sz, sz, vp, vp, vp]),
@@ -219,6 +220,16 @@ def sv_simulate(amps, c, branch=0, init_kind=INIT_ZERO, basis=0, layer_begin=0, 
                              ctypes.c_uint64(basis), layer_begin, layer_end, _opts(opts),
                              _ptr(norm_out), _ptr(bitstrings), m, _ptr(amps_out),
                              1 if c128 else 0, _stream(stream)))
+
+
+def sv_simulate_c128(amps, c, branch=0, init_kind=INIT_ZERO, basis=0, layer_begin=0,
+                     layer_end=-1, norm_out=None, bitstrings=None, amps_out=None, stream=None):
+    m = 0
+    if amps_out is not None:
+        m = amps_out.numel() if hasattr(amps_out, "numel") else len(amps_out)
+    _check(lib().sv_simulate_c128(_ptr(amps), c, ctypes.c_uint64(branch), init_kind,
+                                  ctypes.c_uint64(basis), layer_begin, layer_end, _ptr(norm_out),
+                                  _ptr(bitstrings), m, _ptr(amps_out), _stream(stream)))
 
 
 def sv_apply_plain(amps, c, branch=0, layer_begin=0, layer_end=-1, stream=None):

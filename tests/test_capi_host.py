@@ -273,3 +273,15 @@ def test_dense_blocks_all_gate_kinds():
     qsv.sv_debug_emulate_dense(psi, c, 5)
     ref = sim.simulate(_to_oracle(c.gates()), n)
     assert np.max(np.abs(psi - ref)) < 1e-5
+
+
+@pytest.mark.parametrize("shape", [None, dict(reg_qubits=4, thread_qubits=8, low_qubits=4, plain=0),
+                                   dict(reg_qubits=3, thread_qubits=4, low_qubits=3, plain=0)])
+def test_compiled_pass_source_compiles(shape):
+    """The generated straight-line pass kernels (complex64 and complex128
+    instantiations, with generated initial state and norm epilogue) compile
+    for gfx950 (hipRTC runs without a device)."""
+    spec = workloads.WORKLOADS["4x5-d10"]
+    c = qsv.circuit_create(spec["rows"], spec["cols"], None, spec["depth"], spec["seed"])
+    nbytes, secs = qsv.sv_debug_jit_compile(c, layer_begin=1, opts=shape)
+    assert nbytes > 1000
