@@ -18,11 +18,16 @@
 #include <map>
 #include <vector>
 
+#include "jit.h"
 #include "kernels.h"
 #include "qsv_internal.h"
 
 struct qsv_batch {
     int R = 0, T = 0, c = 0;
+    int jit_mode = 0;  // opts->jit: 1 always, -1 never, 0 for plans shared by >= 8 entries
+    std::vector<std::vector<uint32_t>> group;       // entries of each plan
+    std::vector<char> plan_jit;                     // plan runs as compiled kernels
+    std::vector<qsv::BatchEntry *> d_group_ents;    // per compiled plan: its entries' table
     std::vector<const qsv_circuit *> circs;
     std::vector<uint64_t> branches;
     // built for the layer range of the current run
@@ -53,6 +58,9 @@ qsv_status hipfail(hipError_t e, const char *where) {
 }
 
 void free_tables(qsv_batch *b) {
+    for (auto *p : b->d_group_ents)
+        if (p) hipFree(p);
+    b->d_group_ents.clear();
     if (b->d_progs) hipFree(b->d_progs);
     if (b->d_ents) hipFree(b->d_ents);
     if (b->d_segs) hipFree(b->d_segs);
@@ -96,6 +104,20 @@ qsv_status build_tables(qsv_batch *b, int lb) {
         }
         b->entry_plan[i] = it->second;
     }
+    b->group.assign(b->plans.size(), {});
+    for (size_t i = 0; i < b->circs.size(); ++i) b->group[b->entry_plan[i]].push_back(uint32_t(i));
+    b->plan_jit.assign(b->plans.size(), 0);
+    b->d_group_ents.assign(b->plans.size(), nullptr);
+    for (size_t p = 0; p < b->plans.size(); ++p) {
+        const bool shared = b->group[p].size() >= 8;
+        b->plan_jit[p] = !b->plans[p]->passes.empty() &&
+                         (b->jit_mode > 0 || (b->jit_mode == 0 && shared)) && b->group[p].size() < 65536;
+        if (b->plan_jit[p]) {
+            hipError_t e = hipMalloc(reinterpret_cast<void **>(&b->d_group_ents[p]),
+                                     b->group[p].size() * sizeof(BatchEntry));
+            if (e != hipSuccess) return fail(QSV_ENOMEM, "sv_batch: group entry table");
+        }
+    }
     // program array
     std::vector<PassProg> progs;
     std::vector<uint32_t> prog0(b->plans.size());
@@ -125,6 +147,7 @@ qsv_status build_tables(qsv_batch *b, int lb) {
         b->round_seg_off.push_back(int(segs.size()));
         uint64_t blocks = 0;
         for (size_t i = 0; i < b->circs.size(); ++i) {
+            if (b->plan_jit[b->entry_plan[i]]) continue;  // swept by compiled kernels
             if (b->plans[b->entry_plan[i]]->passes.size() <= r) continue;
             BatchSeg s{};
             s.start = blocks;
@@ -191,6 +214,7 @@ qsv_status sv_batch_create(const qsv_circuit *const *circs, const uint64_t *bran
     if (!ok) return fail(QSV_EUNSUPPORTED, "sv_batch_create: no batch kernel for this tile shape");
     if (b->R + b->T > nmin) return fail(QSV_EUNSUPPORTED, "sv_batch_create: tile larger than a state");
     b->c = (opts && opts->low_qubits) ? opts->low_qubits : std::min(5, b->T + 1);
+    b->jit_mode = opts ? opts->jit : 0;
     b->circs.assign(circs, circs + count);
     b->branches.assign(count, 0);
     if (branch_ids) b->branches.assign(branch_ids, branch_ids + count);
@@ -230,9 +254,26 @@ qsv_status sv_batch_run(qsv_batch *b, void *const *amps_dev, int init_plus,
         if (e != hipSuccess) return hipfail(e, "sv_batch_run");
         e = hipMemcpy(b->d_ents, b->h_ents.data(), count * sizeof(BatchEntry), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hipfail(e, "sv_batch_run: entry upload");
+        const int variant = kJitBatched | (init_plus ? (kJitInit | QSV_INIT_PLUS) : 0);
+        for (size_t p = 0; p < b->plans.size(); ++p) {
+            if (!b->plan_jit[p]) continue;
+            std::vector<BatchEntry> ge;
+            for (uint32_t i : b->group[p]) ge.push_back(b->h_ents[i]);
+            e = hipMemcpy(b->d_group_ents[p], ge.data(), ge.size() * sizeof(BatchEntry),
+                          hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hipfail(e, "sv_batch_run: group entry upload");
+            std::lock_guard<std::mutex> g(b->plans[p]->jit_mu);
+            if ((st = jit_prepare(*b->plans[p], variant)) != QSV_OK) return st;
+        }
         e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hipfail(e, "sv_batch_run: begin capture");
         hipError_t le = hipSuccess;
+        for (size_t p = 0; p < b->plans.size() && le == hipSuccess; ++p) {
+            if (!b->plan_jit[p]) continue;
+            if (jit_launch_batched(*b->plans[p], variant, b->d_group_ents[p],
+                                   unsigned(b->group[p].size()), b->cap) != QSV_OK)
+                le = hipErrorLaunchFailure;
+        }
         for (size_t r = 0; r < b->round_blocks.size() && le == hipSuccess; ++r)
             le = launch_fused_batch(b->R, b->T, b->d_segs + b->round_seg_off[r], b->round_nseg[r],
                                     b->d_ents, b->d_progs, int(r), b->round_blocks[r],

@@ -43,6 +43,13 @@ __device__ __forceinline__ float2 xsign(float2 a, unsigned m) {
     return make_float2(__uint_as_float(__float_as_uint(a.x) ^ m),
                        __uint_as_float(__float_as_uint(a.y) ^ m));
 }
+struct BatchEntryJ {  // layout of the library's batch entry table
+    void *amps;
+    unsigned long long branch;
+    unsigned prog0, n;
+    float init_val;
+    unsigned pad;
+};
 typedef double v2d __attribute__((ext_vector_type(2)));
 #define D2(x, y) make_double2((x), (y))
 __device__ __forceinline__ double2 cmd(double2 a, double cr, double ci) {
@@ -317,8 +324,10 @@ struct Gen {
     // init_kind: -1 = load the state; 0/1/2 = generate |0>, |+>^n or |basis>
     // in registers (first pass of sv_simulate).  norm: accumulate the FP64
     // sum of |amp|^2 of the tile into part[tile] after the store.
+    // batched: the state pointer and branch come from an entry table indexed
+    // by blockIdx.y (all entries share this plan).
     std::string emit(const std::string &name, bool &uses_lds, int init_kind = -1,
-                     bool norm = false, int n = 0) {
+                     bool norm = false, int n = 0, bool batched = false) {
         uses_lds = false;
         for (int pc = 0; pc < P.n_ops; ++pc) {
             if ((P.ops[pc] & 0xff) == OP_XCHG) { uses_lds = true; ++pc; }
@@ -326,9 +335,17 @@ struct Gen {
         std::vector<int> glob(P.glob_bits, P.glob_bits + P.n_glob);
         std::vector<int> tld, tst;
         for (int u = 0; u < T; ++u) { tld.push_back(P.ld_phys[R + u]); tst.push_back(P.st_phys[R + u]); }
-        o << "extern \"C\" __global__ void __launch_bounds__(" << (1 << T) << ") " << name
-          << "(" << CT << "* __restrict__ a, unsigned long long branch, unsigned long long tile0, "
-             "unsigned long long basis, double* __restrict__ part) {\n";
+        o << "extern \"C\" __global__ void __launch_bounds__(" << (1 << T) << ") " << name;
+        if (batched) {
+            o << "(const BatchEntryJ* __restrict__ ents, unsigned long long tile0) {\n";
+            o << "const BatchEntryJ en = ents[blockIdx.y];\n";
+            o << CT << "* __restrict__ a = (" << CT << "*)en.amps;\n";
+            o << "const unsigned long long branch = en.branch, basis = 0ull;\n";
+            o << "double* part = nullptr;\n";
+        } else {
+            o << "(" << CT << "* __restrict__ a, unsigned long long branch, unsigned long long tile0, "
+                 "unsigned long long basis, double* __restrict__ part) {\n";
+        }
         if (uses_lds) o << "extern __shared__ " << CT << " lds[];\n";
         o << "const unsigned t = threadIdx.x;\n(void)basis; (void)part;\n";
         o << "const unsigned long long tile = tile0 + blockIdx.x;\n";
@@ -479,12 +496,13 @@ std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int var
     const int init_kind = (variant & 4) ? (variant & 3) : -1;
     const bool norm = (variant & 8) != 0;
     const bool dp = (variant & kJitDouble) != 0;
+    const bool batched = (variant & kJitBatched) != 0;
     std::string src = kPrelude;
     for (size_t p = 0; p < plan.passes.size(); ++p) {
         Gen g(plan.passes[p].prog, plan.R, plan.T, dp);
         bool uses_lds = false;
         src += g.emit("qsv_pass_" + std::to_string(p), uses_lds, p == 0 ? init_kind : -1,
-                      norm && p + 1 == plan.passes.size(), plan.n);
+                      norm && !batched && p + 1 == plan.passes.size(), plan.n, batched);
         if (lds_bytes)
             lds_bytes->push_back(uses_lds ? ((size_t(1) << (plan.R + plan.T)) + (size_t(1) << plan.T)) *
                                                 (dp ? 16 : 8)
@@ -562,6 +580,29 @@ qsv_status jit_launch(const Plan &plan, int variant, void *amps, uint64_t branch
             double *pt = part;
             void *args[] = {&a, &br, &tt, &bs, &pt};
             hipError_t he = hipModuleLaunchKernel(e.fns[p], unsigned(cnt), 1, 1, 1u << plan.T, 1, 1,
+                                                  unsigned(e.lds[p]), s, args, nullptr);
+            if (he != hipSuccess)
+                return fail(QSV_EHIP, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(he));
+        }
+    }
+    return QSV_OK;
+}
+
+qsv_status jit_launch_batched(const Plan &plan, int variant, const void *ents, unsigned count,
+                              hipStream_t s) {
+    auto vit = plan.jit_variants.find(variant);
+    if (vit == plan.jit_variants.end()) return fail(QSV_EINTERNAL, "jit variant not prepared");
+    const CacheEntry &e = *static_cast<const CacheEntry *>(vit->second.get());
+    const int L = plan.R + plan.T;
+    const uint64_t tiles = 1ull << (plan.n - L);
+    const uint64_t chunk = 1ull << 30;
+    for (size_t p = 0; p < plan.passes.size(); ++p) {
+        for (uint64_t t0 = 0; t0 < tiles; t0 += chunk) {
+            const uint64_t cnt = (tiles - t0 < chunk) ? tiles - t0 : chunk;
+            const void *en = ents;
+            unsigned long long tt = t0;
+            void *args[] = {&en, &tt};
+            hipError_t he = hipModuleLaunchKernel(e.fns[p], unsigned(cnt), count, 1, 1u << plan.T, 1, 1,
                                                   unsigned(e.lds[p]), s, args, nullptr);
             if (he != hipSuccess)
                 return fail(QSV_EHIP, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(he));

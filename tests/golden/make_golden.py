@@ -41,6 +41,39 @@ def main(name="5x6-d20", m=4096, bitstring_seed=workloads.BITSTRING_SEED_BASE + 
     print(out, dt)
 
 
+
+
+def split_branch(name="7x7-d16", after_col=3, branches=(0, 1337), m=1024):
+    """Oracle amplitudes of single branch states of the side-A half of a cut
+    circuit (Fig. 2 split; oracle/sim.py split_circuit), at m sampled local
+    bitstrings.  Output: tests/golden/<name>_A_branch<l>.txt."""
+    spec = workloads.WORKLOADS[name]
+    lat = OC.Lattice(spec["rows"], spec["cols"], workloads.present_grid(spec))
+    gates = OC.random_circuit(lat, spec["depth"], spec["seed"])
+    mask = workloads.column_cut_mask(spec["rows"], spec["cols"], after_col)
+    side_a = [q for q in range(lat.n) if (mask >> q) & 1]
+    info = sim.split_circuit(gates, lat.n, side_a)
+    na = len(info["qa"])
+    c = len(info["cuts"])
+    xs = workloads.bitstrings(na, m, workloads.BITSTRING_SEED_BASE + 40)
+    for br in branches:
+        l = tuple((br >> j) & 1 for j in range(c))
+        ga, _ = info["half"](l)
+        t0 = time.time()
+        psi = sim.simulate(ga, na)
+        dt = time.time() - t0
+        out = os.path.join(HERE, f"{name}_A_branch{br}.txt")
+        with open(out, "w") as f:
+            f.write(f"# workload {name} cut after column {after_col}: side-A half n={na}, "
+                    f"branch {br} of 2^{c}, bitstring_seed={workloads.BITSTRING_SEED_BASE + 40:#x}\n")
+            f.write(f"# oracle complex128 time_s={dt:.1f}\n")
+            for x in xs.tolist():
+                a = psi[x]
+                f.write(f"{x} {a.real:.17g} {a.imag:.17g}\n")
+        print(out, dt)
+
+
 if __name__ == "__main__":
     main("5x6-d20", 4096, workloads.BITSTRING_SEED_BASE + 2)
     main("5x6-d16", 1024, workloads.BITSTRING_SEED_BASE + 6)
+    split_branch("7x7-d16", 3, (0, 1337), 1024)

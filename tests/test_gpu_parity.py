@@ -445,14 +445,17 @@ def _uneven(count, n_range, d_range, seed):
     return out
 
 
+@pytest.mark.parametrize("jit", [0, 1])
 @pytest.mark.parametrize("init_plus", [False, True])
-def test_batch_uneven_circuits(init_plus):
+def test_batch_uneven_circuits(init_plus, jit):
     """Independent circuits of uneven size in one graph launch: every entry's
     full state and its gathered amplitudes against the oracle; the graph is
     replayed with eager work in between and every replay is checked."""
     _gpu()
     items = _uneven(12, (12, 17), (6, 14), 123)
-    b = qsv.sv_batch_create([c for c, _, _ in items])
+    # jit=0: every circuit distinct -> generic kernel; jit=1: compiled kernels per circuit
+    b = qsv.sv_batch_create([c for c, _, _ in items],
+                            opts=dict(reg_qubits=0, thread_qubits=0, low_qubits=0, plain=0, jit=jit))
     states = [torch.empty(1 << n, dtype=torch.complex64, device=DEV) for _, _, n in items]
     m = 64
     xs = np.concatenate([workloads.bitstrings(n, m, 7 + i) for i, (_, _, n) in enumerate(items)])
@@ -498,7 +501,7 @@ def test_batch_split_branches_end_to_end():
     xb = np.array([sim.sub_index(int(x), qb) for x in xs], np.uint64)
     circs = [ha] * nbr + [hb] * nbr
     brs = list(range(nbr)) * 2
-    b = qsv.sv_batch_create(circs, brs)
+    b = qsv.sv_batch_create(circs, brs)  # both halves shared by >= 8 entries: compiled kernels
     states = [torch.empty(1 << len(qa), dtype=torch.complex64, device=DEV) for _ in range(nbr)] + \
              [torch.empty(1 << len(qb), dtype=torch.complex64, device=DEV) for _ in range(nbr)]
     m = xs.size
@@ -535,7 +538,8 @@ def test_batch_split_5x6_d16_full_check():
     m = xs.size
     xa = np.array([sim.sub_index(int(x), qa) for x in xs], np.uint64)
     xb = np.array([sim.sub_index(int(x), qb) for x in xs], np.uint64)
-    b = qsv.sv_batch_create([ha] * nbr + [hb] * nbr, list(range(nbr)) * 2)
+    b = qsv.sv_batch_create([ha] * nbr + [hb] * nbr, list(range(nbr)) * 2,
+                            opts=dict(reg_qubits=0, thread_qubits=0, low_qubits=0, plain=0, jit=-1))
     states = [torch.empty(1 << 15, dtype=torch.complex64, device=DEV) for _ in range(2 * nbr)]
     bits = torch.from_numpy(np.concatenate([xa] * nbr + [xb] * nbr).view(np.int64)).to(DEV)
     table = torch.empty(2 * nbr * m, dtype=torch.complex64, device=DEV)
@@ -679,3 +683,48 @@ def test_c128_sweep_matches_oracle_to_fp64():
     assert np.max(np.abs(out.cpu().numpy() - gref)) <= 1e-12
     del a
     torch.cuda.empty_cache()
+
+
+def _golden_branch(name, br):
+    path = os.path.join(HERE, "golden", f"{name}_A_branch{br}.txt")
+    xs, amps = [], []
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        x, re, im = line.split()
+        xs.append(int(x))
+        amps.append(complex(float(re), float(im)))
+    return np.array(xs, np.uint64), np.array(amps)
+
+
+def test_split_7x7_branches_full_size():
+    """Full-size 49-qubit split (cut after column 3): single branch states of
+    the 28-qubit half against stored oracle amplitudes (compiled kernels and
+    a batch of branches), and branches of the 21-qubit half against the
+    oracle's full half state."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("7x7-d16")
+    mask = workloads.column_cut_mask(7, 7, 3)
+    ha, hb, ceff, folded = qsv.circuit_split(c, mask)
+    a = torch.empty(1 << 28, dtype=torch.complex64, device=DEV)
+    for br in (0, 1337):
+        xs, ref = _golden_branch("7x7-d16", br)
+        bits = torch.from_numpy(xs.view(np.int64)).to(DEV)
+        out = torch.empty(xs.size, dtype=torch.complex128, device=DEV)
+        qsv.sv_simulate(a, ha, branch=br, init_kind=qsv.INIT_ZERO, bitstrings=bits, amps_out=out,
+                        c128=True)
+        d = np.max(np.abs(out.cpu().numpy() - ref))
+        assert d <= TOL and d * 2 ** 14 <= TOL_SCALED, (br, d)
+    del a
+    torch.cuda.empty_cache()
+    # 21-qubit half, a few branches, full state against the oracle
+    gates = OC.random_circuit(OC.Lattice(7, 7), spec["depth"], spec["seed"])
+    side_a = [q for q in range(49) if (mask >> q) & 1]
+    info = sim.split_circuit(gates, 49, side_a)
+    bst = torch.empty(1 << 21, dtype=torch.complex64, device=DEV)
+    for br in (0, 5, 2047):
+        l = tuple((br >> j) & 1 for j in range(ceff))
+        _, gb = info["half"](l)
+        ref = sim.simulate(gb, 21)
+        qsv.sv_simulate(bst, hb, branch=br, init_kind=qsv.INIT_ZERO)
+        _check_full(bst, ref, 21)
