@@ -105,27 +105,35 @@ std::string scatter_expr(const std::string &src, const std::vector<int> &target,
 
 // Code generator for one pass.
 //
-// Besides turning every op into literal code, the generator keeps two kinds
-// of phase factors out of the per-amplitude arithmetic:
-//  - a compile-time rotation i^m per register: even phases (Z, S, CZ between
-//    register qubits) only change m, and butterflies absorb m by choosing
-//    which components they add or subtract;
-//  - a per-thread run-time exponent e of w = e^{i pi/4} and a zero flag:
-//    diagonal gates whose qubits are thread or tile-index bits multiply every
-//    amplitude of a thread by the same factor, so they only update e.
-// Both are applied (one complex multiply per amplitude) before an LDS
-// exchange and together with the pass scale before the store.
+// Besides turning every op into literal code, the generator keeps factors
+// that multiply whole registers out of the per-amplitude arithmetic:
+//  - per register, at compile time, a rotation i^m and a power 2^{-h/2}:
+//    even phases (Z, S, CZ between register qubits) only change m; T on a
+//    register qubit multiplies by (1 + i) and adds one to h; butterflies
+//    absorb both by choosing signs, components and an FMA coefficient;
+//  - per register slot s, at run time, a sign sg<s> = +-1 of the registers
+//    whose bit s is set: CZ between a register qubit and a thread or
+//    tile-index qubit only flips sg<s>, and the next butterfly on slot s uses
+//    it as its FMA coefficient;
+//  - per thread, at run time, an exponent e of w = e^{i pi/4} and a zero
+//    flag: diagonal gates on thread or tile-index qubits only update e.
+// All of them are applied (at most one complex multiply per amplitude) before
+// an LDS exchange and, together with the pass scale, before the store.
 struct Gen {
     const PassProg &P;
     int R, T, N, L;
     std::ostringstream o;
     int m[64];            // pending rotation i^m of each register
+    int h[64];            // pending factor 2^{-h/2} of each register
+    bool sdirty[8];       // slot s carries the run-time sign sg<s>
     bool e_dirty = false; // e or the zero flag may differ from (0, alive)
     bool dp;              // complex128 state (validation instantiation)
+    int uid = 0;          // unique temporaries
     std::string CT, RT, MK, CM, XS, QT, ZERO;
     Gen(const PassProg &p, int r, int t, bool double_precision = false)
         : P(p), R(r), T(t), N(1 << r), L(r + t), dp(double_precision) {
-        for (int j = 0; j < 64; ++j) m[j] = 0;
+        for (int j = 0; j < 64; ++j) m[j] = h[j] = 0;
+        for (int s = 0; s < 8; ++s) sdirty[s] = false;
         CT = dp ? "double2" : "float2";
         RT = dp ? "double" : "float";
         MK = dp ? "D2" : "F2";
@@ -135,6 +143,7 @@ struct Gen {
         ZERO = dp ? "0.0" : "0.f";
     }
     std::string lit(double v) const { return dp ? dbl(v) : flt(v); }
+    std::string tmpname(const char *p) { return std::string(p) + std::to_string(uid++); }
 
     bool is_reg(uint32_t loc) const { return loc < uint32_t(R); }
     bool is_glob(uint32_t loc) const { return loc & 0x80u; }
@@ -144,6 +153,7 @@ struct Gen {
         else s << "((t >> " << (loc - R) << ") & 1u)";
         return s.str();
     }
+    static std::string sgn(int s) { return "sg" + std::to_string(s); }
 
     // component c (0 = re, 1 = im) of i^r * Z as a signed term
     static std::string term(const char *z, int r, int c) {
@@ -154,20 +164,57 @@ struct Gen {
         std::snprintf(b, sizeof b, comp[r][c], z);
         return b;
     }
-    // i^a * X + i^b * Y
-    std::string sum(int a, int b) const {
-        std::string re = term("x", a, 0) + term("y", b, 0);
-        std::string im = term("x", a, 1) + term("y", b, 1);
+    // i^a * X + coef * i^b * Y ; coef == "" means 1
+    std::string sum(int a, int b, const std::string &coef) const {
+        std::string re, im;
+        if (coef.empty()) {
+            re = term("x", a, 0) + term("y", b, 0);
+            im = term("x", a, 1) + term("y", b, 1);
+        } else {
+            re = term("x", a, 0) + "+" + coef + "*(" + term("y", b, 0) + ")";
+            im = term("x", a, 1) + "+" + coef + "*(" + term("y", b, 1) + ")";
+        }
         return MK + "(" + re + "," + im + ")";
     }
 
+    // sign flip of slot s by a 0/1 predicate expression
+    void flip_slot(int s, const std::string &p) {
+        if (sdirty[s]) {
+            o << sgn(s) << " = (" << p << ") ? -" << sgn(s) << " : " << sgn(s) << ";\n";
+        } else {
+            if (!declared_sg[s]) o << RT << " ";
+            o << sgn(s) << " = (" << p << ") ? " << lit(-1.0) << " : " << lit(1.0) << ";\n";
+        }
+        declared_sg[s] = true;
+        sdirty[s] = true;
+    }
+    bool declared_sg[8] = {false, false, false, false, false, false, false, false};
+
     void butterfly(uint32_t code, int S) {
+        // coefficient of Y relative to X per distinct h difference
+        std::map<int, std::string> coef;
+        for (int j = 0; j < N; ++j) {
+            if (j & (1 << S)) continue;
+            const int k = j | (1 << S);
+            const int dh = h[k] - h[j];
+            if (coef.count(dh)) continue;
+            const double mag = std::pow(2.0, -0.5 * dh);
+            if (!sdirty[S]) {
+                coef[dh] = (dh == 0) ? "" : lit(mag);
+            } else if (dh == 0) {
+                coef[dh] = sgn(S);
+            } else {
+                const std::string nm = tmpname("c");
+                o << "const " << RT << " " << nm << " = " << sgn(S) << " * " << lit(mag) << ";\n";
+                coef[dh] = nm;
+            }
+        }
         for (int j = 0; j < N; ++j) {
             if (j & (1 << S)) continue;
             const int k = j | (1 << S);
             const int d = (m[k] - m[j]) & 3;
-            // outputs relative to the common factor i^{m[j]}
-            int a0 = 0, b0 = d, a1 = 0, b1 = d;  // x' = i^a0 X + i^b0 Y ; y' = i^a1 X + i^b1 Y
+            // outputs relative to the common factor i^{m[j]} 2^{-h[j]/2}
+            int a0 = 0, b0 = d, a1 = 0, b1 = d;  // x' = i^a0 X + c i^b0 Y ; y' = i^a1 X + c i^b1 Y
             switch (code) {
             case OP_H: b1 = d + 2; break;                       // x+y, x-y
             case OP_SX: b0 = d + 3; a1 = 3; break;              // x-iy, -ix+y
@@ -175,15 +222,19 @@ struct Gen {
             case OP_SXDG: b0 = d + 1; a1 = 1; break;            // x+iy, ix+y
             case OP_SYDG: a1 = 2; break;                        // x+y, -x+y
             }
-            o << "{const " << CT << " x=v[" << j << "],y=v[" << k << "];v[" << j << "]=" << sum(a0, b0)
-              << ";v[" << k << "]=" << sum(a1, b1) << ";}\n";
+            const std::string &cf = coef[h[k] - h[j]];
+            o << "{const " << CT << " x=v[" << j << "],y=v[" << k << "];v[" << j << "]=" << sum(a0, b0, cf)
+              << ";v[" << k << "]=" << sum(a1, b1, cf) << ";}\n";
             m[k] = m[j];
+            h[k] = h[j];
         }
+        sdirty[S] = false;  // absorbed
     }
     void rot_reg(int j, int k) { m[j] = (m[j] + k / 2) & 3; }
-    void omega_reg(int j) {  // multiply the stored value by w = (1 + i)/sqrt2
-        o << "v[" << j << "]=" << MK << "((v[" << j << "].x-v[" << j << "].y)*" << lit(std::sqrt(0.5))
-          << ",(v[" << j << "].x+v[" << j << "].y)*" << lit(std::sqrt(0.5)) << ");\n";
+    void omega_reg(int j) {  // multiply the stored value by (1 + i); w = (1 + i)/sqrt2
+        o << "v[" << j << "]=" << MK << "(v[" << j << "].x-v[" << j << "].y,v[" << j << "].x+v[" << j
+          << "].y);\n";
+        h[j] += 1;
     }
     void phase_reg(int j, int k) {
         k &= 7;
@@ -192,7 +243,7 @@ struct Gen {
     }
     void zero_reg(int j) {
         o << "v[" << j << "]=" << MK << "(" << ZERO << "," << ZERO << ");\n";
-        m[j] = 0;
+        m[j] = h[j] = 0;
     }
 
     void op_phase(uint32_t loc, int k) {
@@ -213,10 +264,7 @@ struct Gen {
             return;
         }
         if (is_reg(a)) {
-            o << "{const unsigned msk = " << pred(b) << " << 31;\n";
-            for (int j = 0; j < N; ++j)
-                if (j & (1 << a)) o << "v[" << j << "]=" << XS << "(v[" << j << "],msk);\n";
-            o << "}\n";
+            flip_slot(int(a), pred(b));
             return;
         }
         o << "e += (" << pred(a) << " & " << pred(b) << ") * 4u;\n";
@@ -227,14 +275,12 @@ struct Gen {
         std::string l = c ? "unsigned((branch >> " + std::to_string(b) + ") & 1ull)"
                           : std::to_string(b) + "u";
         if (is_reg(loc)) {
-            int save[64];
-            std::copy(m, m + 64, save);
             if (!c) {
                 for (int j = 0; j < N; ++j)
                     if (((j >> loc) & 1) != int(b)) zero_reg(j);
                 return;
             }
-            // branch-dependent: both arms leave the surviving registers' m unchanged
+            // branch-dependent: both arms leave the surviving registers' state unchanged
             o << "if (" << l << ") {\n";
             for (int j = 0; j < N; ++j)
                 if (!(j & (1 << loc))) o << "v[" << j << "]=" << MK << "(" << ZERO << "," << ZERO << ");\n";
@@ -242,7 +288,6 @@ struct Gen {
             for (int j = 0; j < N; ++j)
                 if (j & (1 << loc)) o << "v[" << j << "]=" << MK << "(" << ZERO << "," << ZERO << ");\n";
             o << "}\n";
-            std::copy(save, save + 64, m);
             return;
         }
         o << "alive &= unsigned((" << pred(loc) << ") == " << l << ");\n";
@@ -250,55 +295,85 @@ struct Gen {
     }
 
     void op_zb(uint32_t loc, uint32_t b) {
+        const std::string bit = "unsigned((branch >> " + std::to_string(b) + ") & 1ull)";
         if (is_reg(loc)) {
-            o << "{const unsigned msk = unsigned((branch >> " << b << ") & 1ull) << 31;\n";
-            for (int j = 0; j < N; ++j)
-                if (j & (1 << loc)) o << "v[" << j << "]=" << XS << "(v[" << j << "],msk);\n";
-            o << "}\n";
+            flip_slot(int(loc), bit);
             return;
         }
-        o << "e += (unsigned((branch >> " << b << ") & 1ull) & " << pred(loc) << ") * 4u;\n";
+        o << "e += (" << bit << " & " << pred(loc) << ") * 4u;\n";
         e_dirty = true;
     }
 
-    // Multiply every register by i^{m_j} * w^e * alive * (sr + i si), then
-    // reset the pending factors.
+    // Multiply every register by its pending factors and by (sr + i si), then
+    // reset them: i^{m_j} 2^{-h_j/2} (compile time), prod of sg<s> over the
+    // register's set bits of dirty slots, w^e * alive (run time).
     void materialize(double sr, double si) {
-        const bool unit = (sr == 1.0 && si == 0.0);
-        if (!e_dirty) {
-            for (int j = 0; j < N; ++j) {
-                const int r = m[j] & 3;
-                if (unit) {
-                    if (r == 0) continue;
-                    o << "{const " << CT << " x=v[" << j << "];v[" << j << "]=" << MK << "("
-                      << term("x", r, 0) << "," << term("x", r, 1) << ");}\n";
-                } else if (si == 0.0) {
-                    // real scale: (+-s x or +-s y) per component
-                    o << "{const " << CT << " x=v[" << j << "];v[" << j << "]=" << MK << "(("
-                      << term("x", r, 0) << ")*" << lit(sr) << ",(" << term("x", r, 1) << ")*" << lit(sr)
-                      << ");}\n";
-                } else {
-                    // rotate the constant instead of the value
-                    double cr = sr, ci = si;
-                    for (int q = 0; q < r; ++q) { double t2 = -ci; ci = cr; cr = t2; }
-                    o << "v[" << j << "]=" << CM << "(v[" << j << "]," << lit(cr) << "," << lit(ci) << ");\n";
+        int dmask = 0;
+        for (int s = 0; s < R; ++s)
+            if (sdirty[s]) dmask |= 1 << s;
+        std::map<int, std::string> sig;  // sign products by slot mask
+        auto sign_of = [&](int mask) -> std::string {
+            if (mask == 0) return "";
+            std::string prev;
+            int acc = 0;
+            for (int s = 0; s < R; ++s) {  // build the product bit by bit, reusing prefixes
+                if (!(mask & (1 << s))) continue;
+                acc |= 1 << s;
+                auto it = sig.find(acc);
+                if (it == sig.end()) {
+                    const std::string nm = tmpname("s");
+                    o << "const " << RT << " " << nm << " = " << (prev.empty() ? "" : prev + " * ") << sgn(s)
+                      << ";\n";
+                    it = sig.emplace(acc, nm).first;
                 }
-                m[j] = 0;
+                prev = it->second;
             }
-            return;
+            return prev;
+        };
+        if (e_dirty) {
+            o << "const " << RT << " wr" << uid << " = alive ? " << QT << "[e & 7u] : " << ZERO << ", wi" << uid
+              << " = alive ? " << QT << "[8u + (e & 7u)] : " << ZERO << ";\n";
         }
-        o << "{const " << RT << " a0 = alive ? " << QT << "[e & 7u] : " << ZERO << ", b0 = alive ? " << QT
-          << "[8u + (e & 7u)] : " << ZERO << ";\n";
-        o << "const " << RT << " fr = a0 * " << lit(sr) << " - b0 * " << lit(si) << ", fi = a0 * "
-          << lit(si) << " + b0 * " << lit(sr) << ";\n";
+        const int wid = uid++;
         for (int j = 0; j < N; ++j) {
-            static const char *rr[4] = {"fr", "-fi", "-fr", "fi"};
-            static const char *ri[4] = {"fi", "fr", "-fi", "-fr"};
-            const int r = m[j] & 3;
-            o << "v[" << j << "]=" << CM << "(v[" << j << "]," << rr[r] << "," << ri[r] << ");\n";
-            m[j] = 0;
+            // compile-time factor K = i^m 2^{-h/2} (sr + i si)
+            const double mag = std::pow(2.0, -0.5 * h[j]);
+            double kr = sr * mag, ki = si * mag;
+            for (int q = 0; q < (m[j] & 3); ++q) { double t2 = -ki; ki = kr; kr = t2; }
+            const std::string sj = sign_of(j & dmask);
+            if (!e_dirty) {
+                const bool real = (ki == 0.0), imag = (kr == 0.0);
+                if (sj.empty() && kr == 1.0 && ki == 0.0) continue;
+                if (real || imag) {
+                    // K = k * i^r with real k: components swap/negate, one scale each
+                    const int r = real ? (kr > 0 ? 0 : 2) : (ki > 0 ? 1 : 3);
+                    const double k = real ? std::fabs(kr) : std::fabs(ki);
+                    std::string f;
+                    if (sj.empty()) f = (k == 1.0) ? "" : lit(k);
+                    else f = (k == 1.0) ? sj : ("(" + sj + "*" + lit(k) + ")");
+                    o << "{const " << CT << " x=v[" << j << "];v[" << j << "]=" << MK << "(";
+                    if (f.empty()) o << term("x", r, 0) << "," << term("x", r, 1);
+                    else o << "(" << term("x", r, 0) << ")*" << f << ",(" << term("x", r, 1) << ")*" << f;
+                    o << ");}\n";
+                } else if (sj.empty()) {
+                    o << "v[" << j << "]=" << CM << "(v[" << j << "]," << lit(kr) << "," << lit(ki) << ");\n";
+                } else {
+                    o << "v[" << j << "]=" << CM << "(v[" << j << "]," << sj << "*" << lit(kr) << "," << sj << "*"
+                      << lit(ki) << ");\n";
+                }
+            } else {
+                // (wr + i wi) * K * sign
+                std::string fr = "(wr" + std::to_string(wid) + "*" + lit(kr) + "-wi" + std::to_string(wid) + "*" +
+                                 lit(ki) + ")";
+                std::string fi = "(wr" + std::to_string(wid) + "*" + lit(ki) + "+wi" + std::to_string(wid) + "*" +
+                                 lit(kr) + ")";
+                if (!sj.empty()) { fr = sj + "*" + fr; fi = sj + "*" + fi; }
+                o << "v[" << j << "]=" << CM << "(v[" << j << "]," << fr << "," << fi << ");\n";
+            }
         }
-        o << "e = 0u; alive = 1u;}\n";
+        for (int j = 0; j < N; ++j) m[j] = h[j] = 0;
+        for (int s = 0; s < R; ++s) sdirty[s] = false;
+        if (e_dirty) o << "e = 0u; alive = 1u;\n";
         e_dirty = false;
     }
 
