@@ -83,9 +83,20 @@ typedef struct qsv_batch qsv_batch;      /* opaque */
  *                  each global access a contiguous run (c, 3..8)
  *   plain          1 = one kernel per gate (the unfused comparator path)
  *   jit            1 = compile each pass program into its own straight-line
- *                  kernel at first use (hipRTC, cached per process); -1 = always
- *                  use the generic pass kernel; 0 = compile for states of 2^24
- *                  amplitudes or more
+ *                  kernel at first use (hipRTC, cached per process), one tile
+ *                  per workgroup; 2 = the same kernels as persistent workgroups
+ *                  that prefetch their next tile into registers while they
+ *                  compute the current one; -1 = always use the generic pass
+ *                  kernel; 0 = 1 for states of 2^24 amplitudes or more, else -1
+ *   out_of_place   compiled kernels only.  1 = every pass reads one buffer and
+ *                  writes the other (the caller's state and a second state
+ *                  buffer the library allocates once per device and keeps), so
+ *                  that each pass can write the state with the next pass's
+ *                  qubits at the lowest address bits; the result is always in
+ *                  the caller's buffer.  -1 = in place.  0 = out of place for
+ *                  2^24 amplitudes or more when the second buffer fits.  Calls
+ *                  that overlap on one device share the second buffer: run
+ *                  them with -1.
  */
 typedef struct {
     int reg_qubits;
@@ -93,6 +104,7 @@ typedef struct {
     int low_qubits;
     int plain;
     int jit;
+    int out_of_place;
 } qsv_fuse_opts;
 
 /*

@@ -85,7 +85,7 @@ qsv_status build_tables(qsv_batch *b, int lb) {
         auto it = idx.find(b->circs[i]);
         if (it == idx.end()) {
             qsv_circuit *c = const_cast<qsv_circuit *>(b->circs[i]);
-            PlanKey key{lb, -1, b->R, b->T, b->c};
+            PlanKey key{lb, -1, b->R, b->T, b->c, false};
             std::shared_ptr<Plan> p;
             {
                 std::lock_guard<std::mutex> g(c->mu);

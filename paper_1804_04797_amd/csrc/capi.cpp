@@ -83,11 +83,52 @@ qsv_status check_state(const void *amps, int n) {
     return QSV_OK;
 }
 
+// Second state buffer of out-of-place sweeps, one per device, grown on
+// demand and kept until the process ends.  Calls that overlap on one device
+// share it, so they must not both run out of place.
+qsv_status state_scratch(size_t bytes, void **out) {
+    static std::mutex mu;
+    static void *buf[64] = {nullptr};
+    static size_t cap[64] = {0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(QSV_EUNSUPPORTED, "device ordinal out of range");
+    std::lock_guard<std::mutex> g(mu);
+    if (cap[dev] < bytes) {
+        if (buf[dev]) {
+            // queued work may still use the old buffer
+            hipDeviceSynchronize();
+            hipFree(buf[dev]);
+            buf[dev] = nullptr;
+            cap[dev] = 0;
+        }
+        void *p = nullptr;
+        e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(QSV_ENOMEM, "out-of-place sweep: second state buffer does not fit");
+        }
+        buf[dev] = p;
+        cap[dev] = bytes;
+    }
+    *out = buf[dev];
+    return QSV_OK;
+}
+
+// opts as given, else the autotuned options of this circuit and layer range
+// (sv_tune), else NULL (defaults)
+const qsv_fuse_opts *effective_opts(const qsv_circuit *c, const qsv_fuse_opts *opts, int lb, int le,
+                                    qsv_fuse_opts *store) {
+    if (opts) return opts;
+    if (tuned_opts(c, lb, le, store)) return store;
+    return nullptr;
+}
+
 qsv_status resolve_shape(const qsv_circuit *c, const qsv_fuse_opts *opts, TileShape &sh,
                          int lb = 0, int le = -1) {
+    (void)lb; (void)le;
     sh = default_shape(c->n);
-    qsv_fuse_opts tuned;
-    if (!opts && tuned_opts(c, lb, le, &tuned)) opts = &tuned;
     if (opts) {
         if (opts->reg_qubits) sh.R = opts->reg_qubits;
         if (opts->thread_qubits) sh.T = opts->thread_qubits;
@@ -103,10 +144,50 @@ qsv_status resolve_shape(const qsv_circuit *c, const qsv_fuse_opts *opts, TileSh
     return QSV_OK;
 }
 
+// Out-of-place sweeps (compiled pass kernels only): opts->out_of_place
+// 1 = required, -1 = never, 0 = for states of 2^24 amplitudes or more.
+int oop_mode(const qsv_circuit *c, const qsv_fuse_opts *opts, int jm) {
+    const int o = opts ? opts->out_of_place : 0;
+    if (!jm || o < 0) return 0;
+    if (o > 0) return 2;
+    return c->n >= 24 ? 1 : 0;
+}
+
+qsv_status get_plan(const qsv_circuit *cc, int lb, int le, TileShape sh,
+                    std::shared_ptr<Plan> &out);
+
+// Plan and second buffer of a fused call.  `reads_state`: the first pass
+// loads the caller's state (sv_apply_fused); an out-of-place plan then needs
+// an even number of passes to end in the caller's buffer, else the in-place
+// plan is used.  An automatic out-of-place choice falls back to in place when
+// the second buffer does not fit.
+qsv_status select_plan(const qsv_circuit *c, int lb, int le, TileShape sh, int oop, bool reads_state,
+                       std::shared_ptr<Plan> &plan) {
+    qsv_status st;
+    if (oop) {
+        sh.oop = true;
+        if ((st = get_plan(c, lb, le, sh, plan)) != QSV_OK) return st;
+        if (!(reads_state && plan->passes.size() % 2)) return QSV_OK;
+    }
+    sh.oop = false;
+    return get_plan(c, lb, le, sh, plan);
+}
+
+qsv_status get_fused_plan(const qsv_circuit *c, int lb, int le, TileShape sh, int oop,
+                          bool reads_state, std::shared_ptr<Plan> &plan, void **scratch) {
+    *scratch = nullptr;
+    qsv_status st = select_plan(c, lb, le, sh, oop, reads_state, plan);
+    if (st != QSV_OK || !plan->oop) return st;
+    st = state_scratch(sizeof(float) * 2 * (size_t(1) << c->n), scratch);
+    if (st == QSV_OK || oop > 1) return st;
+    sh.oop = false;
+    return get_plan(c, lb, le, sh, plan);
+}
+
 qsv_status get_plan(const qsv_circuit *cc, int lb, int le, TileShape sh,
                     std::shared_ptr<Plan> &out) {
     qsv_circuit *c = const_cast<qsv_circuit *>(cc);
-    PlanKey key{lb, le, sh.R, sh.T, sh.c};
+    PlanKey key{lb, le, sh.R, sh.T, sh.c, sh.oop};
     std::lock_guard<std::mutex> g(c->mu);
     auto it = c->plans.find(key);
     if (it != c->plans.end()) {
@@ -121,14 +202,17 @@ qsv_status get_plan(const qsv_circuit *cc, int lb, int le, TileShape sh,
     return QSV_OK;
 }
 
-bool use_jit(const qsv_circuit *c, const qsv_fuse_opts *opts) {
+// 0 = generic pass kernel; otherwise the kJit* flags the compiled kernels add
+int jit_mode(const qsv_circuit *c, const qsv_fuse_opts *opts) {
     int j = opts ? opts->jit : 0;
     if (j == 0) {
         const char *env = std::getenv("QSV_JIT");
-        if (env && env[0] == '0') return false;
-        return c->n >= 24;
+        if (env && env[0] == '0') return 0;
+        if (c->n < 24) return 0;
+        j = 1;
     }
-    return j > 0;
+    if (j < 0) return 0;
+    return j >= 2 ? (1 | kJitLoop) : 1;
 }
 
 void gate_matrix_f32(uint8_t kind, float m[8]) {
@@ -264,21 +348,28 @@ qsv_status sv_apply_fused(void *amps, const qsv_circuit *c, uint64_t branch, int
     qsv_status st = check_state(amps, c->n);
     if (st != QSV_OK) return st;
     if (layer_begin < 0) return fail(QSV_EINVAL, "sv_apply_fused: layer_begin < 0");
+    qsv_fuse_opts tuned;
+    opts = effective_opts(c, opts, layer_begin, layer_end, &tuned);
     if (opts && opts->plain) return sv_apply_plain(amps, c, branch, layer_begin, layer_end, stream);
     TileShape sh;
     if ((st = resolve_shape(c, opts, sh, layer_begin, layer_end)) != QSV_OK) return st;
     if (sh.R == 0) return sv_apply_plain(amps, c, branch, layer_begin, layer_end, stream);
     if ((st = check_device()) != QSV_OK) return st;
     std::shared_ptr<Plan> plan;
-    if ((st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (use_jit(c, opts)) {
+    if (const int jm = jit_mode(c, opts)) {
+        void *scratch = nullptr;
+        if ((st = get_fused_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jm), true, plan,
+                                 &scratch)) != QSV_OK)
+            return st;
+        const int variant = kJitPlain | (jm & kJitLoop);
         {
             std::lock_guard<std::mutex> g(plan->jit_mu);
-            if ((st = jit_prepare(*plan, kJitPlain)) != QSV_OK) return st;
+            if ((st = jit_prepare(*plan, variant)) != QSV_OK) return st;
         }
-        return jit_launch(*plan, kJitPlain, amps, branch, 0, nullptr, s);
+        return jit_launch(*plan, variant, amps, scratch, branch, 0, nullptr, s);
     }
+    if ((st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) return st;
     for (const Pass &p : plan->passes) {
         hipError_t e = launch_fused(static_cast<float2 *>(amps), c->n, sh.R, sh.T, p.prog, branch, s);
         if (e != hipSuccess) return hip_fail(e, "sv_apply_fused");
@@ -335,6 +426,8 @@ qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int in
         return fail(QSV_ERANGE, "sv_simulate: basis index >= 2^n");
     if (init_kind == QSV_INIT_ZERO) basis = 0;
     if (layer_begin < 0) return fail(QSV_EINVAL, "sv_simulate: layer_begin < 0");
+    qsv_fuse_opts tuned;
+    opts = effective_opts(c, opts, layer_begin, layer_end, &tuned);
     if (m && (!bitstrings_dev || !amps_out_dev)) return fail(QSV_EINVAL, "sv_simulate: null gather buffer");
     if ((st = check_device()) != QSV_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -345,11 +438,19 @@ qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int in
         fused = sh.R != 0;
     }
     std::shared_ptr<Plan> plan;
-    if (fused && (st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) return st;
+    const int jm = fused ? jit_mode(c, opts) : 0;
+    void *scratch = nullptr;
+    if (jm) {
+        if ((st = get_fused_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jm), false, plan,
+                                 &scratch)) != QSV_OK)
+            return st;
+    } else if (fused && (st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) {
+        return st;
+    }
     bool done_norm = false;
-    if (fused && use_jit(c, opts) && !plan->passes.empty()) {
+    if (jm && !plan->passes.empty()) {
         // initial state generated by the first pass, norm by the last
-        const int variant = kJitInit | init_kind | (norm_out_dev ? kJitNorm : 0);
+        const int variant = kJitInit | init_kind | (norm_out_dev ? kJitNorm : 0) | (jm & kJitLoop);
         {
             std::lock_guard<std::mutex> g(plan->jit_mu);
             if ((st = jit_prepare(*plan, variant)) != QSV_OK) return st;
@@ -357,7 +458,7 @@ qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int in
         double *part = nullptr;
         const uint64_t tiles = 1ull << (c->n - sh.R - sh.T);
         if (norm_out_dev && (st = norm_partials(tiles, &part)) != QSV_OK) return st;
-        if ((st = jit_launch(*plan, variant, amps, branch, basis, part, s)) != QSV_OK) return st;
+        if ((st = jit_launch(*plan, variant, amps, scratch, branch, basis, part, s)) != QSV_OK) return st;
         if (norm_out_dev) {
             hipError_t e = launch_sum_partials(part, tiles, norm_out_dev, s);
             if (e != hipSuccess) return hip_fail(e, "sv_simulate");
@@ -409,7 +510,7 @@ qsv_status sv_simulate_c128(void *amps, const qsv_circuit *c, uint64_t branch, i
     double *part = nullptr;
     const uint64_t tiles = 1ull << (c->n - sh.R - sh.T);
     if (norm_out_dev && (st = norm_partials(tiles, &part)) != QSV_OK) return st;
-    if ((st = jit_launch(*plan, variant, amps, branch, basis, part, s)) != QSV_OK) return st;
+    if ((st = jit_launch(*plan, variant, amps, nullptr, branch, basis, part, s)) != QSV_OK) return st;
     if (norm_out_dev) {
         hipError_t e = launch_sum_partials(part, tiles, norm_out_dev, s);
         if (e != hipSuccess) return hip_fail(e, "sv_simulate_c128");
@@ -426,12 +527,16 @@ qsv_status sv_plan_info(const qsv_circuit *c, int layer_begin, int layer_end,
                         int32_t *order_in_pass, size_t n_gate_cap, uint64_t *resident_mask,
                         size_t pass_cap) {
     if (!c || !n_passes) return fail(QSV_EINVAL, "sv_plan_info: null argument");
+    qsv_fuse_opts tuned;
+    opts = effective_opts(c, opts, layer_begin, layer_end, &tuned);
     TileShape sh;
     qsv_status st = resolve_shape(c, opts, sh, layer_begin, layer_end);
     if (st != QSV_OK) return st;
     if (sh.R == 0) return fail(QSV_EUNSUPPORTED, "sv_plan_info: state too small for a tile");
     std::shared_ptr<Plan> plan;
-    if ((st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) return st;
+    if ((st = select_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jit_mode(c, opts)), false,
+                          plan)) != QSV_OK)
+        return st;
     *n_passes = int(plan->passes.size());
     if (pass_of_gate || order_in_pass) {
         size_t ng = std::min(n_gate_cap, c->gates.size());
@@ -458,26 +563,42 @@ qsv_status sv_debug_emulate(void *amps_host, const qsv_circuit *c, uint64_t bran
                             int layer_begin, int layer_end, const qsv_fuse_opts *opts) {
     if (!c || !amps_host) return fail(QSV_EINVAL, "sv_debug_emulate: null argument");
     if (c->n > 26) return fail(QSV_ERANGE, "sv_debug_emulate: n must be <= 26");
+    qsv_fuse_opts tuned;
+    opts = effective_opts(c, opts, layer_begin, layer_end, &tuned);
     TileShape sh;
     qsv_status st = resolve_shape(c, opts, sh);
     if (st != QSV_OK) return st;
     if (sh.R == 0) return fail(QSV_EUNSUPPORTED, "sv_debug_emulate: state too small for a tile");
     std::shared_ptr<Plan> plan;
-    if ((st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) return st;
-    for (const Pass &p : plan->passes)
-        emulate_pass(p.prog, c->n, sh.R, sh.T, branch, static_cast<float *>(amps_host));
+    if ((st = select_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jit_mode(c, opts)), true,
+                          plan)) != QSV_OK)
+        return st;
+    // the same buffer schedule as the device sweep
+    float *amps = static_cast<float *>(amps_host);
+    std::vector<float> second(plan->oop ? size_t(2) << c->n : 0);
+    const size_t np = plan->passes.size();
+    const float *in = amps;
+    for (size_t p = 0; p < np; ++p) {
+        float *out = (!plan->oop || (np - p) % 2 == 1) ? amps : second.data();
+        emulate_pass(plan->passes[p].prog, c->n, sh.R, sh.T, branch, in, out);
+        in = out;
+    }
     return QSV_OK;
 }
 
 qsv_status sv_debug_jit_compile(const qsv_circuit *c, int layer_begin, int layer_end,
                                 const qsv_fuse_opts *opts, size_t *code_bytes, double *seconds) {
     if (!c) return fail(QSV_EINVAL, "sv_debug_jit_compile: null circuit");
+    qsv_fuse_opts tuned;
+    opts = effective_opts(c, opts, layer_begin, layer_end, &tuned);
     TileShape sh;
     qsv_status st = resolve_shape(c, opts, sh);
     if (st != QSV_OK) return st;
     if (sh.R == 0) return fail(QSV_EUNSUPPORTED, "sv_debug_jit_compile: state too small for a tile");
     std::shared_ptr<Plan> plan;
-    if ((st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) return st;
+    if ((st = select_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jit_mode(c, opts)), false,
+                          plan)) != QSV_OK)
+        return st;
     return jit_compile_only(*plan, code_bytes, seconds);
 }
 

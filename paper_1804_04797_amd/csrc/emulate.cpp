@@ -12,7 +12,7 @@
 
 namespace qsv {
 
-void emulate_pass(const PassProg &P, int n, int R, int T, uint64_t branch, float *amps) {
+void emulate_pass(const PassProg &P, int n, int R, int T, uint64_t branch, const float *src, float *dst) {
     const int L = R + T;
     const int N = 1 << R, NT = 1 << T;
     const uint64_t tiles = 1ull << (n - L);
@@ -21,19 +21,20 @@ void emulate_pass(const PassProg &P, int n, int R, int T, uint64_t branch, float
     const float wi[8] = {0.f, float(s2), 1.f, float(s2), 0.f, float(-s2), -1.f, float(-s2)};
     std::vector<float> v(size_t(2) << L), w(size_t(2) << L);
     for (uint64_t tile = 0; tile < tiles; ++tile) {
-        uint64_t base = 0;
+        uint64_t base = 0, bst = 0;  // tile origin in the read and the written map
         for (int i = 0; i < P.n_glob; ++i) base |= ((tile >> i) & 1ull) << P.glob_bits[i];
-        auto addr = [&](const uint8_t *phys, uint32_t x) {
-            uint64_t a = base;
+        for (int i = 0; i < P.n_glob; ++i) bst |= ((tile >> i) & 1ull) << P.glob_st[i];
+        auto addr = [&](const uint8_t *phys, uint32_t x, uint64_t origin) {
+            uint64_t a = origin;
             for (int s = 0; s < L; ++s)
                 if ((x >> s) & 1) a |= 1ull << phys[s];
             return a;
         };
         // slot coordinate x = j | t << R
         for (uint32_t x = 0; x < (1u << L); ++x) {
-            uint64_t a = addr(P.ld_phys, x);
-            v[2 * x] = amps[2 * a];
-            v[2 * x + 1] = amps[2 * a + 1];
+            uint64_t a = addr(P.ld_phys, x, base);
+            v[2 * x] = src[2 * a];
+            v[2 * x + 1] = src[2 * a + 1];
         }
         auto bit = [&](uint32_t x, uint32_t loc) -> int {
             if (loc & kLocGlobal) return int((base >> (loc & 0x7f)) & 1);
@@ -107,9 +108,9 @@ void emulate_pass(const PassProg &P, int n, int R, int T, uint64_t branch, float
             }
         }
         for (uint32_t x = 0; x < (1u << L); ++x) {
-            uint64_t ad = addr(P.st_phys, x);
-            amps[2 * ad] = v[2 * x];
-            amps[2 * ad + 1] = v[2 * x + 1];
+            uint64_t ad = addr(P.st_phys, x, bst);
+            dst[2 * ad] = v[2 * x];
+            dst[2 * ad + 1] = v[2 * x + 1];
         }
     }
     (void)N; (void)NT;

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -377,92 +378,216 @@ struct Gen {
         e_dirty = false;
     }
 
+    // LDS staging of one exchange.  When some register slot s of the new
+    // layout takes an old register slot (perm[s] < R), the data splits into
+    // two independent halves by that bit, which go through LDS one after the
+    // other: half the buffer, so twice the workgroups per CU.
+    //
+    // The buffer is indexed in the slot coordinates of either the old layout
+    // (the store is a plain register store, the load gathers) or the new one
+    // (the other way round), leaving out the split slot.  Coordinate q has the
+    // element weight 2^tau[q] (register slots) or (M + 1) * 2^sigma[q - R]
+    // (thread slots), M = registers per half (or all): tau and sigma are bit
+    // permutations, so the address is injective and stays below (M + 1) * 2^T,
+    // and each register's offset is a literal.  They are chosen so that the
+    // lanes the LDS serves together hit distinct banks on the store and on the
+    // load.
+    struct XLayout {
+        bool by_new = false;
+        int split = -1;      // new register slot s of the split, or -1
+        int skip = -1;       // coordinate left out (perm[s] or s), or -1
+        int M = 0;           // registers per staged part
+        int tau[kMaxSlots] = {};
+        int sigma[kMaxSlots] = {};
+    };
+    int lds_elems = 0;       // largest staging buffer of the pass (elements)
+
+    uint32_t xweight(const XLayout &x, int q) const {
+        if (q == x.skip) return 0;
+        return q < R ? (1u << x.tau[q]) : (uint32_t(x.M + 1) << x.sigma[q - R]);
+    }
+    // worst number of lanes sharing a bank pair among the lanes whose low
+    // `lanes_log2` bits vary (lane bit u carries weight w[u]), for 8-byte
+    // elements on `banks` 4-byte banks
+    static int conflict(const uint32_t *w, int nb, int lanes_log2, int banks) {
+        const int bits = std::min(nb, lanes_log2);
+        const uint32_t mod = uint32_t(banks / 2);
+        int cnt[64] = {};
+        int worst = 0;
+        for (int l = 0; l < (1 << bits); ++l) {
+            uint32_t a = 0;
+            for (int u = 0; u < bits; ++u)
+                if ((l >> u) & 1) a += w[u];
+            worst = std::max(worst, ++cnt[a % mod]);
+        }
+        return worst;
+    }
+    // lane weights of the store (old thread slots) and the load (new thread slots)
+    void lane_weights(const XLayout &x, const int *perm, const int *inv, uint32_t *ww, uint32_t *wr) const {
+        for (int u = 0; u < T; ++u) {
+            ww[u] = xweight(x, x.by_new ? inv[R + u] : R + u);
+            wr[u] = xweight(x, x.by_new ? R + u : perm[R + u]);
+        }
+    }
+    int xcost(const XLayout &x, const int *perm, const int *inv) const {
+        uint32_t ww[kMaxSlots], wr[kMaxSlots];
+        lane_weights(x, perm, inv, ww, wr);
+        // 64 banks serving 32 lanes, and 32 banks serving 16 lanes
+        return 2 * (conflict(ww, T, 5, 64) + conflict(wr, T, 5, 64)) + conflict(ww, T, 4, 32) +
+               conflict(wr, T, 4, 32);
+    }
+    void base_layout(XLayout &x, bool by_new, int split, const int *perm) const {
+        x.by_new = by_new;
+        x.split = split;
+        x.skip = split < 0 ? -1 : (by_new ? split : perm[split]);
+        x.M = split < 0 ? N : N / 2;
+        int k = 0;
+        for (int q = 0; q < R; ++q) x.tau[q] = (q == x.skip) ? 0 : k++;
+        for (int u = 0; u < T; ++u) x.sigma[u] = u;
+    }
+    XLayout choose_layout(const int *perm, const int *inv) const {
+        // split slot: prefer a register slot that stays in place
+        int split = -1;
+        for (int q = 0; q < R && split < 0; ++q)
+            if (perm[q] == q) split = q;
+        for (int q = 0; q < R && split < 0; ++q)
+            if (perm[q] < R) split = q;
+        XLayout best;
+        base_layout(best, false, split, perm);
+        int best_cost = xcost(best, perm, inv);
+        const int floor_cost = 6;  // every group conflict-free
+        uint64_t rng = 0x9E3779B97F4A7C15ull ^ uint64_t(uid);
+        auto next = [&rng]() {
+            rng ^= rng << 13; rng ^= rng >> 7; rng ^= rng << 17;
+            return rng;
+        };
+        for (int trial = 0; trial < 4000 && best_cost > floor_cost; ++trial) {
+            XLayout x;
+            base_layout(x, (trial & 1) != 0, split, perm);
+            if (trial >= 2) {
+                int regs[kMaxSlots], nr = 0;
+                for (int q = 0; q < R; ++q)
+                    if (q != x.skip) regs[nr++] = q;
+                for (int i = nr - 1; i > 0; --i)
+                    std::swap(x.tau[regs[i]], x.tau[regs[next() % uint64_t(i + 1)]]);
+                for (int u = T - 1; u > 0; --u) std::swap(x.sigma[u], x.sigma[next() % uint64_t(u + 1)]);
+            }
+            const int c = xcost(x, perm, inv);
+            if (c < best_cost) { best_cost = c; best = x; }
+        }
+        return best;
+    }
+    std::string lane_base(const uint32_t *w, int M) const {
+        bool plain = true;
+        for (int u = 0; u < T; ++u) plain = plain && w[u] == (uint32_t(M + 1) << u);
+        if (plain) return "t * " + std::to_string(M + 1) + "u";
+        std::ostringstream e;
+        e << "0u";
+        for (int u = 0; u < T; ++u)
+            if (w[u]) e << " + ((t >> " << u << ") & 1u) * " << w[u] << "u";
+        return e.str();
+    }
+
     void op_xchg(uint64_t pw) {
         materialize(1.0, 0.0);
-        int perm[kMaxSlots];
+        int perm[kMaxSlots], inv[kMaxSlots];
         for (int s = 0; s < L; ++s) perm[s] = int((pw >> (4 * s)) & 0xf);
-        // write at padded old coordinate, read at padded new coordinate
-        o << "{__syncthreads();\n";
-        for (int j = 0; j < N; ++j) o << "lds[wt+" << j << "]=v[" << j << "];\n";
-        o << "unsigned yt = 0u";
-        for (int u = 0; u < T; ++u) o << " | (((t >> " << u << ") & 1u) << " << perm[R + u] << ")";
-        o << ";\nconst unsigned rt = yt + (yt >> " << R << ");\n__syncthreads();\n";
-        for (int j = 0; j < N; ++j) {
-            unsigned yj = 0;
-            for (int s = 0; s < R; ++s)
-                if ((j >> s) & 1) yj |= 1u << perm[s];
-            o << "v[" << j << "]=lds[rt+" << (yj + (yj >> R)) << "u];\n";
+        for (int s = 0; s < L; ++s) inv[perm[s]] = s;
+        const XLayout x = choose_layout(perm, inv);
+        lds_elems = std::max(lds_elems, (x.M + 1) << T);
+        uint32_t ww[kMaxSlots], wr[kMaxSlots];
+        lane_weights(x, perm, inv, ww, wr);
+        const int id = uid++;
+        const int parts = x.split < 0 ? 1 : 2;
+        // register j of the old layout is stored at wb + offset, register j
+        // of the new layout is loaded from rb + offset (into nv: the old
+        // values of the second part are still to be stored)
+        o << "{const unsigned wb" << id << " = " << lane_base(ww, x.M) << ";\n";
+        o << "const unsigned rb" << id << " = " << lane_base(wr, x.M) << ";\n";
+        o << CT << " nv" << id << "[" << N << "];\n";
+        for (int h = 0; h < parts; ++h) {
+            o << "__syncthreads();\n";
+            for (int j = 0; j < N; ++j) {
+                if (parts == 2 && ((j >> perm[x.split]) & 1) != h) continue;
+                uint32_t off = 0;
+                for (int s = 0; s < R; ++s)
+                    if ((j >> s) & 1) off += xweight(x, x.by_new ? inv[s] : s);
+                o << "lds[wb" << id << "+" << off << "u]=v[" << j << "];\n";
+            }
+            o << "__syncthreads();\n";
+            for (int j = 0; j < N; ++j) {
+                if (parts == 2 && ((j >> x.split) & 1) != h) continue;
+                uint32_t off = 0;
+                for (int s = 0; s < R; ++s)
+                    if ((j >> s) & 1) off += xweight(x, x.by_new ? s : perm[s]);
+                o << "nv" << id << "[" << j << "]=lds[rb" << id << "+" << off << "u];\n";
+            }
         }
+        for (int j = 0; j < N; ++j) o << "v[" << j << "]=nv" << id << "[" << j << "];\n";
         o << "}\n";
     }
 
-    // init_kind: -1 = load the state; 0/1/2 = generate |0>, |+>^n or |basis>
-    // in registers (first pass of sv_simulate).  norm: accumulate the FP64
-    // sum of |amp|^2 of the tile into part[tile] after the store.
-    // batched: the state pointer and branch come from an entry table indexed
-    // by blockIdx.y (all entries share this plan).
-    std::string emit(const std::string &name, bool &uses_lds, int init_kind = -1,
-                     bool norm = false, int n = 0, bool batched = false) {
-        uses_lds = false;
-        for (int pc = 0; pc < P.n_ops; ++pc) {
-            if ((P.ops[pc] & 0xff) == OP_XCHG) { uses_lds = true; ++pc; }
-        }
-        std::vector<int> glob(P.glob_bits, P.glob_bits + P.n_glob);
-        std::vector<int> tld, tst;
-        for (int u = 0; u < T; ++u) { tld.push_back(P.ld_phys[R + u]); tst.push_back(P.st_phys[R + u]); }
-        o << "extern \"C\" __global__ void __launch_bounds__(" << (1 << T) << ") " << name;
-        if (batched) {
-            o << "(const BatchEntryJ* __restrict__ ents, unsigned long long tile0) {\n";
-            o << "const BatchEntryJ en = ents[blockIdx.y];\n";
-            o << CT << "* __restrict__ a = (" << CT << "*)en.amps;\n";
-            o << "const unsigned long long branch = en.branch, basis = 0ull;\n";
-            o << "double* part = nullptr;\n";
+    // Offset (in elements) of register j under the physical bits of the slots.
+    uint64_t reg_offset(int j, const uint8_t *phys, int s0) const {
+        uint64_t r = 0;
+        for (int s = s0; s < R; ++s)
+            if ((j >> s) & 1) r |= 1ull << phys[s];
+        return r;
+    }
+    // Load this thread's 2^R amplitudes of the tile at `basev` into `dst`.
+    void emit_load(const std::string &dst, const std::string &basev, const std::vector<int> &tld) {
+        if (dp) {
+            o << "{const v2d* src = (const v2d*)(srcp + (" << basev << " | " << scatter_expr("t", tld, true)
+              << "));\n";
+            for (int j = 0; j < N; ++j)
+                o << "{const v2d w = __builtin_nontemporal_load(src + " << hex64(reg_offset(j, P.ld_phys, 0))
+                  << ");" << dst << "[" << j << "]=D2(w.x,w.y);}\n";
         } else {
-            o << "(" << CT << "* __restrict__ a, unsigned long long branch, unsigned long long tile0, "
-                 "unsigned long long basis, double* __restrict__ part) {\n";
+            o << "{const v4f* src = (const v4f*)(srcp + (" << basev << " | " << scatter_expr("t", tld, true)
+              << "));\n";
+            for (int j = 0; j < N; j += 2)
+                o << "{const v4f w = __builtin_nontemporal_load(src + " << hex64(reg_offset(j, P.ld_phys, 1) / 2)
+                  << ");" << dst << "[" << j << "]=F2(w.x,w.y);" << dst << "[" << j + 1 << "]=F2(w.z,w.w);}\n";
         }
-        if (uses_lds) o << "extern __shared__ " << CT << " lds[];\n";
-        o << "const unsigned t = threadIdx.x;\n(void)basis; (void)part;\n";
-        o << "const unsigned long long tile = tile0 + blockIdx.x;\n";
-        o << "const unsigned long long base = " << scatter_expr("tile", glob, true) << ";\n";
-        o << "unsigned e = 0u, alive = 1u;\n";
-        o << "(void)base; (void)branch; (void)e; (void)alive;\n";
-        if (uses_lds) o << "const unsigned wt = t * " << ((1 << R) + 1) << "u;\n";
-        o << CT << " v[" << N << "];\n";
-        if (init_kind == 1) {
-            const std::string val = lit(std::pow(2.0, -0.5 * n));
-            for (int j = 0; j < N; ++j) o << "v[" << j << "]=" << MK << "(" << val << "," << ZERO << ");\n";
-        } else if (init_kind == 0 || init_kind == 2) {
-            o << "{const unsigned long long me = base | " << scatter_expr("t", tld, true) << ";\n";
-            for (int j = 0; j < N; ++j) {
-                uint64_t roff = 0;
-                for (int s = 0; s < R; ++s)
-                    if ((j >> s) & 1) roff |= 1ull << P.ld_phys[s];
-                o << "v[" << j << "]=" << MK << "((me | " << hex64(roff) << ") == basis ? " << lit(1.0)
-                  << " : " << ZERO << ", " << ZERO << ");\n";
-            }
-            o << "}\n";
-        } else if (dp) {
-            o << "{const v2d* src = (const v2d*)(a + (base | " << scatter_expr("t", tld, true) << "));\n";
-            for (int j = 0; j < N; ++j) {
-                uint64_t roff = 0;
-                for (int s = 0; s < R; ++s)
-                    if ((j >> s) & 1) roff |= 1ull << P.ld_phys[s];
-                o << "{const v2d w = __builtin_nontemporal_load(src + " << hex64(roff) << ");v[" << j
-                  << "]=D2(w.x,w.y);}\n";
-            }
-            o << "}\n";
+        o << "}\n";
+    }
+    void emit_store(const std::vector<int> &tst) {
+        if (dp) {
+            o << "{v2d* dst = (v2d*)(a + (bst | " << scatter_expr("t", tst, true) << "));\n";
+            for (int j = 0; j < N; ++j)
+                o << "{const v2d w = {v[" << j << "].x,v[" << j << "].y};__builtin_nontemporal_store(w, dst + "
+                  << hex64(reg_offset(j, P.st_phys, 0)) << ");}\n";
         } else {
-            o << "{const v4f* src = (const v4f*)(a + (base | " << scatter_expr("t", tld, true) << "));\n";
-            for (int j = 0; j < N; j += 2) {
-                uint64_t roff = 0;
-                for (int s = 1; s < R; ++s)
-                    if ((j >> s) & 1) roff |= 1ull << P.ld_phys[s];
-                o << "{const v4f w = __builtin_nontemporal_load(src + " << hex64(roff / 2) << ");v[" << j
-                  << "]=F2(w.x,w.y);v[" << j + 1 << "]=F2(w.z,w.w);}\n";
-            }
-            o << "}\n";
+            o << "{v4f* dst = (v4f*)(a + (bst | " << scatter_expr("t", tst, true) << "));\n";
+            for (int j = 0; j < N; j += 2)
+                o << "{const v4f w = {v[" << j << "].x,v[" << j << "].y,v[" << j + 1 << "].x,v[" << j + 1
+                  << "].y};__builtin_nontemporal_store(w, dst + " << hex64(reg_offset(j, P.st_phys, 1) / 2)
+                  << ");}\n";
         }
+        o << "}\n";
+    }
+    // FP64 |amp|^2 of the tile into part[tile]: products of FP32 values are
+    // exact in FP64; fixed order: registers, then an xor butterfly over the
+    // wave, then the waves of the workgroup in index order.  In a loop the
+    // reduction buffer alternates between two halves so that a wave of the
+    // next tile cannot overwrite a value thread 0 has not read yet.
+    void emit_norm(bool loop) {
+        o << "{double acc = 0.0;\n";
+        for (int j = 0; j < N; ++j)
+            o << "acc += (double)v[" << j << "].x*(double)v[" << j << "].x + (double)v[" << j << "].y*(double)v["
+              << j << "].y;\n";
+        const int waves = (1 << T) >= 64 ? (1 << T) / 64 : 1;
+        const int width = (1 << T) >= 64 ? 64 : (1 << T);
+        for (int off = width / 2; off >= 1; off /= 2)
+            o << "acc += __shfl_xor(acc, " << off << ", " << width << ");\n";
+        o << "__shared__ double red[" << 2 * waves << "];\n";
+        const std::string half = loop ? "(unsigned(it & 1u) * " + std::to_string(waves) + "u)" : "0u";
+        o << "if ((t & " << (width - 1) << "u) == 0u) red[" << half << " + t / " << width << "u] = acc;\n";
+        o << "__syncthreads();\nif (t == 0u) {double s = 0.0;\n";
+        for (int w = 0; w < waves; ++w) o << "s += red[" << half << " + " << w << "u];\n";
+        o << "part[tile] = s;}\n}\n";
+    }
+    void emit_ops() {
         bool scaled = false;
         for (int pc = 0; pc < P.n_ops; ++pc) {
             const uint64_t op = P.ops[pc];
@@ -480,44 +605,89 @@ struct Gen {
             }
         }
         if (!scaled) materialize(1.0, 0.0);
-        if (dp) {
-            o << "{v2d* dst = (v2d*)(a + (base | " << scatter_expr("t", tst, true) << "));\n";
-            for (int j = 0; j < N; ++j) {
-                uint64_t roff = 0;
-                for (int s = 0; s < R; ++s)
-                    if ((j >> s) & 1) roff |= 1ull << P.st_phys[s];
-                o << "{const v2d w = {v[" << j << "].x,v[" << j << "].y};__builtin_nontemporal_store(w, dst + "
-                  << hex64(roff) << ");}\n";
-            }
+    }
+    void emit_init(int init_kind, int n, const std::vector<int> &tld) {
+        if (init_kind == 1) {
+            const std::string val = lit(std::pow(2.0, -0.5 * n));
+            for (int j = 0; j < N; ++j) o << "v[" << j << "]=" << MK << "(" << val << "," << ZERO << ");\n";
         } else {
-        o << "{v4f* dst = (v4f*)(a + (base | " << scatter_expr("t", tst, true) << "));\n";
-        for (int j = 0; j < N; j += 2) {
-            uint64_t roff = 0;
-            for (int s = 1; s < R; ++s)
-                if ((j >> s) & 1) roff |= 1ull << P.st_phys[s];
-            o << "{const v4f w = {v[" << j << "].x,v[" << j << "].y,v[" << j + 1 << "].x,v[" << j + 1
-              << "].y};__builtin_nontemporal_store(w, dst + " << hex64(roff / 2) << ");}\n";
-        }
-        }
-        o << "}\n";
-        if (norm) {
-            // FP64 |amp|^2: products of FP32 values are exact in FP64; fixed
-            // order: registers, then an xor butterfly over the wave, then the
-            // waves of the workgroup in index order.
-            o << "{double acc = 0.0;\n";
+            o << "{const unsigned long long me = base | " << scatter_expr("t", tld, true) << ";\n";
             for (int j = 0; j < N; ++j)
-                o << "acc += (double)v[" << j << "].x*(double)v[" << j << "].x + (double)v[" << j
-                  << "].y*(double)v[" << j << "].y;\n";
-            const int waves = (1 << T) >= 64 ? (1 << T) / 64 : 1;
-            const int width = (1 << T) >= 64 ? 64 : (1 << T);
-            for (int off = width / 2; off >= 1; off /= 2)
-                o << "acc += __shfl_xor(acc, " << off << ", " << width << ");\n";
-            o << "__shared__ double red[" << waves << "];\n";
-            o << "if ((t & " << (width - 1) << "u) == 0u) red[t / " << width << "u] = acc;\n";
-            o << "__syncthreads();\nif (t == 0u) {double s = 0.0;\n";
-            for (int w = 0; w < waves; ++w) o << "s += red[" << w << "];\n";
-            o << "part[tile] = s;}\n}\n";
+                o << "v[" << j << "]=" << MK << "((me | " << hex64(reg_offset(j, P.ld_phys, 0)) << ") == basis ? "
+                  << lit(1.0) << " : " << ZERO << ", " << ZERO << ");\n";
+            o << "}\n";
         }
+    }
+
+    // init_kind: -1 = load the state; 0/1/2 = generate |0>, |+>^n or |basis>
+    // in registers (first pass of sv_simulate).  norm: accumulate the FP64
+    // sum of |amp|^2 of the tile into part[tile] after the store.
+    // batched: the state pointer and branch come from an entry table indexed
+    // by blockIdx.y (all entries share this plan).
+    // loop: each workgroup walks the tiles tile0 + blockIdx.x, + gridDim.x,
+    // ... below tile0 + ntile, loading the next tile into a second register
+    // set while it computes the current one.
+    std::string emit(const std::string &name, bool &uses_lds, int init_kind = -1, bool norm = false,
+                     int n = 0, bool batched = false, bool loop = false) {
+        uses_lds = false;
+        for (int pc = 0; pc < P.n_ops; ++pc) {
+            if ((P.ops[pc] & 0xff) == OP_XCHG) { uses_lds = true; ++pc; }
+        }
+        std::vector<int> glob(P.glob_bits, P.glob_bits + P.n_glob);
+        std::vector<int> globst(P.glob_st, P.glob_st + P.n_glob);
+        std::vector<int> tld, tst;
+        for (int u = 0; u < T; ++u) { tld.push_back(P.ld_phys[R + u]); tst.push_back(P.st_phys[R + u]); }
+        o << "extern \"C\" __global__ void __launch_bounds__(" << (1 << T) << ") " << name;
+        if (batched) {
+            o << "(const BatchEntryJ* __restrict__ ents, unsigned long long tile0) {\n";
+            o << "const BatchEntryJ en = ents[blockIdx.y];\n";
+            o << CT << "* a = (" << CT << "*)en.amps;\n";
+            o << "const " << CT << "* srcp = a;\n";
+            o << "const unsigned long long branch = en.branch, basis = 0ull;\n";
+            o << "double* part = nullptr;\n";
+        } else {
+            // srcp == a for passes that work in place
+            o << "(const " << CT << "* srcp, " << CT << "* a, unsigned long long branch, unsigned long long tile0, "
+                 "unsigned long long basis, double* __restrict__ part, unsigned long long ntile) {\n";
+        }
+        if (uses_lds) o << "extern __shared__ " << CT << " lds[];\n";
+        o << "const unsigned t = threadIdx.x;\n(void)basis; (void)part; (void)branch; (void)srcp;\n";
+        if (!loop) {
+            o << "const unsigned long long tile = tile0 + blockIdx.x;\n";
+            o << "const unsigned long long base = " << scatter_expr("tile", glob, true) << ";\n";
+            o << "const unsigned long long bst = " << scatter_expr("tile", globst, true) << ";\n";
+            o << CT << " v[" << N << "];\n";
+            if (init_kind >= 0) emit_init(init_kind, n, tld);
+            else emit_load("v", "base", tld);
+        } else {
+            const bool pre = init_kind < 0;
+            o << "const unsigned long long tend = tile0 + ntile;\n";
+            o << "unsigned long long tile = tile0 + blockIdx.x;\n";
+            if (pre) {
+                o << CT << " nx[" << N << "];\n";
+                o << "if (tile < tend) {const unsigned long long nb = " << scatter_expr("tile", glob, true) << ";\n";
+                emit_load("nx", "nb", tld);
+                o << "}\n";
+            }
+            o << "for (unsigned it = 0u; tile < tend; tile += gridDim.x, ++it) {\n";
+            o << "const unsigned long long base = " << scatter_expr("tile", glob, true) << ";\n";
+            o << "const unsigned long long bst = " << scatter_expr("tile", globst, true) << ";\n";
+            o << CT << " v[" << N << "];\n";
+            if (pre) {
+                for (int j = 0; j < N; ++j) o << "v[" << j << "]=nx[" << j << "];\n";
+                o << "{const unsigned long long nt = tile + gridDim.x;\nif (nt < tend) {"
+                  << "const unsigned long long nb = " << scatter_expr("nt", glob, true) << ";\n";
+                emit_load("nx", "nb", tld);
+                o << "}}\n";
+            } else {
+                emit_init(init_kind, n, tld);
+            }
+        }
+        o << "unsigned e = 0u, alive = 1u;\n(void)e; (void)alive;\n";
+        emit_ops();
+        emit_store(tst);
+        if (norm) emit_norm(loop);
+        if (loop) o << "}\n";
         o << "}\n";
         return o.str();
     }
@@ -527,6 +697,7 @@ struct CacheEntry {
     hipModule_t mod = nullptr;
     std::vector<hipFunction_t> fns;
     std::vector<size_t> lds;
+    std::vector<unsigned> resident;  // workgroups of each pass kernel the device holds at once
     double compile_s = 0;
 };
 
@@ -572,16 +743,14 @@ std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int var
     const bool norm = (variant & 8) != 0;
     const bool dp = (variant & kJitDouble) != 0;
     const bool batched = (variant & kJitBatched) != 0;
+    const bool loop = (variant & kJitLoop) != 0 && !batched;
     std::string src = kPrelude;
     for (size_t p = 0; p < plan.passes.size(); ++p) {
         Gen g(plan.passes[p].prog, plan.R, plan.T, dp);
         bool uses_lds = false;
         src += g.emit("qsv_pass_" + std::to_string(p), uses_lds, p == 0 ? init_kind : -1,
-                      norm && !batched && p + 1 == plan.passes.size(), plan.n, batched);
-        if (lds_bytes)
-            lds_bytes->push_back(uses_lds ? ((size_t(1) << (plan.R + plan.T)) + (size_t(1) << plan.T)) *
-                                                (dp ? 16 : 8)
-                                          : 0);
+                      norm && !batched && p + 1 == plan.passes.size(), plan.n, batched, loop);
+        if (lds_bytes) lds_bytes->push_back(uses_lds ? size_t(g.lds_elems) * (dp ? 16 : 8) : 0);
     }
     return src;
 }
@@ -593,6 +762,8 @@ qsv_status jit_compile_only(const Plan &plan, size_t *code_bytes, double *second
     auto t0 = std::chrono::steady_clock::now();
     // the complex128 instantiation must compile too
     qsv_status st = compile_source(jit_source(plan, &lds, kJitDouble | kJitInit | 1 | kJitNorm), code, log);
+    if (st != QSV_OK) return st;
+    st = compile_source(jit_source(plan, &lds, kJitInit | 1 | kJitNorm | kJitLoop), code, log);
     if (st != QSV_OK) return st;
     std::string src = jit_source(plan, &lds, kJitInit | 1 | kJitNorm);
     st = compile_source(src, code, log);
@@ -629,6 +800,14 @@ qsv_status jit_prepare(Plan &plan, int variant) {
             if (he != hipSuccess)
                 return fail(QSV_EHIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(he));
             e->fns.push_back(f);
+            int per_cu = 0, cus = 0;
+            he = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 1 << plan.T, lds[p]);
+            if (he != hipSuccess)
+                return fail(QSV_EHIP, std::string("occupancy query: ") + hipGetErrorString(he));
+            he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            if (he != hipSuccess)
+                return fail(QSV_EHIP, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(he));
+            e->resident.push_back(unsigned(std::max(1, per_cu) * std::max(1, cus)));
         }
         e->lds = lds;
         e->compile_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -639,26 +818,36 @@ qsv_status jit_prepare(Plan &plan, int variant) {
     return QSV_OK;
 }
 
-qsv_status jit_launch(const Plan &plan, int variant, void *amps, uint64_t branch, uint64_t basis,
-                      double *part, hipStream_t s) {
+qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, uint64_t branch,
+                      uint64_t basis, double *part, hipStream_t s) {
     auto vit = plan.jit_variants.find(variant);
     if (vit == plan.jit_variants.end()) return fail(QSV_EINTERNAL, "jit variant not prepared");
     const CacheEntry &e = *static_cast<const CacheEntry *>(vit->second.get());
     const int L = plan.R + plan.T;
     const uint64_t tiles = 1ull << (plan.n - L);
     const uint64_t chunk = 1ull << 30;
-    for (size_t p = 0; p < plan.passes.size(); ++p) {
+    const size_t np = plan.passes.size();
+    if (plan.oop && (!scratch || (!(variant & kJitInit) && np % 2)))
+        return fail(QSV_EINTERNAL, "out-of-place plan without a usable buffer schedule");
+    // Out-of-place plans alternate between the two buffers so that the last
+    // pass writes the caller's: pass p writes amps when np - p is odd.
+    void *in = amps;
+    for (size_t p = 0; p < np; ++p) {
+        void *outb = (!plan.oop || (np - p) % 2 == 1) ? amps : scratch;
         for (uint64_t t0 = 0; t0 < tiles; t0 += chunk) {
             const uint64_t cnt = (tiles - t0 < chunk) ? tiles - t0 : chunk;
-            unsigned long long br = branch, tt = t0, bs = basis;
-            void *a = amps;
+            unsigned long long br = branch, tt = t0, bs = basis, nt = cnt;
+            void *src = in, *dst = outb;
             double *pt = part;
-            void *args[] = {&a, &br, &tt, &bs, &pt};
-            hipError_t he = hipModuleLaunchKernel(e.fns[p], unsigned(cnt), 1, 1, 1u << plan.T, 1, 1,
+            void *args[] = {&src, &dst, &br, &tt, &bs, &pt, &nt};
+            // a looping kernel gets as many workgroups as the device holds at once
+            const uint64_t grid = (variant & kJitLoop) ? std::min<uint64_t>(cnt, e.resident[p]) : cnt;
+            hipError_t he = hipModuleLaunchKernel(e.fns[p], unsigned(grid), 1, 1, 1u << plan.T, 1, 1,
                                                   unsigned(e.lds[p]), s, args, nullptr);
             if (he != hipSuccess)
                 return fail(QSV_EHIP, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(he));
         }
+        in = outb;
     }
     return QSV_OK;
 }

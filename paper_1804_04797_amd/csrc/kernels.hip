@@ -166,7 +166,7 @@ __device__ __forceinline__ void fused_tile(float2 *__restrict__ amps, const Pass
     constexpr int N = 1 << R;
     const uint32_t t = threadIdx.x;
 
-    uint64_t base = 0;
+    uint64_t base = 0;  // tile origin in the map the pass reads
     for (int i = 0; i < P.n_glob; ++i) base |= ((tile >> i) & 1ull) << P.glob_bits[i];
 
     float2 v[N];
@@ -295,11 +295,13 @@ __device__ __forceinline__ void fused_tile(float2 *__restrict__ amps, const Pass
     } while (++pc < P.n_ops);
 
     {
+        uint64_t bst = 0;  // tile origin in the map the pass writes
+        for (int i = 0; i < P.n_glob; ++i) bst |= ((tile >> i) & 1ull) << P.glob_st[i];
         uint64_t toff = 0;
 #pragma unroll
         for (int u = 0; u < T; ++u)
             if ((t >> u) & 1u) toff |= 1ull << P.st_phys[R + u];
-        float2 *dst = amps + (base | toff);
+        float2 *dst = amps + (bst | toff);
 #pragma unroll
         for (int j = 0; j < N; j += 2) {
             uint64_t roff = 0;

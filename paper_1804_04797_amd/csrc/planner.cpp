@@ -19,6 +19,7 @@
 // state is exact (up to rounding) after every pass.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -50,6 +51,9 @@ TileShape default_shape(int n) {
 
 namespace {
 
+// Thread slots hold the lowest resident index bits at load and store.
+constexpr bool kLanesLow = true;
+
 struct G {
     uint8_t kind;
     int q0, q1;   // q1 = -1 for single-qubit gates
@@ -59,6 +63,7 @@ struct G {
 
 struct DepGraph {
     std::vector<G> g;
+    std::vector<double> w;  // selection weight of each gate
     std::vector<std::vector<int>> succ;
     std::vector<int> npred;
 };
@@ -111,7 +116,7 @@ DepGraph build_deps(const qsv_circuit &c, const std::vector<int> &idx) {
 
 // Gates (in a valid order) that one pass with resident set `res` can apply,
 // given the current done flags and pending-predecessor counts.
-int simulate_pass(const DepGraph &d, const std::vector<char> &done, const std::vector<int> &pend,
+double simulate_pass(const DepGraph &d, const std::vector<char> &done, const std::vector<int> &pend,
                   uint64_t res, std::vector<int> *order) {
     std::vector<int> p = pend;
     std::vector<char> dn = done;
@@ -120,8 +125,7 @@ int simulate_pass(const DepGraph &d, const std::vector<char> &done, const std::v
     for (size_t i = 0; i < d.g.size(); ++i)
         if (!dn[i] && p[i] == 0) ready.push_back(int(i));
     std::make_heap(ready.begin(), ready.end(), std::greater<int>());
-    int count = 0;
-    std::vector<int> blocked;
+    double count = 0;
     while (!ready.empty()) {
         std::pop_heap(ready.begin(), ready.end(), std::greater<int>());
         int i = ready.back();
@@ -129,7 +133,7 @@ int simulate_pass(const DepGraph &d, const std::vector<char> &done, const std::v
         const G &x = d.g[i];
         if (x.nd && !((res >> x.q0) & 1)) continue;  // blocked for this pass
         dn[i] = 1;
-        ++count;
+        count += d.w[i];
         if (order) order->push_back(i);
         for (int s : d.succ[i]) {
             if (--p[s] == 0) {
@@ -154,10 +158,11 @@ uint64_t choose_resident(const DepGraph &d, const std::vector<char> &done,
     std::vector<int> first(n);
     for (int q = 0; q < n; ++q) first[q] = first_pending_nd(d, done, q);
     while (size < L) {
-        int best_q = -1, best_gain = -1, best_first = 0;
+        int best_q = -1, best_first = 0;
+        double best_gain = -1;
         for (int q = 0; q < n; ++q) {
             if ((S >> q) & 1) continue;
-            int gain = simulate_pass(d, done, pend, S | (1ull << q), nullptr);
+            double gain = simulate_pass(d, done, pend, S | (1ull << q), nullptr);
             if (gain > best_gain || (gain == best_gain && first[q] < best_first)) {
                 best_gain = gain;
                 best_q = q;
@@ -168,7 +173,7 @@ uint64_t choose_resident(const DepGraph &d, const std::vector<char> &done,
         ++size;
     }
     // hill climbing: swap one non-forced member for one outsider
-    int cur = simulate_pass(d, done, pend, S, nullptr);
+    double cur = simulate_pass(d, done, pend, S, nullptr);
     for (int iter = 0; iter < 4; ++iter) {
         bool improved = false;
         for (int a = 0; a < n && !improved; ++a) {
@@ -176,7 +181,7 @@ uint64_t choose_resident(const DepGraph &d, const std::vector<char> &done,
             for (int b = 0; b < n; ++b) {
                 if ((S >> b) & 1) continue;
                 uint64_t S2 = (S & ~(1ull << a)) | (1ull << b);
-                int v = simulate_pass(d, done, pend, S2, nullptr);
+                double v = simulate_pass(d, done, pend, S2, nullptr);
                 if (v > cur) {
                     S = S2;
                     cur = v;
@@ -210,14 +215,21 @@ struct ProgBuilder {
     }
 };
 
-uint8_t locator(const Slots &sl, int q) {
+// slot of a resident qubit, else its physical bit (tile-index bit) at load
+uint8_t locator(const Slots &sl, const int *phys, int q) {
     int s = sl.where[q];
-    return s >= 0 ? uint8_t(s) : uint8_t(kLocGlobal | q);
+    return s >= 0 ? uint8_t(s) : uint8_t(kLocGlobal | phys[q]);
 }
 
 }  // namespace
 
-qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Plan &out) {
+namespace {
+
+// One plan.  The resident set of each pass maximises the summed weight of
+// the gates the pass can apply; gate i of the range weighs
+// 1 + lambda * (1 - i / count), so lambda > 0 favours finishing old gates.
+qsv_status build_plan_weighted(const qsv_circuit &c, int lb, int le, TileShape shape, double lambda,
+                               Plan &out) {
     const int n = c.n;
     const int R = shape.R, T = shape.T, L = R + T, cl = shape.c;
     if (R < 1 || T < 1 || L > n || L > kMaxSlots || cl < 1 || cl - 1 > T || cl > L)
@@ -225,25 +237,51 @@ qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Pla
     out.passes.clear();
     out.gate_range.clear();
     out.jit_variants.clear();
-    out.n = n; out.R = R; out.T = T; out.c = cl;
+    out.n = n; out.R = R; out.T = T; out.c = cl; out.oop = shape.oop;
     gates_in_range(c, lb, le, out.gate_range);
     const std::vector<int> &idx = out.gate_range;
     DepGraph d = build_deps(c, idx);
+    d.w.resize(d.g.size());
+    for (size_t i = 0; i < d.g.size(); ++i)
+        d.w[i] = 1.0 + lambda * (1.0 - double(i) / double(d.g.size()));
     const size_t NG = idx.size();
     std::vector<char> done(NG, 0);
     std::vector<int> pend = d.npred;
     size_t n_done = 0;
-    // The low cl index bits are resident in every pass (contiguous runs).
-    const uint64_t forced = (cl >= 64) ? ~0ull : ((1ull << cl) - 1);
+    // Qubit-to-bit map.  Every pass reads the state under the current map
+    // and may write it under another one: the next pass's resident qubits
+    // are placed at the lowest physical bits, so that its tiles are compact
+    // blocks of memory.  The call starts and ends in the natural map.  The
+    // qubits at physical bits 0..cl-1 are resident in the pass that writes
+    // that map and in the pass that reads it, so every access is a run of
+    // 2^cl contiguous amplitudes (bit 0 pairs two amplitudes per 16-byte
+    // access).
+    int phys[64], qat[64];
+    for (int q = 0; q < n; ++q) phys[q] = qat[q] = q;
+    const uint64_t natural = (cl >= 64) ? ~0ull : ((1ull << cl) - 1);
+    auto completes = [&](uint64_t Sx) {  // one pass over Sx applies every remaining gate
+        std::vector<int> ord;
+        simulate_pass(d, done, pend, Sx, &ord);
+        return ord.size() == NG - n_done;
+    };
     int total_phase = 0;  // exponent of w = e^{i pi/4} removed so far
     int carry_half = 0;   // removed factors of 2^{-1/2} not yet applied
+    bool final_scaled = false;
 
-    while (n_done < NG) {
-        uint64_t S = choose_resident(d, done, pend, n, L, forced);
+    if (NG == 0) return QSV_OK;
+    uint64_t S = choose_resident(d, done, pend, n, L, natural);
+    for (;;) {
+        const bool natural_now = [&] {
+            for (int q = 0; q < n; ++q)
+                if (phys[q] != q) return false;
+            return true;
+        }();
+        if (n_done == NG && natural_now && final_scaled) break;
         // --- slot assignment at load time -----------------------------------
-        // slot 0 <- qubit 0 (physical bit 0, the pair inside one 16-byte load);
-        // thread slots 0..cl-2 <- qubits 1..cl-1; the other resident qubits go
-        // to register slots first by their first non-diagonal use in the pass.
+        // slot 0 <- the qubit at bit 0; thread slots 0..cl-2 <- the qubits at
+        // bits 1..cl-1; with kLanesLow the other thread slots take the lowest
+        // remaining bits and the registers the highest, in order of first
+        // non-diagonal use in the pass.
         std::vector<int> porder;
         simulate_pass(d, done, pend, S, &porder);
         std::vector<int> first_use(n, 1 << 30);
@@ -255,29 +293,37 @@ qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Pla
         sl.R = R; sl.T = T; sl.L = L;
         std::fill(sl.where, sl.where + 64, -1);
         std::fill(sl.occ, sl.occ + kMaxSlots, -1);
-        sl.set(0, 0);
-        for (int u = 0; u < cl - 1; ++u) sl.set(R + u, u + 1);
+        sl.set(0, qat[0]);
+        for (int u = 0; u < cl - 1; ++u) sl.set(R + u, qat[u + 1]);
         std::vector<int> rest;
-        for (int q = cl; q < n; ++q)
-            if ((S >> q) & 1) rest.push_back(q);
-        std::stable_sort(rest.begin(), rest.end(),
-                         [&](int a, int b) { return first_use[a] < first_use[b]; });
-        {
+        for (int b = cl; b < n; ++b)
+            if ((S >> qat[b]) & 1) rest.push_back(qat[b]);  // ascending physical bit
+        if (kLanesLow) {
             size_t k = 0;
-            for (int s = 1; s < R && k < rest.size(); ++s) sl.set(s, rest[k++]);
+            for (int u = cl - 1; u < T && k < rest.size(); ++u) sl.set(R + u, rest[k++]);
+            std::vector<int> hi(rest.begin() + k, rest.end());
+            std::stable_sort(hi.begin(), hi.end(),
+                             [&](int a, int b) { return first_use[a] < first_use[b]; });
+            for (int s2 = 1; s2 < R && size_t(s2 - 1) < hi.size(); ++s2) sl.set(s2, hi[s2 - 1]);
+        } else {
+            std::stable_sort(rest.begin(), rest.end(),
+                             [&](int a, int b) { return first_use[a] < first_use[b]; });
+            size_t k = 0;
+            for (int s2 = 1; s2 < R && k < rest.size(); ++s2) sl.set(s2, rest[k++]);
+            std::sort(rest.begin() + k, rest.end(), [&](int a, int b) { return phys[a] < phys[b]; });
             for (int u = cl - 1; u < T && k < rest.size(); ++u) sl.set(R + u, rest[k++]);
         }
         Pass pass;
         PassProg &P = pass.prog;
         std::memset(&P, 0, sizeof(P));
         pass.resident_logical = S;
-        for (int s = 0; s < L; ++s) P.ld_phys[s] = uint8_t(sl.occ[s]);
-        {
-            int k = 0;
-            for (int q = 0; q < n; ++q)
-                if (!((S >> q) & 1)) P.glob_bits[k++] = uint8_t(q);
-            P.n_glob = k;
-        }
+        for (int s2 = 0; s2 < L; ++s2) P.ld_phys[s2] = uint8_t(phys[sl.occ[s2]]);
+        // tile-index bit i <- the i-th non-resident qubit in physical order
+        std::vector<int> tq;
+        for (int b = 0; b < n; ++b)
+            if (!((S >> qat[b]) & 1)) tq.push_back(qat[b]);
+        P.n_glob = int(tq.size());
+        for (size_t i = 0; i < tq.size(); ++i) P.glob_bits[i] = uint8_t(phys[tq[i]]);
 
         // --- list scheduling with register-slot exchanges -------------------
         std::vector<char> dn = done;
@@ -306,14 +352,14 @@ qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Pla
                     case QSV_SY: pb.op(make_op(OP_SY, sl.where[x.q0])); ++m_nd; phase += 1; break;
                     case QSV_SXDG: pb.op(make_op(OP_SXDG, sl.where[x.q0])); ++m_nd; phase += 7; break;
                     case QSV_SYDG: pb.op(make_op(OP_SYDG, sl.where[x.q0])); ++m_nd; phase += 7; break;
-                    case QSV_T: pb.op(make_op(OP_PHASE, locator(sl, x.q0), 1)); break;
-                    case QSV_TDG: pb.op(make_op(OP_PHASE, locator(sl, x.q0), 7)); break;
-                    case QSV_Z: pb.op(make_op(OP_PHASE, locator(sl, x.q0), 4)); break;
-                    case QSV_CZ: pb.op(make_op(OP_CZ, locator(sl, x.q0), locator(sl, x.q1))); break;
-                    case QSV_P0: pb.op(make_op(OP_PROJ, locator(sl, x.q0), 0, 0)); break;
-                    case QSV_P1: pb.op(make_op(OP_PROJ, locator(sl, x.q0), 1, 0)); break;
-                    case QSV_PB: pb.op(make_op(OP_PROJ, locator(sl, x.q0), x.arg, 1)); break;
-                    case QSV_ZB: pb.op(make_op(OP_ZB, locator(sl, x.q0), x.arg)); break;
+                    case QSV_T: pb.op(make_op(OP_PHASE, locator(sl, phys, x.q0), 1)); break;
+                    case QSV_TDG: pb.op(make_op(OP_PHASE, locator(sl, phys, x.q0), 7)); break;
+                    case QSV_Z: pb.op(make_op(OP_PHASE, locator(sl, phys, x.q0), 4)); break;
+                    case QSV_CZ: pb.op(make_op(OP_CZ, locator(sl, phys, x.q0), locator(sl, phys, x.q1))); break;
+                    case QSV_P0: pb.op(make_op(OP_PROJ, locator(sl, phys, x.q0), 0, 0)); break;
+                    case QSV_P1: pb.op(make_op(OP_PROJ, locator(sl, phys, x.q0), 1, 0)); break;
+                    case QSV_PB: pb.op(make_op(OP_PROJ, locator(sl, phys, x.q0), x.arg, 1)); break;
+                    case QSV_ZB: pb.op(make_op(OP_ZB, locator(sl, phys, x.q0), x.arg)); break;
                     default: return fail(QSV_EINTERNAL, "planner: unknown gate kind");
                     }
                     dn[i] = 1;
@@ -373,56 +419,119 @@ qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Pla
             std::copy(sl.occ, sl.occ + L, occ_old);
             for (int s = 0; s < L; ++s) sl.set(s, occ_old[perm[s]]);
         }
-        // --- restore the coalesced layout of qubits 0..cl-1 for the store ---
-        {
-            bool ok = sl.occ[0] == 0;
-            for (int u = 0; u < cl - 1; ++u) ok = ok && sl.occ[R + u] == u + 1;
-            if (!ok) {
-                int target[kMaxSlots];   // new slot -> qubit
-                for (int s = 0; s < L; ++s) target[s] = -1;
-                target[0] = 0;
-                for (int u = 0; u < cl - 1; ++u) target[R + u] = u + 1;
-                std::vector<int> others;
-                for (int s = 0; s < L; ++s)
-                    if (sl.occ[s] >= cl) others.push_back(sl.occ[s]);
-                // keep others in place where possible
-                std::vector<char> used(L, 0);
-                for (int s = 0; s < L; ++s)
-                    if (target[s] >= 0) used[s] = 1;
-                std::vector<int> homeless;
-                for (int q : others) {
-                    int s = sl.where[q];
-                    if (!used[s]) { target[s] = q; used[s] = 1; }
-                    else homeless.push_back(q);
-                }
-                size_t h = 0;
-                for (int s = 0; s < L; ++s)
-                    if (!used[s]) { target[s] = homeless[h++]; used[s] = 1; }
-                int perm[kMaxSlots];
-                for (int s = 0; s < L; ++s) perm[s] = sl.where[target[s]];
-                pb.xchg(perm, L);
-                int occ_old[kMaxSlots];
-                std::copy(sl.occ, sl.occ + L, occ_old);
-                for (int s = 0; s < L; ++s) sl.set(s, occ_old[perm[s]]);
-            }
-        }
-        for (int s = 0; s < L; ++s) P.st_phys[s] = uint8_t(sl.occ[s]);
-        if (sched.empty())
+        if (sched.empty() && n_done < NG)
             return fail(QSV_EINTERNAL, "planner made no progress");
         // commit the scheduled gates
         for (int i : sched) {
             done[i] = 1;
             ++n_done;
-            for (int s : d.succ[i]) --pend[s];
+            for (int s2 : d.succ[i]) --pend[s2];
         }
+
+        // --- resident set of the next pass and the map this pass writes -----
+        int nphys[64];
+        uint64_t S_next = 0;
+        if (!shape.oop) {
+            // in place: the tile a pass writes is the tile it read
+            for (int q = 0; q < n; ++q) nphys[q] = q;
+            if (n_done < NG) S_next = choose_resident(d, done, pend, n, L, natural);
+        } else if (n_done == NG && (S & natural) == natural) {
+            for (int q = 0; q < n; ++q) nphys[q] = q;  // final store in natural order
+        } else {
+            // anchors: cl qubits resident now and in the next pass
+            uint64_t Sf = (n_done < NG) ? choose_resident(d, done, pend, n, L, 0) : natural;
+            std::vector<int> anchor;
+            for (int b = 0; b < n && int(anchor.size()) < cl; ++b)
+                if (((S & Sf) >> qat[b]) & 1) anchor.push_back(qat[b]);
+            for (int b = 0; b < n && int(anchor.size()) < cl; ++b)  // top up from S
+                if (((S & ~Sf) >> qat[b]) & 1) anchor.push_back(qat[b]);
+            uint64_t A = 0;
+            for (int q : anchor) A |= 1ull << q;
+            S_next = ((Sf & A) == A) ? Sf : choose_resident(d, done, pend, n, L, A);
+            if (n_done < NG && completes(S_next) && (S_next & natural) != natural) {
+                // a last pass must also hold the natural low bits for its store
+                const uint64_t S2 = choose_resident(d, done, pend, n, L, A | natural);
+                if (completes(S2)) S_next = S2;
+            }
+            if (n_done == NG) S_next = choose_resident(d, done, pend, n, L, A | natural);
+            // new map from bit 0 up: the anchors, the other qubits resident in
+            // both passes, then alternately one resident only in the next pass
+            // (its load) and one resident only now (this store), then the rest
+            std::vector<int> both, next_only, now_only, other;
+            std::vector<char> is_anchor(n, 0);
+            for (int q : anchor) is_anchor[q] = 1;
+            for (int bb = 0; bb < n; ++bb) {
+                const int q = qat[bb];
+                if (is_anchor[q]) continue;
+                const bool nx = (S_next >> q) & 1, now = (S >> q) & 1;
+                (nx && now ? both : nx ? next_only : now ? now_only : other).push_back(q);
+            }
+            std::vector<int> order(anchor);
+            order.insert(order.end(), both.begin(), both.end());
+            for (size_t i = 0; i < std::max(next_only.size(), now_only.size()); ++i) {
+                if (i < next_only.size()) order.push_back(next_only[i]);
+                if (i < now_only.size()) order.push_back(now_only[i]);
+            }
+            order.insert(order.end(), other.begin(), other.end());
+            for (int b = 0; b < n; ++b) nphys[order[b]] = b;
+        }
+        int nqat[64];
+        for (int q = 0; q < n; ++q) nqat[nphys[q]] = q;
+
+        // --- layout for the store ----------------------------------------------
+        // slot 0 <- the qubit written to bit 0, thread slots 0..cl-2 <- those
+        // written to bits 1..cl-1; with kLanesLow the other thread slots take
+        // the resident qubits with the lowest written bits.
+        {
+            int target[kMaxSlots];  // new slot -> qubit
+            for (int s2 = 0; s2 < L; ++s2) target[s2] = -1;
+            std::vector<char> used(L, 0), placed(n, 0);
+            target[0] = nqat[0];
+            used[0] = 1;
+            placed[nqat[0]] = 1;
+            std::vector<int> res;  // resident qubits by written bit
+            for (int b = 1; b < n; ++b)
+                if ((S >> nqat[b]) & 1) res.push_back(nqat[b]);
+            const int fixed_thr = kLanesLow ? T : cl - 1;
+            for (int u = 0; u < fixed_thr && u < int(res.size()); ++u) {
+                target[R + u] = res[u];
+                used[R + u] = 1;
+                placed[res[u]] = 1;
+            }
+            // everything else stays in its slot where possible
+            std::vector<int> homeless;
+            for (int q : res) {
+                if (placed[q]) continue;
+                int s2 = sl.where[q];
+                if (!used[s2]) { target[s2] = q; used[s2] = 1; }
+                else homeless.push_back(q);
+            }
+            size_t h = 0;
+            for (int s2 = 0; s2 < L; ++s2)
+                if (!used[s2]) { target[s2] = homeless[h++]; used[s2] = 1; }
+            bool same = true;
+            for (int s2 = 0; s2 < L; ++s2) same = same && sl.occ[s2] == target[s2];
+            if (!same) {
+                int perm[kMaxSlots];
+                for (int s2 = 0; s2 < L; ++s2) perm[s2] = sl.where[target[s2]];
+                pb.xchg(perm, L);
+                int occ_old[kMaxSlots];
+                std::copy(sl.occ, sl.occ + L, occ_old);
+                for (int s2 = 0; s2 < L; ++s2) sl.set(s2, occ_old[perm[s2]]);
+            }
+        }
+        for (int s2 = 0; s2 < L; ++s2) P.st_phys[s2] = uint8_t(nphys[sl.occ[s2]]);
+        for (size_t i = 0; i < tq.size(); ++i) P.glob_st[i] = uint8_t(nphys[tq[i]]);
+
         total_phase = (total_phase + phase) & 7;
         // Intermediate passes apply the exact power of two of the removed
-        // 2^{-m/2}; an odd half power is carried to the call's last pass, which
-        // also applies the accumulated phase, so at most one inexact factor
-        // is rounded per call.
+        // 2^{-m/2}; an odd half power is carried to the pass that applies the
+        // last gates, which also applies the accumulated phase, so at most
+        // one inexact factor is rounded per call.
         carry_half += m_nd;
+        const bool last_gates = (n_done == NG) && !final_scaled;
         double mag;
-        if (n_done == NG) {
+        if (last_gates) {
             mag = std::pow(2.0, -0.5 * carry_half);
             carry_half = 0;
         } else {
@@ -430,7 +539,7 @@ qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Pla
             carry_half &= 1;
         }
         double sr = mag, si = 0.0;
-        if (n_done == NG) {
+        if (last_gates) {
             double ang = M_PI / 4.0 * total_phase;
             sr = mag * std::cos(ang);
             si = mag * std::sin(ang);
@@ -439,6 +548,7 @@ qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Pla
                 sr = mag * re[total_phase / 2];
                 si = mag * im[total_phase / 2];
             }
+            final_scaled = true;
         }
         P.scale_re = float(sr);
         P.scale_im = float(si);
@@ -451,6 +561,35 @@ qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Pla
         P.n_ops = int(pb.ops.size());
         for (int i : sched) pass.gates.push_back(idx[i]);
         out.passes.push_back(std::move(pass));
+        std::copy(nphys, nphys + n, phys);
+        std::copy(nqat, nqat + n, qat);
+        S = S_next;
+        if (out.passes.size() > 4 * NG + 8) return fail(QSV_EINTERNAL, "planner does not terminate");
+    }
+    return QSV_OK;
+}
+
+int exchanges(const Plan &p) {
+    int k = 0;
+    for (const Pass &x : p.passes)
+        for (int pc = 0; pc < x.prog.n_ops; ++pc)
+            if ((x.prog.ops[pc] & 0xff) == OP_XCHG) { ++k; ++pc; }
+    return k;
+}
+
+}  // namespace
+
+// The greedy selection is tried with a few gate weightings; the plan with
+// the fewest passes (then the fewest exchanges) is kept.
+qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Plan &out) {
+    static const double kLambda[] = {0.0, 0.5, 1.0};
+    qsv_status st = build_plan_weighted(c, lb, le, shape, kLambda[0], out);
+    if (st != QSV_OK) return st;
+    for (size_t k = 1; k < sizeof(kLambda) / sizeof(kLambda[0]); ++k) {
+        Plan alt;
+        if (build_plan_weighted(c, lb, le, shape, kLambda[k], alt) != QSV_OK) continue;
+        const size_t pa = alt.passes.size(), po = out.passes.size();
+        if (pa < po || (pa == po && exchanges(alt) < exchanges(out))) out.passes = std::move(alt.passes);
     }
     return QSV_OK;
 }

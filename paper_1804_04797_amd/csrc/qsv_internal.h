@@ -49,7 +49,8 @@ struct PassProg {
     uint64_t ops[kMaxOps];
     uint8_t ld_phys[kMaxSlots];   // physical bit of each slot when loading
     uint8_t st_phys[kMaxSlots];   // physical bit of each slot when storing
-    uint8_t glob_bits[48];        // non-resident physical bits, tile index bit i -> glob_bits[i]
+    uint8_t glob_bits[48];        // tile index bit i -> physical bit when loading
+    uint8_t glob_st[48];          // tile index bit i -> physical bit when storing
     float scale_re, scale_im;
     int32_t n_ops;
     int32_t n_glob;
@@ -78,8 +79,9 @@ struct Pass {
 
 struct PlanKey {
     int lb, le, R, T, c;
+    bool oop;
     bool operator<(const PlanKey &o) const {
-        return std::tie(lb, le, R, T, c) < std::tie(o.lb, o.le, o.R, o.T, o.c);
+        return std::tie(lb, le, R, T, c, oop) < std::tie(o.lb, o.le, o.R, o.T, o.c, o.oop);
     }
 };
 
@@ -107,6 +109,7 @@ struct DenseKey {
 
 struct Plan {
     int n = 0, R = 0, T = 0, c = 0;
+    bool oop = false;  // passes write a second buffer (free qubit-to-bit maps)
     std::vector<Pass> passes;
     std::vector<int> gate_range;  // indices of the gates in the layer range
     std::map<int, std::shared_ptr<void>> jit_variants;  // compiled kernels (jit.cpp)
@@ -136,7 +139,10 @@ qsv_status generate_lattice_circuit(int rows, int cols, const uint8_t *present, 
                                     uint64_t seed, qsv_circuit *out);
 
 // planner.cpp
-struct TileShape { int R, T, c; };
+// oop: every pass but the first reads one buffer and writes the other, so a
+// pass may write the state under any qubit-to-bit map; otherwise every pass
+// works in place in the natural map.
+struct TileShape { int R, T, c; bool oop = false; };
 qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Plan &out);
 TileShape default_shape(int n);
 void gates_in_range(const qsv_circuit &c, int lb, int le, std::vector<int> &idx);
@@ -149,6 +155,7 @@ qsv_status build_dense_plan(const qsv_circuit &c, int lb, int le, int k, uint64_
                             DensePlan &out);
 
 // emulate.cpp
-void emulate_pass(const PassProg &p, int n, int R, int T, uint64_t branch, float *amps);
+// src == dst for in-place passes
+void emulate_pass(const PassProg &p, int n, int R, int T, uint64_t branch, const float *src, float *dst);
 
 }  // namespace qsv

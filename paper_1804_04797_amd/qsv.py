@@ -40,7 +40,8 @@ class QsvError(RuntimeError):
 
 class FuseOpts(ctypes.Structure):
     _fields_ = [("reg_qubits", ctypes.c_int), ("thread_qubits", ctypes.c_int),
-                ("low_qubits", ctypes.c_int), ("plain", ctypes.c_int), ("jit", ctypes.c_int)]
+                ("low_qubits", ctypes.c_int), ("plain", ctypes.c_int), ("jit", ctypes.c_int),
+                ("out_of_place", ctypes.c_int)]
 
 
 _lib = None
@@ -323,7 +324,8 @@ def sv_tune(amps_scratch, c, layer_begin=0, layer_end=-1, stream=None):
     _check(lib().sv_tune(_ptr(amps_scratch), c, layer_begin, layer_end, ctypes.byref(o),
                          ctypes.byref(ms), _stream(stream)))
     return ({"reg_qubits": o.reg_qubits, "thread_qubits": o.thread_qubits,
-             "low_qubits": o.low_qubits, "plain": 0, "jit": 0}, ms.value)
+             "low_qubits": o.low_qubits, "plain": 0, "jit": o.jit,
+             "out_of_place": o.out_of_place}, ms.value)
 
 
 def sv_apply_dense(amps, c, k, branch=0, layer_begin=0, layer_end=-1, stream=None):

@@ -186,6 +186,39 @@ def test_plan_respects_dependencies(shape):
     assert 1 <= info["n_passes"] <= 25
 
 
+OOP_SHAPES = [(4, 6, 5), (3, 6, 4), (2, 3, 2), (3, 4, 3), (4, 7, 4), (5, 8, 4), (4, 6, 3)]
+
+
+@pytest.mark.parametrize("name", ["4x5-d10", "5x6-d16"])
+def test_emulated_out_of_place_plans(name):
+    """Out-of-place plans write every pass under a new qubit-to-bit map (the
+    next pass's qubits at the low bits) into the other buffer; emulated with
+    the device's buffer schedule, against the oracle.  A plan with an odd
+    pass count falls back to the in-place plan when the first pass reads the
+    state, so the shapes cover both cases."""
+    spec = workloads.WORKLOADS[name]
+    rows, cols = spec["rows"], spec["cols"]
+    depth = spec["depth"] if rows * cols <= 20 else 8
+    c = qsv.circuit_create(rows, cols, None, depth, spec["seed"])
+    n = rows * cols
+    if n > 20:  # a 20-qubit sub-lattice keeps the emulation quick
+        c = qsv.circuit_create(4, 5, None, 12, spec["seed"])
+        n = 20
+    ref = sim.simulate(_to_oracle(c.gates()), n)
+    even = 0
+    for sh in OOP_SHAPES:
+        for oop in (1, -1):
+            o = dict(reg_qubits=sh[0], thread_qubits=sh[1], low_qubits=sh[2], plain=0, jit=1,
+                     out_of_place=oop)
+            psi = np.zeros(1 << n, np.complex64)
+            psi[0] = 1
+            qsv.sv_debug_emulate(psi, c, opts=o)
+            assert np.max(np.abs(psi - ref)) < 1e-6, (sh, oop)
+            if oop == 1 and qsv.sv_plan_info(c, opts=o)["n_passes"] % 2 == 0:
+                even += 1
+    assert even >= 1  # at least one shape ran the two-buffer schedule
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 def test_emulated_plan_matches_oracle(shape):
     spec = workloads.WORKLOADS["4x5-d10"]

@@ -104,10 +104,11 @@ def _opts(shape, jit=0):
     return dict(reg_qubits=shape[0], thread_qubits=shape[1], low_qubits=shape[2], plain=0, jit=jit)
 
 
-@pytest.mark.parametrize("jit", [-1, 1])
+@pytest.mark.parametrize("jit", [-1, 1, 2])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_fused_4x5_all_shapes(shape, jit):
-    """Generic pass kernel (jit=-1) and per-pass compiled kernels (jit=1)."""
+    """Generic pass kernel (jit=-1), per-pass compiled kernels (jit=1) and their
+    persistent prefetching form (jit=2)."""
     _gpu()
     spec, c, lat = _lattice_circuit("4x5-d10")
     ref = sim.simulate(_oracle_gates(c), lat.n)
@@ -141,7 +142,7 @@ def test_fused_explicit_gates_all_kinds():
     c = qsv.circuit_create(4, 4, None, gates=g)
     ref = sim.simulate(_oracle_gates(c), n)
     for shape in (None, (3, 6, 4), (5, 9, 7), (6, 8, 5)):
-        for jit in (-1, 1):
+        for jit in (-1, 1, 2):
             a = _state(n)
             qsv.sv_apply_fused(a, c, opts=_opts(shape, jit))
             got = a.cpu().numpy()
@@ -364,7 +365,7 @@ def test_split_end_to_end_gpu():
     A = torch.empty(1 << len(qa), dtype=torch.complex64, device=DEV)
     B = torch.empty(1 << len(qb), dtype=torch.complex64, device=DEV)
     for br in range(nbr):
-        jit = 1 if br % 2 else -1   # both pass-kernel flavours
+        jit = (-1, 1, 2)[br % 3]   # every pass-kernel flavour
         qsv.sv_init(A, len(qa), qsv.INIT_ZERO)
         qsv.sv_apply_fused(A, ha, branch=br, opts=_opts(None, jit))
         qsv.sv_amplitudes(A, len(qa), xa, At[br])
@@ -382,7 +383,7 @@ def test_split_end_to_end_gpu():
     assert np.max(np.abs(out.cpu().numpy() - want)) <= 1e-12
 
 
-@pytest.mark.parametrize("jit", [-1, 1])
+@pytest.mark.parametrize("jit", [-1, 1, 2])
 @pytest.mark.parametrize("kind,basis,lb", [(qsv.INIT_ZERO, 0, 0), (qsv.INIT_PLUS, 0, 1),
                                            (qsv.INIT_BASIS, 0xABCDE, 0)])
 def test_simulate_entry(kind, basis, lb, jit):
@@ -412,6 +413,68 @@ def test_simulate_entry(kind, basis, lb, jit):
     qsv.sv_norm_fp64(a, n, n2)
     assert abs(nrm.item() - n2.item()) <= 1e-12
     assert abs(nrm.item() - 1) <= 1e-5
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 5), (3, 6, 4), (5, 8, 4), (4, 7, 4), (4, 6, 3)])
+@pytest.mark.parametrize("jit", [1, 2])
+def test_out_of_place_sweeps(shape, jit):
+    """Two-buffer sweeps (each pass writes the state under the next pass's
+    qubit-to-bit map into the other buffer) against the oracle and against the
+    in-place sweep: sv_apply_fused (falls back to in place for an odd pass
+    count) and sv_simulate (first pass generates the state, any pass count)."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("4x5-d10")
+    n = lat.n
+    gates = _oracle_gates(c)
+    ref = sim.simulate(gates, n)
+    ref_plus = sim.run(np.full(1 << n, 2.0 ** (-n / 2), np.complex128), n,
+                       [g for g in gates if g[3] >= 1])
+    o = dict(reg_qubits=shape[0], thread_qubits=shape[1], low_qubits=shape[2], plain=0, jit=jit)
+    for oop in (1, -1):
+        a = _state(n)
+        qsv.sv_apply_fused(a, c, opts=dict(o, out_of_place=oop))
+        _check_full(a, ref, n)
+        b = torch.empty(1 << n, dtype=torch.complex64, device=DEV)
+        nrm = torch.zeros(1, dtype=torch.float64, device=DEV)
+        qsv.sv_simulate(b, c, init_kind=qsv.INIT_PLUS, layer_begin=1,
+                        opts=dict(o, out_of_place=oop), norm_out=nrm)
+        _check_full(b, ref_plus, n)
+        n2 = torch.zeros(1, dtype=torch.float64, device=DEV)
+        qsv.sv_norm_fp64(b, n, n2)
+        assert abs(nrm.item() - n2.item()) <= 1e-12
+
+
+@pytest.mark.parametrize("shape", [(5, 8, 4), (4, 7, 4)])
+def test_persistent_kernels_many_tiles(shape):
+    """24 qubits: 2^11 or 2^13 tiles, several per resident workgroup, so the
+    persistent kernels run their prefetch loop (and the norm's alternating
+    reduction buffer) many times.  Against the oracle, and bit for bit against
+    the one-tile-per-workgroup kernels, which run the same arithmetic."""
+    _gpu()
+    n, depth = 24, 14
+    c = qsv.circuit_create(4, 6, None, depth, 0x5EED0024)
+    lat = OC.Lattice(4, 6)
+    ref = sim.run(np.full(1 << n, 2.0 ** (-n / 2), np.complex128), n,
+                  [g for g in _oracle_gates(c) if g[3] >= 1])
+    outs = {}
+    for jit in (1, 2):
+        a = torch.empty(1 << n, dtype=torch.complex64, device=DEV)
+        nrm = torch.zeros(1, dtype=torch.float64, device=DEV)
+        qsv.sv_simulate(a, c, init_kind=qsv.INIT_PLUS, layer_begin=1, opts=_opts(shape, jit),
+                        norm_out=nrm)
+        _check_full(a, ref, n)
+        n2 = torch.zeros(1, dtype=torch.float64, device=DEV)
+        qsv.sv_norm_fp64(a, n, n2)
+        assert abs(nrm.item() - n2.item()) <= 1e-12
+        # in-place sweep on a loaded state (prefetch path of every pass)
+        b = _state(n, qsv.INIT_PLUS)
+        qsv.sv_apply_fused(b, c, layer_begin=1, opts=_opts(shape, jit))
+        # (the generated first pass may fold its constant start values at compile time)
+        assert torch.max(torch.abs(a - b)).item() <= 1e-9
+        outs[jit] = (a, nrm.item())
+    assert torch.equal(outs[1][0], outs[2][0])
+    assert outs[1][1] == outs[2][1]
+    assert lat.n == n
 
 
 def test_simulate_full_size_5x6_d20():
