@@ -401,6 +401,7 @@ struct Gen {
         int sigma[kMaxSlots] = {};
     };
     int lds_elems = 0;       // largest staging buffer of the pass (elements)
+    bool persistent = false; // generating the persistent (prefetching) form
 
     uint32_t xweight(const XLayout &x, int q) const {
         if (q == x.skip) return 0;
@@ -432,9 +433,10 @@ struct Gen {
     int xcost(const XLayout &x, const int *perm, const int *inv) const {
         uint32_t ww[kMaxSlots], wr[kMaxSlots];
         lane_weights(x, perm, inv, ww, wr);
-        // 64 banks serving 32 lanes, and 32 banks serving 16 lanes
-        return 2 * (conflict(ww, T, 5, 64) + conflict(wr, T, 5, 64)) + conflict(ww, T, 4, 32) +
-               conflict(wr, T, 4, 32);
+        // gfx950 serves an 8-byte LDS access 16 lanes at a time from 32
+        // 4-byte banks (measured: lane stride 2^k elements costs min(2^k, 16)
+        // times the conflict-free rate, odd strides are conflict-free)
+        return conflict(ww, T, 4, 32) + conflict(wr, T, 4, 32);
     }
     void base_layout(XLayout &x, bool by_new, int split, const int *perm) const {
         x.by_new = by_new;
@@ -445,17 +447,26 @@ struct Gen {
         for (int q = 0; q < R; ++q) x.tau[q] = (q == x.skip) ? 0 : k++;
         for (int u = 0; u < T; ++u) x.sigma[u] = u;
     }
+    int split_slot(const int *perm) const {  // prefer a register slot that stays in place
+        for (int q = 0; q < R; ++q)
+            if (perm[q] == q) return q;
+        for (int q = 0; q < R; ++q)
+            if (perm[q] < R) return q;
+        return -1;
+    }
     XLayout choose_layout(const int *perm, const int *inv) const {
-        // split slot: prefer a register slot that stays in place
-        int split = -1;
-        for (int q = 0; q < R && split < 0; ++q)
-            if (perm[q] == q) split = q;
-        for (int q = 0; q < R && split < 0; ++q)
-            if (perm[q] < R) split = q;
+        // Staging in two halves (split >= 0, a register slot that stays a
+        // register slot) halves the buffer but doubles the barriers: worth it
+        // only when the whole tile's buffer would leave one workgroup per CU
+        // (2^14-amplitude tiles); 2^13-amplitude tiles measured faster staged whole.
+        // The persistent form holds two register sets, which limits it to two
+        // workgroups per CU anyway: it always stages whole.
+        const bool big = (size_t(N + 1) << T) * (dp ? 16 : 8) > size_t(80) << 10;
+        const int split = (big && !persistent) ? split_slot(perm) : -1;
         XLayout best;
         base_layout(best, false, split, perm);
         int best_cost = xcost(best, perm, inv);
-        const int floor_cost = 6;  // every group conflict-free
+        const int floor_cost = 2;  // store and load conflict-free
         uint64_t rng = 0x9E3779B97F4A7C15ull ^ uint64_t(uid);
         auto next = [&rng]() {
             rng ^= rng << 13; rng ^= rng >> 7; rng ^= rng << 17;
@@ -630,6 +641,7 @@ struct Gen {
     std::string emit(const std::string &name, bool &uses_lds, int init_kind = -1, bool norm = false,
                      int n = 0, bool batched = false, bool loop = false) {
         uses_lds = false;
+        persistent = loop;
         for (int pc = 0; pc < P.n_ops; ++pc) {
             if ((P.ops[pc] & 0xff) == OP_XCHG) { uses_lds = true; ++pc; }
         }
