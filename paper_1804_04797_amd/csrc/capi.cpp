@@ -237,7 +237,7 @@ using namespace qsv;
 extern "C" {
 
 const char *qsv_last_error(void) { return g_err.c_str(); }
-const char *qsv_version(void) { return "qsv 0.2 gfx950"; }
+const char *qsv_version(void) { return "qsv 0.3 gfx950"; }
 
 qsv_status circuit_create(int rows, int cols, const uint8_t *present, int depth, uint64_t seed,
                           const qsv_gate *gates, size_t n_gates, qsv_circuit **out) {
