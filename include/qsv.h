@@ -340,6 +340,16 @@ qsv_status sv_debug_emulate_dense(void *amps_host, const qsv_circuit *c, uint64_
 qsv_status sv_debug_jit_compile(const qsv_circuit *c, int layer_begin, int layer_end,
                                 const qsv_fuse_opts *opts, size_t *code_bytes, double *seconds);
 
+/*
+ * qsv_release_device_buffers - free the device memory the library keeps on
+ * the current device between calls: the second state buffer of out-of-place
+ * sweeps (8 * 2^n bytes, allocated at the first such sweep) and the FP64
+ * partial sums of the norm.  Synchronises the device first.  Later calls
+ * allocate again as needed.  For callers that need the memory back (e.g.
+ * before allocating a larger state).
+ */
+qsv_status qsv_release_device_buffers(void);
+
 const char *qsv_last_error(void);
 /* Library version string. */
 const char *qsv_version(void);

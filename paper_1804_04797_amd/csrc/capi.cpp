@@ -49,10 +49,14 @@ qsv_status check_device() {
 
 // FP64 partial-sum buffer of the norm reductions, one per device, grown on
 // demand and kept for the life of the process.
+std::mutex g_part_mu;
+double *g_part[64] = {nullptr};
+size_t g_part_cap[64] = {0};
+
 qsv_status norm_partials(size_t count, double **out) {
-    static std::mutex mu;
-    static double *buf[64] = {nullptr};
-    static size_t cap[64] = {0};
+    std::mutex &mu = g_part_mu;
+    double **buf = g_part;
+    size_t *cap = g_part_cap;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -86,10 +90,14 @@ qsv_status check_state(const void *amps, int n) {
 // Second state buffer of out-of-place sweeps, one per device, grown on
 // demand and kept until the process ends.  Calls that overlap on one device
 // share it, so they must not both run out of place.
+std::mutex g_scratch_mu;
+void *g_scratch[64] = {nullptr};
+size_t g_scratch_cap[64] = {0};
+
 qsv_status state_scratch(size_t bytes, void **out) {
-    static std::mutex mu;
-    static void *buf[64] = {nullptr};
-    static size_t cap[64] = {0};
+    std::mutex &mu = g_scratch_mu;
+    void **buf = g_scratch;
+    size_t *cap = g_scratch_cap;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -237,6 +245,28 @@ using namespace qsv;
 extern "C" {
 
 const char *qsv_last_error(void) { return g_err.c_str(); }
+qsv_status qsv_release_device_buffers(void) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(QSV_EUNSUPPORTED, "device ordinal out of range");
+    e = hipDeviceSynchronize();  // queued sweeps may still use them
+    if (e != hipSuccess) return hip_fail(e, "qsv_release_device_buffers");
+    {
+        std::lock_guard<std::mutex> g(g_scratch_mu);
+        if (g_scratch[dev]) hipFree(g_scratch[dev]);
+        g_scratch[dev] = nullptr;
+        g_scratch_cap[dev] = 0;
+    }
+    {
+        std::lock_guard<std::mutex> g(g_part_mu);
+        if (g_part[dev]) hipFree(g_part[dev]);
+        g_part[dev] = nullptr;
+        g_part_cap[dev] = 0;
+    }
+    return QSV_OK;
+}
+
 const char *qsv_version(void) { return "qsv 0.3 gfx950"; }
 
 qsv_status circuit_create(int rows, int cols, const uint8_t *present, int depth, uint64_t seed,

@@ -29,7 +29,8 @@ EXPORTS = ["circuit_create", "circuit_destroy", "circuit_info", "circuit_gates",
            "circuit_split", "sv_init", "sv_apply_fused", "sv_apply_plain", "sv_amplitudes",
            "sv_norm_fp64", "sv_branch_combine", "sv_simulate", "sv_simulate_c128", "sv_batch_create", "sv_batch_run",
            "sv_batch_destroy", "sv_plan_info", "sv_debug_emulate", "sv_debug_jit_compile",
-           "sv_tune", "sv_apply_dense", "sv_debug_emulate_dense", "qsv_last_error", "qsv_version"]
+           "sv_tune", "sv_apply_dense", "sv_debug_emulate_dense", "qsv_release_device_buffers",
+           "qsv_last_error", "qsv_version"]
 
 
 class QsvError(RuntimeError):
@@ -77,6 +78,7 @@ def lib():
         "sv_plan_info": (st, [vp, i32, i32, vp, P(i32), vp, vp, sz, vp, sz]),
         "sv_debug_emulate": (st, [vp, vp, u64, i32, i32, vp]),
         "sv_debug_jit_compile": (st, [vp, i32, i32, vp, P(sz), P(ctypes.c_double)]),
+        "qsv_release_device_buffers": (st, []),
         "sv_tune": (st, [vp, vp, i32, i32, vp, P(ctypes.c_double), vp]),
         "sv_apply_dense": (st, [vp, vp, u64, i32, i32, i32, P(i32), vp]),
         "sv_debug_emulate_dense": (st, [vp, vp, u64, i32, i32, i32, P(i32)]),
@@ -315,6 +317,12 @@ def sv_debug_jit_compile(c, layer_begin=0, layer_end=-1, opts=None):
     _check(lib().sv_debug_jit_compile(c, layer_begin, layer_end, _opts(opts), ctypes.byref(nb),
                                       ctypes.byref(sec)))
     return nb.value, sec.value
+
+
+def release_device_buffers():
+    """Free the library's device buffers on the current device (second state
+    buffer of out-of-place sweeps, norm partial sums)."""
+    _check(lib().qsv_release_device_buffers())
 
 
 def sv_tune(amps_scratch, c, layer_begin=0, layer_end=-1, stream=None):
