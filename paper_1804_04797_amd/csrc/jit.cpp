@@ -308,7 +308,17 @@ struct Gen {
     // Multiply every register by its pending factors and by (sr + i si), then
     // reset them: i^{m_j} 2^{-h_j/2} (compile time), prod of sg<s> over the
     // register's set bits of dirty slots, w^e * alive (run time).
-    void materialize(double sr, double si) {
+    // move_mask < 0: apply every pending factor.  Otherwise (an exchange that
+    // moves the register slots in move_mask to thread slots, no pending
+    // per-thread phase) apply the run-time signs and only the part of each
+    // register's compile-time factor that depends on those slots: register j
+    // gets K_j / K_{j with them cleared}; the remaining compile-time factors
+    // depend on staying register bits only, which op_xchg then renames to
+    // their new slots.  (The signs are functions of the thread that computed
+    // them; an exchange hands the data to other threads, so they are applied.)
+    void materialize(double sr, double si, int move_mask = -1) {
+        const bool partial = move_mask >= 0;
+        if (partial && e_dirty) return materialize(sr, si);
         int dmask = 0;
         for (int s = 0; s < R; ++s)
             if (sdirty[s]) dmask |= 1 << s;
@@ -337,10 +347,13 @@ struct Gen {
         }
         const int wid = uid++;
         for (int j = 0; j < N; ++j) {
-            // compile-time factor K = i^m 2^{-h/2} (sr + i si)
-            const double mag = std::pow(2.0, -0.5 * h[j]);
+            // compile-time factor K = i^m 2^{-h/2} (sr + i si), relative to
+            // register j0 in the partial form
+            const int j0 = partial ? (j & ~move_mask) : -1;
+            const int dm = partial ? m[j] - m[j0] : m[j], dh = partial ? h[j] - h[j0] : h[j];
+            const double mag = std::pow(2.0, -0.5 * dh);
             double kr = sr * mag, ki = si * mag;
-            for (int q = 0; q < (m[j] & 3); ++q) { double t2 = -ki; ki = kr; kr = t2; }
+            for (int q = 0; q < (dm & 3); ++q) { double t2 = -ki; ki = kr; kr = t2; }
             const std::string sj = sign_of(j & dmask);
             if (!e_dirty) {
                 const bool real = (ki == 0.0), imag = (kr == 0.0);
@@ -372,10 +385,31 @@ struct Gen {
                 o << "v[" << j << "]=" << CM << "(v[" << j << "]," << fr << "," << fi << ");\n";
             }
         }
+        if (partial) {
+            for (int j = 0; j < N; ++j) { m[j] = m[j & ~move_mask]; h[j] = h[j & ~move_mask]; }
+            for (int s = 0; s < R; ++s) sdirty[s] = false;
+            return;
+        }
         for (int j = 0; j < N; ++j) m[j] = h[j] = 0;
         for (int s = 0; s < R; ++s) sdirty[s] = false;
         if (e_dirty) o << "e = 0u; alive = 1u;\n";
         e_dirty = false;
+    }
+
+    // After an exchange: the compile-time factors left by a partial
+    // materialize depend on staying register slots only; move them with
+    // their slots.
+    void rename_factors(const int *perm) {
+        int mo[64], ho[64];
+        std::copy(m, m + N, mo);
+        std::copy(h, h + N, ho);
+        for (int jn = 0; jn < N; ++jn) {
+            int jo = 0;  // old register index of the staying bits of jn
+            for (int sn = 0; sn < R; ++sn)
+                if (((jn >> sn) & 1) && perm[sn] < R) jo |= 1 << perm[sn];
+            m[jn] = mo[jo];
+            h[jn] = ho[jo];
+        }
     }
 
     // LDS staging of one exchange.  When some register slot s of the new
@@ -499,11 +533,49 @@ struct Gen {
         return e.str();
     }
 
+    // An exchange that only swaps register slots with thread slots 4 and 5
+    // (lane bits 4 and 5 of a wave) is a 2x2 transpose between a register
+    // bit and a lane bit: v_permlane16_swap (lane bit 4) and
+    // v_permlane32_swap (lane bit 5) on every register pair, no LDS.
+    bool lane_swaps(const int *perm) {
+        if (dp || T < 6) return false;
+        std::vector<std::pair<int, int>> pairs;  // (register slot, lane bit)
+        for (int s = 0; s < L; ++s) {
+            if (perm[s] == s) continue;
+            const int o = perm[s];
+            if (perm[o] != s) return false;
+            if (s < R && (o == R + 4 || o == R + 5)) pairs.push_back({s, o - R});
+            else if (!(o < R && (s == R + 4 || s == R + 5))) return false;
+        }
+        if (pairs.empty()) return false;
+        for (auto &pr : pairs) {
+            const char *fn = pr.second == 4 ? "__builtin_amdgcn_permlane16_swap" : "__builtin_amdgcn_permlane32_swap";
+            for (int j = 0; j < N; ++j) {
+                if (j & (1 << pr.first)) continue;
+                const int k = j | (1 << pr.first);
+                o << "{const auto rx = " << fn << "(__float_as_uint(v[" << j << "].x), __float_as_uint(v[" << k
+                  << "].x), false, false);const auto ry = " << fn << "(__float_as_uint(v[" << j
+                  << "].y), __float_as_uint(v[" << k << "].y), false, false);v[" << j
+                  << "]=F2(__uint_as_float(rx[0]),__uint_as_float(ry[0]));v[" << k
+                  << "]=F2(__uint_as_float(rx[1]),__uint_as_float(ry[1]));}\n";
+            }
+        }
+        return true;
+    }
+
     void op_xchg(uint64_t pw) {
-        materialize(1.0, 0.0);
         int perm[kMaxSlots], inv[kMaxSlots];
         for (int s = 0; s < L; ++s) perm[s] = int((pw >> (4 * s)) & 0xf);
         for (int s = 0; s < L; ++s) inv[perm[s]] = s;
+        int move_mask = 0;  // old register slots that become thread slots
+        for (int s = 0; s < R; ++s)
+            if (inv[s] >= R) move_mask |= 1 << s;
+        const bool carry = !e_dirty;
+        materialize(1.0, 0.0, carry ? move_mask : -1);
+        if (lane_swaps(perm)) {
+            if (carry) rename_factors(perm);
+            return;
+        }
         const XLayout x = choose_layout(perm, inv);
         lds_elems = std::max(lds_elems, (x.M + 1) << T);
         uint32_t ww[kMaxSlots], wr[kMaxSlots];
@@ -536,6 +608,7 @@ struct Gen {
         }
         for (int j = 0; j < N; ++j) o << "v[" << j << "]=nv" << id << "[" << j << "];\n";
         o << "}\n";
+        if (carry) rename_factors(perm);
     }
 
     // Offset (in elements) of register j under the physical bits of the slots.

@@ -53,6 +53,8 @@ namespace {
 
 // Thread slots hold the lowest resident index bits at load and store.
 constexpr bool kLanesLow = true;
+// Exchanges prefer thread slots 4 and 5 (cross-lane swaps, see build_plan).
+constexpr bool kLanePorts = true;
 
 struct G {
     uint8_t kind;
@@ -385,6 +387,32 @@ qsv_status build_plan_weighted(const qsv_circuit &c, int lb, int le, TileShape s
                     want.push_back(x.q0);
             }
             if (want.empty()) break;  // should not happen: some gate is ready
+            // victims: register slots ordered by furthest next use
+            std::vector<int> regs(R);
+            std::iota(regs.begin(), regs.end(), 0);
+            std::sort(regs.begin(), regs.end(), [&](int a, int b) {
+                return next_use[sl.occ[a]] > next_use[sl.occ[b]];
+            });
+            int perm[kMaxSlots];
+            for (int s2 = 0; s2 < L; ++s2) perm[s2] = s2;
+            // Thread slots 4 and 5 are lane bits 4 and 5 of a wave: a register
+            // slot swapped with one of them is a cross-lane swap inside each
+            // wave (no LDS, no barrier).  Use it when every wanted qubit sits there.
+            bool ports = kLanePorts && T >= 6 && want.size() <= 2;
+            for (int q : want) ports = ports && (sl.where[q] == R + 4 || sl.where[q] == R + 5);
+            if (ports) {
+                int k = 0;
+                for (int q : want) {
+                    const int vs = regs[k++], ts = sl.where[q];
+                    perm[vs] = ts;
+                    perm[ts] = vs;
+                }
+                pb.xchg(perm, L);
+                int occ_old[kMaxSlots];
+                std::copy(sl.occ, sl.occ + L, occ_old);
+                for (int s2 = 0; s2 < L; ++s2) sl.set(s2, occ_old[perm[s2]]);
+                continue;
+            }
             // fill the remaining register capacity with the next-needed thread qubits
             std::vector<int> cand;
             for (int q = 0; q < n; ++q)
@@ -393,14 +421,6 @@ qsv_status build_plan_weighted(const qsv_circuit &c, int lb, int le, TileShape s
                     cand.push_back(q);
             std::sort(cand.begin(), cand.end(),
                       [&](int a, int b) { return next_use[a] < next_use[b]; });
-            // victims: register slots ordered by furthest next use
-            std::vector<int> regs(R);
-            std::iota(regs.begin(), regs.end(), 0);
-            std::sort(regs.begin(), regs.end(), [&](int a, int b) {
-                return next_use[sl.occ[a]] > next_use[sl.occ[b]];
-            });
-            int perm[kMaxSlots];
-            for (int s = 0; s < L; ++s) perm[s] = s;
             int k = 0;
             std::vector<int> incoming = want;
             for (int q : cand) incoming.push_back(q);
@@ -413,6 +433,23 @@ qsv_status build_plan_weighted(const qsv_circuit &c, int lb, int le, TileShape s
                 perm[vs] = ts;
                 perm[ts] = vs;
                 ++k;
+            }
+            if (kLanePorts && T >= 6) {
+                // a general exchange also parks the next-needed thread qubits
+                // at the lane ports for a later cross-lane swap
+                std::vector<int> nxt;
+                for (int s2 = R; s2 < L; ++s2) {
+                    const int q = sl.occ[perm[s2]];
+                    if (next_use[q] < (1 << 30)) nxt.push_back(q);
+                }
+                std::sort(nxt.begin(), nxt.end(), [&](int a, int b) { return next_use[a] < next_use[b]; });
+                for (int pi = 0; pi < 2 && pi < int(nxt.size()); ++pi) {
+                    const int port = R + 4 + pi;
+                    int t2 = -1;
+                    for (int s2 = R; s2 < L; ++s2)
+                        if (sl.occ[perm[s2]] == nxt[pi]) t2 = s2;
+                    if (t2 >= 0 && t2 != port && !(pi == 1 && t2 == R + 4)) std::swap(perm[port], perm[t2]);
+                }
             }
             pb.xchg(perm, L);
             int occ_old[kMaxSlots];
