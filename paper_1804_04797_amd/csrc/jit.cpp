@@ -787,7 +787,20 @@ struct CacheEntry {
 };
 
 std::mutex g_mu;
-std::map<std::pair<int, std::string>, std::shared_ptr<CacheEntry>> g_cache;
+std::map<std::pair<int, std::string>, std::shared_ptr<CacheEntry>> g_cache;   // by source text
+std::map<std::pair<int, std::string>, std::shared_ptr<CacheEntry>> g_pcache;  // by pass programs
+
+// The generated source is a function of the pass programs, the tile shape, n
+// and the variant: a plan whose programs were compiled before (e.g. the same
+// circuit created again) reuses the kernels without generating the source.
+std::string program_key(const Plan &plan, int variant) {
+    std::string k;
+    const int head[4] = {variant, plan.n, plan.R, plan.T};
+    k.append(reinterpret_cast<const char *>(head), sizeof(head));
+    for (const Pass &p : plan.passes)
+        k.append(reinterpret_cast<const char *>(&p.prog), sizeof(PassProg));
+    return k;
+}
 double g_total_compile_s = 0;
 
 qsv_status compile_source(const std::string &src, std::vector<char> &code, std::string &log) {
@@ -864,6 +877,15 @@ qsv_status jit_prepare(Plan &plan, int variant) {
     int dev = 0;
     hipError_t he = hipGetDevice(&dev);
     if (he != hipSuccess) return fail(QSV_EHIP, "hipGetDevice failed");
+    const auto pkey = std::make_pair(dev, program_key(plan, variant));
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        auto pit = g_pcache.find(pkey);
+        if (pit != g_pcache.end()) {
+            plan.jit_variants[variant] = pit->second;
+            return QSV_OK;
+        }
+    }
     std::vector<size_t> lds;
     std::string src = jit_source(plan, &lds, variant);
     std::lock_guard<std::mutex> g(g_mu);
@@ -899,6 +921,7 @@ qsv_status jit_prepare(Plan &plan, int variant) {
         g_total_compile_s += e->compile_s;
         it = g_cache.emplace(key, e).first;
     }
+    g_pcache[pkey] = it->second;
     plan.jit_variants[variant] = it->second;
     return QSV_OK;
 }

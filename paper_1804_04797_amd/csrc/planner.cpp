@@ -21,7 +21,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <numeric>
+#include <thread>
+#include <vector>
 
 #include "qsv_internal.h"
 
@@ -230,8 +233,14 @@ namespace {
 // One plan.  The resident set of each pass maximises the summed weight of
 // the gates the pass can apply; gate i of the range weighs
 // 1 + lambda * (1 - i / count), so lambda > 0 favours finishing old gates.
+//
+// follow (out-of-place plans): each pass writes the map its final slot
+// layout gives, so the store needs no restoring exchange; the qubits in
+// register slot 0 and thread slots 0..cl-2 at the end of the pass are then
+// forced into the next pass.  Otherwise the map puts the next pass's best
+// qubits at the low bits and the pass restores that layout before its store.
 qsv_status build_plan_weighted(const qsv_circuit &c, int lb, int le, TileShape shape, double lambda,
-                               Plan &out) {
+                               bool follow, Plan &out) {
     const int n = c.n;
     const int R = shape.R, T = shape.T, L = R + T, cl = shape.c;
     if (R < 1 || T < 1 || L > n || L > kMaxSlots || cl < 1 || cl - 1 > T || cl > L)
@@ -474,6 +483,33 @@ qsv_status build_plan_weighted(const qsv_circuit &c, int lb, int le, TileShape s
             if (n_done < NG) S_next = choose_resident(d, done, pend, n, L, natural);
         } else if (n_done == NG && (S & natural) == natural) {
             for (int q = 0; q < n; ++q) nphys[q] = q;  // final store in natural order
+        } else if (follow && n_done < NG) {
+            // The written map follows the slots at the end of the pass, so the
+            // store needs no exchange: register slot 0 -> bit 0, thread slots
+            // in order -> bits 1..T, the other registers next, then the next
+            // pass's new qubits, then the rest.  The qubits at bits 0..cl-1 are
+            // forced into the next pass (every access stays a contiguous run).
+            std::vector<int> anchor;
+            anchor.push_back(sl.occ[0]);
+            for (int u = 0; u < cl - 1; ++u) anchor.push_back(sl.occ[R + u]);
+            uint64_t A = 0;
+            for (int q : anchor) A |= 1ull << q;
+            S_next = choose_resident(d, done, pend, n, L, A);
+            if (completes(S_next) && (S_next & natural) != natural) {
+                const uint64_t S2 = choose_resident(d, done, pend, n, L, A | natural);
+                if (completes(S2)) S_next = S2;
+            }
+            std::vector<int> order;
+            order.push_back(sl.occ[0]);
+            for (int u = 0; u < T; ++u) order.push_back(sl.occ[R + u]);
+            for (int s2 = 1; s2 < R; ++s2) order.push_back(sl.occ[s2]);
+            for (int pass2 = 0; pass2 < 2; ++pass2)
+                for (int bb = 0; bb < n; ++bb) {
+                    const int q = qat[bb];
+                    if ((S >> q) & 1) continue;
+                    if (((S_next >> q) & 1) == (pass2 == 0)) order.push_back(q);
+                }
+            for (int b = 0; b < n; ++b) nphys[order[b]] = b;
         } else {
             // anchors: cl qubits resident now and in the next pass
             uint64_t Sf = (n_done < NG) ? choose_resident(d, done, pend, n, L, 0) : natural;
@@ -606,27 +642,57 @@ qsv_status build_plan_weighted(const qsv_circuit &c, int lb, int le, TileShape s
     return QSV_OK;
 }
 
+// Exchanges staged through LDS (a swap of register slots with thread slots
+// 4/5 only is a cross-lane swap and is not counted).
 int exchanges(const Plan &p) {
     int k = 0;
     for (const Pass &x : p.passes)
-        for (int pc = 0; pc < x.prog.n_ops; ++pc)
-            if ((x.prog.ops[pc] & 0xff) == OP_XCHG) { ++k; ++pc; }
+        for (int pc = 0; pc < x.prog.n_ops; ++pc) {
+            if ((x.prog.ops[pc] & 0xff) != OP_XCHG) continue;
+            const uint64_t w = x.prog.ops[++pc];
+            const int L = p.R + p.T;
+            bool lane = p.T >= 6, any = false;
+            for (int s = 0; s < L && lane; ++s) {
+                const int o = int((w >> (4 * s)) & 0xf);
+                if (o == s) continue;
+                any = true;
+                const int back = int((w >> (4 * o)) & 0xf);
+                lane = back == s && ((s < p.R && (o == p.R + 4 || o == p.R + 5)) ||
+                                     (o < p.R && (s == p.R + 4 || s == p.R + 5)));
+            }
+            if (!(lane && any)) ++k;
+        }
     return k;
 }
 
 }  // namespace
 
-// The greedy selection is tried with a few gate weightings; the plan with
-// the fewest passes (then the fewest exchanges) is kept.
+// The greedy selection is tried with a few gate weightings (and, out of
+// place, both map policies); the plan with the fewest passes, then the
+// fewest LDS exchanges, is kept.
 qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Plan &out) {
     static const double kLambda[] = {0.0, 0.5, 1.0};
-    qsv_status st = build_plan_weighted(c, lb, le, shape, kLambda[0], out);
+    const int nl = int(sizeof(kLambda) / sizeof(kLambda[0]));
+    const int variants = nl * (shape.oop ? 2 : 1);
+    // the variants are independent: plan them concurrently
+    std::vector<std::unique_ptr<Plan>> alt(size_t(variants - 1));
+    std::vector<qsv_status> ast(size_t(variants - 1), QSV_EINTERNAL);
+    std::vector<std::thread> pool;
+    for (int v = 1; v < variants; ++v) {
+        alt[size_t(v - 1)].reset(new Plan);
+        pool.emplace_back([&, v] {
+            ast[size_t(v - 1)] = build_plan_weighted(c, lb, le, shape, kLambda[v % nl], v >= nl,
+                                                     *alt[size_t(v - 1)]);
+        });
+    }
+    qsv_status st = build_plan_weighted(c, lb, le, shape, kLambda[0], false, out);
+    for (auto &th : pool) th.join();
     if (st != QSV_OK) return st;
-    for (size_t k = 1; k < sizeof(kLambda) / sizeof(kLambda[0]); ++k) {
-        Plan alt;
-        if (build_plan_weighted(c, lb, le, shape, kLambda[k], alt) != QSV_OK) continue;
-        const size_t pa = alt.passes.size(), po = out.passes.size();
-        if (pa < po || (pa == po && exchanges(alt) < exchanges(out))) out.passes = std::move(alt.passes);
+    for (int v = 1; v < variants; ++v) {
+        Plan &a = *alt[size_t(v - 1)];
+        if (ast[size_t(v - 1)] != QSV_OK) continue;
+        const size_t pa = a.passes.size(), po = out.passes.size();
+        if (pa < po || (pa == po && exchanges(a) < exchanges(out))) out.passes = std::move(a.passes);
     }
     return QSV_OK;
 }

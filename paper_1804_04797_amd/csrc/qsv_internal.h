@@ -55,6 +55,8 @@ struct PassProg {
     int32_t n_ops;
     int32_t n_glob;
 };
+// no padding: the compiled-kernel cache keys on the raw bytes
+static_assert(sizeof(PassProg) == 8 * kMaxOps + 2 * kMaxSlots + 96 + 16, "PassProg has padding");
 
 // Device-side tables of a batch (batch.cpp).
 struct BatchEntry {
