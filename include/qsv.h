@@ -160,6 +160,14 @@ qsv_status circuit_split(const qsv_circuit *c, uint64_t side_a_mask,
                          size_t *n_folded);
 
 /*
+ * circuit_inverse - the adjoint circuit U^dagger: gates in reverse order,
+ * each replaced by its adjoint (T <-> TDG, SX <-> SXDG, SY <-> SYDG; H, CZ,
+ * Z, ZB and the projectors P0, P1, PB are their own adjoints), layer numbers
+ * mirrored (layer' = max layer - layer).  *out is a new host-owned circuit.
+ */
+qsv_status circuit_inverse(const qsv_circuit *c, qsv_circuit **out);
+
+/*
  * sv_init - write a basis or uniform state into amps (device complex64[2^n]).
  *   kind 0 = |0...0>, 1 = |+>^n (every amplitude 2^{-n/2}, i.e. layer 0
  *   applied), 2 = |basis>.
@@ -252,6 +260,16 @@ qsv_status sv_amplitudes(const void *amps, int n_qubits, const uint64_t *bitstri
  * out_dev: device double[1].
  */
 qsv_status sv_norm_fp64(const void *amps, int n_qubits, double *out_dev, void *stream);
+
+/*
+ * sv_inner_product - <a|b> = sum_i conj(a_i) b_i of two complex64[2^n]
+ * device states, every product and partial sum in FP64, fixed-order tree
+ * (deterministic).  out_dev: device double[2] = (re, im).  With a = U2^dagger
+ * |x> and b = U1 |psi0> this is the Task-2 amplitude <x|U2 U1|psi0> of
+ * Section 2.2 from two half-depth sweeps.
+ */
+qsv_status sv_inner_product(const void *a, const void *b, int n_qubits, double *out_dev,
+                            void *stream);
 
 /*
  * sv_branch_combine - out[x] = s_x * sum_b a_tab[b][x] * b_tab[b][x]

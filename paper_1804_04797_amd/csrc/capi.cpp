@@ -430,6 +430,19 @@ qsv_status sv_norm_fp64(const void *amps, int n_qubits, double *out_dev, void *s
     return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_norm_fp64");
 }
 
+qsv_status sv_inner_product(const void *a, const void *b, int n_qubits, double *out_dev, void *stream) {
+    qsv_status st = check_state(a, n_qubits);
+    if (st != QSV_OK) return st;
+    if ((st = check_state(b, n_qubits)) != QSV_OK) return st;
+    if (!out_dev) return fail(QSV_EINVAL, "sv_inner_product: null output");
+    if ((st = check_device()) != QSV_OK) return st;
+    double *part = nullptr;
+    if ((st = norm_partials(2 * 65536, &part)) != QSV_OK) return st;
+    hipError_t e = launch_dot(static_cast<const float2 *>(a), static_cast<const float2 *>(b), n_qubits,
+                              out_dev, part, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_inner_product");
+}
+
 qsv_status sv_branch_combine(const void *a_tab, const void *b_tab, size_t n_branches, size_t m,
                              const int8_t *sign_dev, void *out_dev, void *stream) {
     if (m && (!a_tab || !b_tab || !out_dev)) return fail(QSV_EINVAL, "sv_branch_combine: null buffer");

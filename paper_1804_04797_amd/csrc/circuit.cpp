@@ -8,6 +8,7 @@
 // reproduces the gate counts of Table "28qubit" and the cut counts quoted in
 // Section 2.1.2; they are spelled out in qsv.h next to circuit_create.
 #include <algorithm>
+#include <memory>
 #include <cstring>
 
 #include "qsv_internal.h"
@@ -193,5 +194,36 @@ extern "C" qsv_status circuit_split(const qsv_circuit *c, uint64_t side_a_mask,
     *half_b = B.release();
     *c_eff = cuts;
     *n_folded = folds;
+    return QSV_OK;
+}
+
+// Adjoint circuit: reversed order, each gate replaced by its adjoint (T <-> T^dagger,
+// X^1/2 <-> (X^1/2)^dagger, Y^1/2 <-> (Y^1/2)^dagger; H, CZ, Z, ZB self-adjoint; the
+// projectors P0, P1, PB are self-adjoint).  Layer numbers are mirrored so that
+// layer ranges keep their meaning.  Used for the Task-2 amplitude <x|U|psi> =
+// <U^dagger x|psi> with the circuit split in time (Section 2.2).
+extern "C" qsv_status circuit_inverse(const qsv_circuit *c, qsv_circuit **out) {
+    if (!c || !out) return fail(QSV_EINVAL, "circuit_inverse: null argument");
+    auto r = std::unique_ptr<qsv_circuit>(new qsv_circuit);
+    r->n = c->n;
+    r->depth = c->depth;
+    int top = 0;
+    for (const qsv_gate &g : c->gates) top = std::max(top, int(g.layer));
+    r->gates.reserve(c->gates.size());
+    for (size_t i = c->gates.size(); i-- > 0;) {
+        qsv_gate g = c->gates[i];
+        switch (g.kind) {
+        case QSV_T: g.kind = QSV_TDG; break;
+        case QSV_TDG: g.kind = QSV_T; break;
+        case QSV_SX: g.kind = QSV_SXDG; break;
+        case QSV_SXDG: g.kind = QSV_SX; break;
+        case QSV_SY: g.kind = QSV_SYDG; break;
+        case QSV_SYDG: g.kind = QSV_SY; break;
+        default: break;  // H, CZ, Z, ZB, P0, P1, PB
+        }
+        g.layer = uint16_t(top - int(g.layer));
+        r->gates.push_back(g);
+    }
+    *out = r.release();
     return QSV_OK;
 }

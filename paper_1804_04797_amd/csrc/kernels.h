@@ -27,6 +27,9 @@ hipError_t launch_gather(const float2 *amps, int n, const uint64_t *xs, uint64_t
 hipError_t launch_gather_c128(const void *amps, int n, const uint64_t *xs, uint64_t m, void *out,
                               hipStream_t s);
 hipError_t launch_norm(const float2 *amps, int n, double *out, double *partials, hipStream_t s);
+// <a|b> in FP64 into out[0] (re), out[1] (im); partials: 2 * 65536 doubles
+hipError_t launch_dot(const float2 *a, const float2 *b, int n, double *out, double *partials,
+                      hipStream_t s);
 hipError_t launch_sum_partials(const double *part, uint64_t count, double *out, hipStream_t s);
 hipError_t launch_branch_combine(const float2 *A, const float2 *B, uint64_t nb, uint64_t m,
                                  const int8_t *sign, double2 *out, hipStream_t s);

@@ -656,6 +656,64 @@ k_sum_partials(const double *__restrict__ part, uint64_t count, double *__restri
     if (threadIdx.x == 0) *out = s[0];
 }
 
+// <a|b> = sum conj(a_i) b_i with FP64 products of the FP32 inputs (exact),
+// same fixed-order tree as the norm: per-block partials (re at part[blk],
+// im at part[nblk + blk]), then k_sum_partials on each half.
+__global__ void __launch_bounds__(256)
+k_dot_partial(const float4 *__restrict__ a, const float4 *__restrict__ b, uint64_t quads_per_block,
+              double *__restrict__ part) {
+    __shared__ double sr[256], si[256];
+    const uint64_t start = uint64_t(blockIdx.x) * quads_per_block;
+    double ar = 0.0, ai = 0.0;
+    for (uint64_t i = threadIdx.x; i < quads_per_block; i += 256) {
+        const float4 x = a[start + i], y = b[start + i];
+        const double x0 = x.x, x1 = x.y, x2 = x.z, x3 = x.w;
+        const double y0 = y.x, y1 = y.y, y2 = y.z, y3 = y.w;
+        ar += (x0 * y0 + x1 * y1) + (x2 * y2 + x3 * y3);
+        ai += (x0 * y1 - x1 * y0) + (x2 * y3 - x3 * y2);
+    }
+    sr[threadIdx.x] = ar;
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (int(threadIdx.x) < h) {
+            sr[threadIdx.x] += sr[threadIdx.x + h];
+            si[threadIdx.x] += si[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = sr[0];
+        part[gridDim.x + blockIdx.x] = si[0];
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_dot_small(const float2 *__restrict__ a, const float2 *__restrict__ b, uint64_t dim,
+            double *__restrict__ out) {
+    __shared__ double sr[256], si[256];
+    double ar = 0.0, ai = 0.0;
+    for (uint64_t i = threadIdx.x; i < dim; i += 256) {
+        const double x0 = a[i].x, x1 = a[i].y, y0 = b[i].x, y1 = b[i].y;
+        ar += x0 * y0 + x1 * y1;
+        ai += x0 * y1 - x1 * y0;
+    }
+    sr[threadIdx.x] = ar;
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (int(threadIdx.x) < h) {
+            sr[threadIdx.x] += sr[threadIdx.x + h];
+            si[threadIdx.x] += si[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sr[0];
+        out[1] = si[0];
+    }
+}
+
 __global__ void __launch_bounds__(256)
 k_norm_small(const float2 *__restrict__ a, uint64_t dim, double *__restrict__ out) {
     __shared__ double s[256];
@@ -882,6 +940,25 @@ hipError_t launch_norm(const float2 *amps, int n, double *out, double *partials,
     hipLaunchKernelGGL(k_norm_partial, dim3(blocks), dim3(256), 0, s,
                        reinterpret_cast<const float4 *>(amps), qpb, partials);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, partials, uint64_t(blocks), out);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(const float2 *a, const float2 *b, int n, double *out, double *partials,
+                      hipStream_t s) {
+    const uint64_t dim = 1ull << n;
+    if (n < 14) {
+        hipLaunchKernelGGL(k_dot_small, dim3(1), dim3(256), 0, s, a, b, dim, out);
+        return hipGetLastError();
+    }
+    int lb = n - 1 - 10;  // blocks of 1024 quads, at most 65536 blocks
+    if (lb > 16) lb = 16;
+    const unsigned blocks = 1u << lb;
+    const uint64_t qpb = (dim / 2) >> lb;
+    hipLaunchKernelGGL(k_dot_partial, dim3(blocks), dim3(256), 0, s, reinterpret_cast<const float4 *>(a),
+                       reinterpret_cast<const float4 *>(b), qpb, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, partials, uint64_t(blocks), out);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, partials + blocks, uint64_t(blocks),
+                       out + 1);
     return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ EXPORTS = ["circuit_create", "circuit_destroy", "circuit_info", "circuit_gates",
            "sv_norm_fp64", "sv_branch_combine", "sv_simulate", "sv_simulate_c128", "sv_batch_create", "sv_batch_run",
            "sv_batch_destroy", "sv_plan_info", "sv_debug_emulate", "sv_debug_jit_compile",
            "sv_tune", "sv_apply_dense", "sv_debug_emulate_dense", "qsv_release_device_buffers",
+           "circuit_inverse", "sv_inner_product",
            "qsv_last_error", "qsv_version"]
 
 
@@ -79,6 +80,8 @@ def lib():
         "sv_debug_emulate": (st, [vp, vp, u64, i32, i32, vp]),
         "sv_debug_jit_compile": (st, [vp, i32, i32, vp, P(sz), P(ctypes.c_double)]),
         "qsv_release_device_buffers": (st, []),
+        "circuit_inverse": (st, [vp, P(vp)]),
+        "sv_inner_product": (st, [vp, vp, i32, vp, vp]),
         "sv_tune": (st, [vp, vp, i32, i32, vp, P(ctypes.c_double), vp]),
         "sv_apply_dense": (st, [vp, vp, u64, i32, i32, i32, P(i32), vp]),
         "sv_debug_emulate_dense": (st, [vp, vp, u64, i32, i32, i32, P(i32)]),
@@ -317,6 +320,17 @@ def sv_debug_jit_compile(c, layer_begin=0, layer_end=-1, opts=None):
     _check(lib().sv_debug_jit_compile(c, layer_begin, layer_end, _opts(opts), ctypes.byref(nb),
                                       ctypes.byref(sec)))
     return nb.value, sec.value
+
+
+def circuit_inverse(c) -> Circuit:
+    out = ctypes.c_void_p()
+    _check(lib().circuit_inverse(c, ctypes.byref(out)))
+    return Circuit(out.value)
+
+
+def sv_inner_product(a, b, n_qubits, out_dev, stream=None):
+    """<a|b> in FP64 into out_dev (device float64[2] = re, im)."""
+    _check(lib().sv_inner_product(_ptr(a), _ptr(b), n_qubits, _ptr(out_dev), _stream(stream)))
 
 
 def release_device_buffers():

@@ -318,3 +318,18 @@ def test_compiled_pass_source_compiles(shape):
     c = qsv.circuit_create(spec["rows"], spec["cols"], None, spec["depth"], spec["seed"])
     nbytes, secs = qsv.sv_debug_jit_compile(c, layer_begin=1, opts=shape)
     assert nbytes > 1000
+
+
+def test_circuit_inverse_matches_oracle():
+    """circuit_inverse: reversed order, adjoint kinds, mirrored layers, against
+    the oracle generator's adjoint of the same circuit."""
+    spec = workloads.WORKLOADS["5x6-d16"]
+    c = qsv.circuit_create(spec["rows"], spec["cols"], None, spec["depth"], spec["seed"])
+    inv = qsv.circuit_inverse(c)
+    fwd = _to_oracle(c.gates())
+    want = OC.inverse_circuit(fwd)
+    got = _to_oracle(inv.gates())
+    top = max(g[3] for g in fwd)
+    assert [g[:3] for g in got] == [g[:3] for g in want]
+    assert [g[3] for g in got] == [top - g[3] for g in want]
+    assert inv.info()[0] == c.info()[0]

@@ -415,6 +415,67 @@ def test_simulate_entry(kind, basis, lb, jit):
     assert abs(nrm.item() - 1) <= 1e-5
 
 
+def _half_sweep_amplitudes(c, n, xs, h, opts=None):
+    """alpha_x = <U2^dagger x | U1 +> with U1 = layers [1, h) on |+> and U2 =
+    layers [h, end]: two sweeps and an FP64 inner product per bitstring."""
+    inv = qsv.circuit_inverse(c)
+    top = max(int(g["layer"]) for g in c.gates())
+    psi = torch.empty(1 << n, dtype=torch.complex64, device=DEV)
+    qsv.sv_simulate(psi, c, init_kind=qsv.INIT_PLUS, layer_begin=1, layer_end=h, opts=opts)
+    phi = torch.empty_like(psi)
+    dot = torch.zeros(2, dtype=torch.float64, device=DEV)
+    out = []
+    for x in xs:
+        qsv.sv_simulate(phi, inv, init_kind=qsv.INIT_BASIS, basis=int(x), layer_begin=0,
+                        layer_end=top - h + 1, opts=opts)
+        qsv.sv_inner_product(phi, psi, n, dot)
+        d = dot.cpu().numpy()
+        out.append(complex(d[0], d[1]))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("jit", [-1, 1])
+def test_task2_amplitudes_4x5(jit):
+    """Task-2 amplitudes from two half-depth sweeps and the FP64 inner product,
+    against the oracle's full state; both pass-kernel flavours."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("4x5-d10")
+    n = lat.n
+    ref = sim.run(np.full(1 << n, 2.0 ** (-n / 2), np.complex128), n,
+                  [g for g in _oracle_gates(c) if g[3] >= 1])
+    xs = workloads.bitstrings(n, 12, 21)
+    got = _half_sweep_amplitudes(c, n, xs, 5, _opts(None, jit))
+    assert np.max(np.abs(got - ref[xs])) <= TOL
+    # the inner product itself on identical inputs: FP64 reference on the host
+    a = _state(n, qsv.INIT_PLUS)
+    qsv.sv_apply_fused(a, c, layer_begin=1)
+    b = _state(n, qsv.INIT_PLUS)
+    dot = torch.zeros(2, dtype=torch.float64, device=DEV)
+    qsv.sv_inner_product(a, b, n, dot)
+    want = np.vdot(a.cpu().numpy().astype(np.complex128), b.cpu().numpy().astype(np.complex128))
+    d = dot.cpu().numpy()
+    assert abs(complex(d[0], d[1]) - want) <= 1e-12
+
+
+def test_task2_amplitudes_5x6_d20_golden():
+    """30 qubits at full size: four Task-2 amplitudes from half-depth sweeps
+    (layers 1..10 forward, 11..20 adjoint) against the stored oracle values."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("5x6-d20")
+    xs, amps = [], []
+    for line in open(os.path.join(HERE, "golden", "5x6-d20_amplitudes.txt")):
+        if line.startswith("#"):
+            continue
+        x, re_, im_ = line.split()
+        xs.append(int(x))
+        amps.append(complex(float(re_), float(im_)))
+        if len(xs) == 4:
+            break
+    got = _half_sweep_amplitudes(c, lat.n, np.array(xs, np.uint64), 11)
+    assert np.max(np.abs(got - np.array(amps))) <= TOL
+    assert np.max(np.abs(got - np.array(amps))) * 2 ** (lat.n / 2) <= TOL_SCALED
+
+
 @pytest.mark.parametrize("shape", [(4, 6, 5), (3, 6, 4), (5, 8, 4), (4, 7, 4), (4, 6, 3)])
 @pytest.mark.parametrize("jit", [1, 2])
 def test_out_of_place_sweeps(shape, jit):

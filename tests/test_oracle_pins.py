@@ -291,6 +291,27 @@ def test_unitarity_inverse_returns_to_zero():
     assert np.max(np.abs(psi - e0)) < 1e-13
 
 
+def test_task2_amplitude_from_two_half_sweeps():
+    # Section 2.2, Task 2: alpha_x = <x|U|+>.  Split in time, U = U2 U1:
+    # alpha_x = <U2^dagger x | U1 +>, two sweeps of half the depth and an inner
+    # product; against the amplitude of the full forward sweep.
+    lat = C.Lattice(4, 4)
+    gates = C.random_circuit(lat, 14, 0x7A5C)
+    n = lat.n
+    full = sim.simulate(gates, n)
+    h = 7
+    first = [g for g in gates if g[3] < h]
+    second = [g for g in gates if g[3] >= h]
+    psi1 = sim.simulate(first, n)
+    rng = random.Random(5)
+    for x in [0, (1 << n) - 1] + [rng.randrange(1 << n) for _ in range(6)]:
+        phi = np.zeros(1 << n, np.complex128)
+        phi[x] = 1
+        sim.run(phi, n, C.inverse_circuit(second))
+        alpha = np.vdot(phi, psi1)
+        assert abs(alpha - full[x]) < 1e-13, x
+
+
 def test_porter_thomas_deep_circuit():
     # Section 3 (Fig. 10): output probabilities of deep random circuits follow
     # Porter-Thomas: N * sum p^2 -> 2 and N*p ~ Exp(1).
