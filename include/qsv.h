@@ -283,6 +283,23 @@ qsv_status sv_branch_combine(const void *a_tab, const void *b_tab, size_t n_bran
                              size_t m, const int8_t *sign_dev, void *out_dev, void *stream);
 
 /*
+ * sv_branch_combine_full - the complete state of a cut circuit (Fig. 2,
+ * eq. (1), eqs. (6)-(7)): out[x] = s(x) * sum_b A_b[x_A] B_b[x_B] for all
+ * 2^(n_a + n_b) indices x, a complex GEMM on FP32 matrix cores (FP32
+ * accumulation).  a_states: complex64 [n_branches][2^n_a] (branch-major),
+ * local qubit i of side A = i-th set bit of side_a_mask; b_states likewise
+ * for the other n_b qubits (as circuit_split numbers them).  folded_a /
+ * folded_b: the folded pairs of circuit_split (global qubit numbers, side A
+ * first), s(x) = (-1)^{sum x_a x_b}.  out_state: complex64[2^(n_a+n_b)] in
+ * natural order.  Limits: 7 <= n_a, 7 <= n_b <= 22, n_a + n_b <= 34, at most
+ * 64 folded pairs.  All buffers are caller-owned device memory.
+ */
+qsv_status sv_branch_combine_full(const void *a_states, const void *b_states, size_t n_branches,
+                                  int n_a, int n_b, uint64_t side_a_mask, const int32_t *folded_a,
+                                  const int32_t *folded_b, size_t n_folded, void *out_state,
+                                  void *stream);
+
+/*
  * Batched execution: many states (branches of split halves, or independent
  * circuits of uneven size) swept by ONE persistent kernel launch, replayed
  * from a captured hipGraph.

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqsv.so")
-SOURCES = ["kernels.hip", "capi.cpp", "circuit.cpp", "planner.cpp", "emulate.cpp", "batch.cpp",
+SOURCES = ["kernels.hip", "combine.hip", "capi.cpp", "circuit.cpp", "planner.cpp", "emulate.cpp", "batch.cpp",
            "jit.cpp", "tune.cpp", "dense.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

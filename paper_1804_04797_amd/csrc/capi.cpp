@@ -443,6 +443,52 @@ qsv_status sv_inner_product(const void *a, const void *b, int n_qubits, double *
     return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_inner_product");
 }
 
+qsv_status sv_branch_combine_full(const void *a_states, const void *b_states, size_t n_branches,
+                                  int n_a, int n_b, uint64_t side_a_mask, const int32_t *folded_a,
+                                  const int32_t *folded_b, size_t n_folded, void *out_state,
+                                  void *stream) {
+    if (!a_states || !b_states || !out_state) return fail(QSV_EINVAL, "sv_branch_combine_full: null buffer");
+    if (n_folded && (!folded_a || !folded_b))
+        return fail(QSV_EINVAL, "sv_branch_combine_full: null folded pairs");
+    const int n = n_a + n_b;
+    if (n_a < 7 || n_b < 7 || n_b > 22 || n > kMaxQubits)
+        return fail(QSV_EUNSUPPORTED, "sv_branch_combine_full: needs 7 <= n_a, 7 <= n_b <= 22, n_a + n_b <= 34");
+    if (n_branches == 0 || n_branches > (size_t(1) << 30))
+        return fail(QSV_ERANGE, "sv_branch_combine_full: branch count out of range");
+    if (n_folded > 64) return fail(QSV_ERANGE, "sv_branch_combine_full: more than 64 folded pairs");
+    const uint64_t all = (1ull << n) - 1;
+    if ((side_a_mask & ~all) || __builtin_popcountll(side_a_mask) != n_a)
+        return fail(QSV_EINVAL, "sv_branch_combine_full: side mask does not match n_a");
+    for (const void *p : {a_states, b_states, static_cast<const void *>(out_state)})
+        if (reinterpret_cast<uintptr_t>(p) % 8) return fail(QSV_EINVAL, "sv_branch_combine_full: misaligned buffer");
+    CombineArgs P;
+    std::memset(&P, 0, sizeof(P));
+    P.na = n_a;
+    P.nb = n_b;
+    int local[64];
+    {
+        int ka = 0, kb = 0;
+        for (int q = 0; q < n; ++q) {
+            if ((side_a_mask >> q) & 1) { P.pos_a[ka] = uint8_t(q); local[q] = ka++; }
+            else { P.pos_b[kb] = uint8_t(q); local[q] = kb++; }
+        }
+    }
+    for (size_t f = 0; f < n_folded; ++f) {
+        const int a = folded_a[f], b = folded_b[f];
+        if (a < 0 || a >= n || b < 0 || b >= n || !((side_a_mask >> a) & 1) || ((side_a_mask >> b) & 1))
+            return fail(QSV_EINVAL, "sv_branch_combine_full: folded pair is not (side A, side B)");
+        P.fold_a[f] = uint8_t(local[a]);
+        P.fold_b[f] = uint8_t(local[b]);
+    }
+    P.n_fold = int32_t(n_folded);
+    qsv_status st = check_device();
+    if (st != QSV_OK) return st;
+    hipError_t e = launch_combine_gemm(static_cast<const float2 *>(a_states), static_cast<const float2 *>(b_states),
+                                       n_branches, P, static_cast<float2 *>(out_state),
+                                       static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_branch_combine_full");
+}
+
 qsv_status sv_branch_combine(const void *a_tab, const void *b_tab, size_t n_branches, size_t m,
                              const int8_t *sign_dev, void *out_dev, void *stream) {
     if (m && (!a_tab || !b_tab || !out_dev)) return fail(QSV_EINVAL, "sv_branch_combine: null buffer");

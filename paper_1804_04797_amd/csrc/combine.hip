@@ -1,0 +1,131 @@
+// Full-state branch combine on matrix cores (Fig. 2, eq. (1); eqs. (6)-(7)):
+//
+//   Psi[x] = s(x) * sum_b A_b[x_A] B_b[x_B]
+//
+// for a circuit cut into sides A and B (circuit_split): x_A / x_B are the
+// bits of x on the two sides, A_b / B_b the branch states of the halves and
+// s(x) = (-1)^{sum over folded pairs x_a x_b}.  As matrices, Psi = Ahat Bhat^T
+// with Ahat[x_A][b] = A_b[x_A], a complex GEMM of shape 2^nA x 2^nB x nb.  It
+// runs as two real GEMMs over an interleaved K index k = 2b + part:
+//   Mr = sum_k A1[k] B1[k],  A1 = (Ar, -Ai),  B1 = (Br, Bi)
+//   Mi = sum_k A2[k] B1[k],  A2 = (Ai,  Ar)
+// on v_mfma_f32_16x16x4f32 with FP32 accumulation.  A workgroup owns a
+// 128 x 128 output tile; each of its four waves a 64 x 64 quadrant (4 x 4
+// MFMA blocks for each of Mr, Mi).  Branch chunks of 16 are staged in LDS as
+// k-major planes; the next chunk's global loads are issued before the current
+// chunk's MFMA work so that they overlap it.  The epilogue applies s(x) and
+// scatters the tile to the state's natural index order.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace qsv {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kTile = 128;  // output rows (x_A) and columns (x_B) per workgroup
+constexpr int kBr = 16;     // branches per LDS chunk
+constexpr int kK = 2 * kBr; // interleaved K per chunk
+
+__global__ void __launch_bounds__(256)
+k_combine_gemm(const float2 *__restrict__ A, const float2 *__restrict__ B, uint64_t nbr,
+               const CombineArgs P, float2 *__restrict__ out) {
+    __shared__ float a1[kK][kTile], a2[kK][kTile], b1[kK][kTile];
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+    const uint64_t rowsA = 1ull << P.na, rowsB = 1ull << P.nb;
+    const uint64_t i0 = uint64_t(blockIdx.x) * kTile, j0 = uint64_t(blockIdx.y) * kTile;
+    const uint32_t wr = w & 1u, wc = w >> 1;  // quadrant of this wave
+    const uint32_t lr = lane & 15u, lk = lane >> 4;
+    v4f accr[4][4], acci[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            accr[m][c] = v4f{0, 0, 0, 0};
+            acci[m][c] = v4f{0, 0, 0, 0};
+        }
+    constexpr int kPer = kBr * kTile / 256;  // staged elements per thread and side
+    float2 na_[kPer], nb_[kPer];
+    auto fetch = [&](uint64_t b0) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const uint32_t e = t + uint32_t(q) * 256u, b = e / kTile, r = e % kTile;
+            na_[q] = make_float2(0.f, 0.f);
+            nb_[q] = make_float2(0.f, 0.f);
+            if (b0 + b < nbr) {
+                na_[q] = A[(b0 + b) * rowsA + i0 + r];
+                nb_[q] = B[(b0 + b) * rowsB + j0 + r];
+            }
+        }
+    };
+    fetch(0);
+    for (uint64_t b0 = 0; b0 < nbr; b0 += kBr) {
+        __syncthreads();  // previous chunk's fragments are read
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const uint32_t e = t + uint32_t(q) * 256u, b = e / kTile, r = e % kTile;
+            a1[2 * b][r] = na_[q].x;
+            a1[2 * b + 1][r] = -na_[q].y;
+            a2[2 * b][r] = na_[q].y;
+            a2[2 * b + 1][r] = na_[q].x;
+            b1[2 * b][r] = nb_[q].x;
+            b1[2 * b + 1][r] = nb_[q].y;
+        }
+        __syncthreads();
+        if (b0 + kBr < nbr) fetch(b0 + kBr);  // in flight during the MFMA work
+#pragma unroll
+        for (int ks = 0; ks < kK; ks += 4) {
+            float fa1[4], fa2[4], fb[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                fa1[m] = a1[ks + lk][wr * 64 + m * 16 + lr];
+                fa2[m] = a2[ks + lk][wr * 64 + m * 16 + lr];
+                fb[m] = b1[ks + lk][wc * 64 + m * 16 + lr];
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    accr[m][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa1[m], fb[c], accr[m][c], 0, 0, 0);
+                    acci[m][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa2[m], fb[c], acci[m][c], 0, 0, 0);
+                }
+        }
+    }
+    // epilogue: block (m, c) element r of this lane is row 4*lk + r, column lr
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint64_t i = i0 + wr * 64 + m * 16 + 4 * lk + r;
+            uint64_t xa = 0, fmask = 0;
+            for (int q = 0; q < P.na; ++q)
+                if ((i >> q) & 1ull) xa |= 1ull << P.pos_a[q];
+            for (int f = 0; f < P.n_fold; ++f)
+                if ((i >> P.fold_a[f]) & 1ull) fmask ^= 1ull << P.fold_b[f];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const uint64_t j = j0 + wc * 64 + c * 16 + lr;
+                uint64_t x = xa;
+                for (int q = 0; q < P.nb; ++q)
+                    if ((j >> q) & 1ull) x |= 1ull << P.pos_b[q];
+                const float sgn = (__popcll(fmask & j) & 1) ? -1.f : 1.f;
+                out[x] = make_float2(sgn * accr[m][c][r], sgn * acci[m][c][r]);
+            }
+        }
+    }
+    (void)rowsB;
+}
+
+}  // namespace
+
+hipError_t launch_combine_gemm(const float2 *A, const float2 *B, uint64_t nbr, const CombineArgs &P,
+                               float2 *out, hipStream_t s) {
+    const dim3 grid(unsigned(1ull << (P.na - 7)), unsigned(1ull << (P.nb - 7)));
+    hipLaunchKernelGGL(k_combine_gemm, grid, dim3(256), 0, s, A, B, nbr, P, out);
+    return hipGetLastError();
+}
+
+}  // namespace qsv

@@ -30,6 +30,16 @@ hipError_t launch_norm(const float2 *amps, int n, double *out, double *partials,
 // <a|b> in FP64 into out[0] (re), out[1] (im); partials: 2 * 65536 doubles
 hipError_t launch_dot(const float2 *a, const float2 *b, int n, double *out, double *partials,
                       hipStream_t s);
+// Full-state branch combine (combine.hip).  Local bit q of side A / B sits at
+// global bit pos_a[q] / pos_b[q]; folded pair f couples local A bit fold_a[f]
+// with local B bit fold_b[f].
+struct CombineArgs {
+    int32_t na, nb, n_fold, pad;
+    uint8_t pos_a[64], pos_b[64];
+    uint8_t fold_a[64], fold_b[64];
+};
+hipError_t launch_combine_gemm(const float2 *A, const float2 *B, uint64_t nbr, const CombineArgs &P,
+                               float2 *out, hipStream_t s);
 hipError_t launch_sum_partials(const double *part, uint64_t count, double *out, hipStream_t s);
 hipError_t launch_branch_combine(const float2 *A, const float2 *B, uint64_t nb, uint64_t m,
                                  const int8_t *sign, double2 *out, hipStream_t s);

@@ -30,7 +30,7 @@ EXPORTS = ["circuit_create", "circuit_destroy", "circuit_info", "circuit_gates",
            "sv_norm_fp64", "sv_branch_combine", "sv_simulate", "sv_simulate_c128", "sv_batch_create", "sv_batch_run",
            "sv_batch_destroy", "sv_plan_info", "sv_debug_emulate", "sv_debug_jit_compile",
            "sv_tune", "sv_apply_dense", "sv_debug_emulate_dense", "qsv_release_device_buffers",
-           "circuit_inverse", "sv_inner_product",
+           "circuit_inverse", "sv_inner_product", "sv_branch_combine_full",
            "qsv_last_error", "qsv_version"]
 
 
@@ -82,6 +82,7 @@ def lib():
         "qsv_release_device_buffers": (st, []),
         "circuit_inverse": (st, [vp, P(vp)]),
         "sv_inner_product": (st, [vp, vp, i32, vp, vp]),
+        "sv_branch_combine_full": (st, [vp, vp, sz, i32, i32, u64, vp, vp, sz, vp, vp]),
         "sv_tune": (st, [vp, vp, i32, i32, vp, P(ctypes.c_double), vp]),
         "sv_apply_dense": (st, [vp, vp, u64, i32, i32, i32, P(i32), vp]),
         "sv_debug_emulate_dense": (st, [vp, vp, u64, i32, i32, i32, P(i32)]),
@@ -331,6 +332,18 @@ def circuit_inverse(c) -> Circuit:
 def sv_inner_product(a, b, n_qubits, out_dev, stream=None):
     """<a|b> in FP64 into out_dev (device float64[2] = re, im)."""
     _check(lib().sv_inner_product(_ptr(a), _ptr(b), n_qubits, _ptr(out_dev), _stream(stream)))
+
+
+def sv_branch_combine_full(a_states, b_states, n_branches, n_a, n_b, side_a_mask, folded_a,
+                           folded_b, out_state, stream=None):
+    """Complete state of a cut circuit from all branch states of both halves
+    (folded pairs as returned by circuit_split, host int32 arrays)."""
+    fa = np.ascontiguousarray(np.asarray(folded_a, dtype=np.int32))
+    fb = np.ascontiguousarray(np.asarray(folded_b, dtype=np.int32))
+    _check(lib().sv_branch_combine_full(_ptr(a_states), _ptr(b_states), n_branches, n_a, n_b,
+                                        ctypes.c_uint64(side_a_mask), fa.ctypes.data if fa.size else None,
+                                        fb.ctypes.data if fb.size else None, fa.size, _ptr(out_state),
+                                        _stream(stream)))
 
 
 def release_device_buffers():

@@ -676,6 +676,71 @@ def test_batch_split_5x6_d16_full_check():
     assert d <= TOL and d * 2 ** 15 <= TOL_SCALED, d
 
 
+def _split_branch_states(c, mask, n, nbr_expect=None, jit=0):
+    """All branch states of both halves of a cut circuit, as two contiguous
+    branch-major tensors."""
+    ha, hb, ceff, folded = qsv.circuit_split(c, mask)
+    na = bin(mask).count("1")
+    nb_ = n - na
+    nbr = 1 << ceff
+    if nbr_expect is not None:
+        assert nbr == nbr_expect
+    A = torch.empty(nbr, 1 << na, dtype=torch.complex64, device=DEV)
+    B = torch.empty(nbr, 1 << nb_, dtype=torch.complex64, device=DEV)
+    if min(na, nb_) >= 11:
+        b = qsv.sv_batch_create([ha] * nbr + [hb] * nbr, list(range(nbr)) * 2,
+                                opts=dict(reg_qubits=0, thread_qubits=0, low_qubits=0, plain=0, jit=jit))
+        qsv.sv_batch_run(b, [A[i] for i in range(nbr)] + [B[i] for i in range(nbr)], init_plus=True)
+    else:  # halves too small for a batch: one call per branch state
+        for i in range(nbr):
+            qsv.sv_simulate(A[i], ha, branch=i, init_kind=qsv.INIT_PLUS, layer_begin=1)
+            qsv.sv_simulate(B[i], hb, branch=i, init_kind=qsv.INIT_PLUS, layer_begin=1)
+    torch.cuda.synchronize()
+    return A, B, nbr, na, nb_, folded
+
+
+@pytest.mark.parametrize("depth,col", [(11, 2), (8, 1)])
+def test_combine_full_state_4x6(depth, col):
+    """Full-state combine on matrix cores (Psi = A B^T with the folded sign):
+    4x6 lattice cut after column 2 (12 | 12 qubits, 64 branch pairs) or 1
+    (8 | 16 qubits, 4 branch pairs: fewer than one staged chunk), every
+    amplitude against the unsplit oracle state; both cuts fold final-layer
+    crossings into the sign."""
+    _gpu()
+    rows, cols, seed = 4, 6, 77
+    n = rows * cols
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    mask = workloads.column_cut_mask(rows, cols, col)
+    A, B, nbr, na, nb_, folded = _split_branch_states(c, mask, n)
+    out = torch.empty(1 << n, dtype=torch.complex64, device=DEV)
+    fa = [a for a, _ in folded]
+    fb = [b_ for _, b_ in folded]
+    qsv.sv_branch_combine_full(A, B, nbr, na, nb_, mask, fa, fb, out)
+    ref = sim.simulate(OC.random_circuit(OC.Lattice(rows, cols), depth, seed), n)
+    _check_full(out, ref, n)
+    assert len(folded) > 0  # the sign path is exercised
+
+
+def test_combine_full_state_5x6_d16():
+    """30 qubits at full branch count: 1024 branch pairs of 15-qubit halves
+    combined into the 2^30 state on matrix cores, against the stored oracle
+    amplitudes; FP64 norm of the result."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("5x6-d16")
+    xs, ref = _golden("5x6-d16")
+    n = lat.n
+    mask = workloads.column_cut_mask(spec["rows"], spec["cols"], 2)
+    A, B, nbr, na, nb_, folded = _split_branch_states(c, mask, n, 1024, jit=-1)
+    out = torch.empty(1 << n, dtype=torch.complex64, device=DEV)
+    qsv.sv_branch_combine_full(A, B, nbr, na, nb_, mask, [], [], out)
+    got = out[torch.from_numpy(xs.view(np.int64)).to(DEV)].cpu().numpy()
+    d = np.max(np.abs(got - ref))
+    assert d <= TOL and d * 2 ** (n / 2) <= TOL_SCALED, d
+    nrm = torch.zeros(1, dtype=torch.float64, device=DEV)
+    qsv.sv_norm_fp64(out, n, nrm)
+    assert abs(nrm.item() - 1) <= 1e-5
+
+
 def test_split_7x7_d16_branch_norm_identity():
     """Full-size 49-qubit split (cut after column 3, 28|21): projector branches
     of the 28-qubit half satisfy sum over the last cut group of |A_l|^2 =
