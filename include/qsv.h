@@ -86,8 +86,10 @@ typedef struct qsv_batch qsv_batch;      /* opaque */
  *                  kernel at first use (hipRTC, cached per process), one tile
  *                  per workgroup; 2 = the same kernels as persistent workgroups
  *                  that prefetch their next tile into registers while they
- *                  compute the current one; -1 = always use the generic pass
- *                  kernel; 0 = 1 for states of 2^24 amplitudes or more, else -1
+ *                  compute the current one; 3 = per pass: pass p persistent iff
+ *                  bit p of pass_forms is set (p < 23); -1 = always use the
+ *                  generic pass kernel; 0 = 1 for states of 2^24 amplitudes or
+ *                  more, else -1
  *   out_of_place   compiled kernels only.  1 = every pass reads one buffer and
  *                  writes the other (the caller's state and a second state
  *                  buffer the library allocates once per device and keeps), so
@@ -97,6 +99,7 @@ typedef struct qsv_batch qsv_batch;      /* opaque */
  *                  2^24 amplitudes or more when the second buffer fits.  Calls
  *                  that overlap on one device share the second buffer: run
  *                  them with -1.
+ *   pass_forms     see jit = 3.
  */
 typedef struct {
     int reg_qubits;
@@ -105,6 +108,7 @@ typedef struct {
     int plain;
     int jit;
     int out_of_place;
+    uint32_t pass_forms;
 } qsv_fuse_opts;
 
 /*

@@ -220,6 +220,7 @@ int jit_mode(const qsv_circuit *c, const qsv_fuse_opts *opts) {
         j = 1;
     }
     if (j < 0) return 0;
+    if (j == 3) return 1 | kJitPerPass | int((opts->pass_forms & 0x7fffffu) << 8);
     return j >= 2 ? (1 | kJitLoop) : 1;
 }
 
@@ -238,6 +239,29 @@ void gate_matrix_f32(uint8_t kind, float m[8]) {
 }
 
 }  // namespace
+
+// Per-pass times of the sweep as sv_simulate runs it from |+>^n (the
+// autotuner's choice of kernel form per pass).
+qsv_status time_sweep_passes(const qsv_circuit *c, int lb, int le, const qsv_fuse_opts *opts,
+                             void *amps, hipStream_t s, std::vector<float> &ms) {
+    TileShape sh;
+    qsv_status st = resolve_shape(c, opts, sh, lb, le);
+    if (st != QSV_OK) return st;
+    const int jm = jit_mode(c, opts);
+    if (sh.R == 0 || !jm) return fail(QSV_EUNSUPPORTED, "pass timing needs compiled pass kernels");
+    std::shared_ptr<Plan> plan;
+    void *scratch = nullptr;
+    if ((st = get_fused_plan(c, lb, le, sh, oop_mode(c, opts, jm), false, plan, &scratch)) != QSV_OK)
+        return st;
+    if (plan->passes.empty()) return fail(QSV_EUNSUPPORTED, "empty layer range");
+    const int variant = kJitInit | QSV_INIT_PLUS | (jm & ~3);
+    {
+        std::lock_guard<std::mutex> g(plan->jit_mu);
+        if ((st = jit_prepare(*plan, variant)) != QSV_OK) return st;
+    }
+    return jit_launch(*plan, variant, amps, scratch, 0, 0, nullptr, s, &ms);
+}
+
 }  // namespace qsv
 
 using namespace qsv;
@@ -392,7 +416,7 @@ qsv_status sv_apply_fused(void *amps, const qsv_circuit *c, uint64_t branch, int
         if ((st = get_fused_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jm), true, plan,
                                  &scratch)) != QSV_OK)
             return st;
-        const int variant = kJitPlain | (jm & kJitLoop);
+        const int variant = kJitPlain | (jm & ~3);
         {
             std::lock_guard<std::mutex> g(plan->jit_mu);
             if ((st = jit_prepare(*plan, variant)) != QSV_OK) return st;
@@ -539,7 +563,7 @@ qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int in
     bool done_norm = false;
     if (jm && !plan->passes.empty()) {
         // initial state generated by the first pass, norm by the last
-        const int variant = kJitInit | init_kind | (norm_out_dev ? kJitNorm : 0) | (jm & kJitLoop);
+        const int variant = kJitInit | init_kind | (norm_out_dev ? kJitNorm : 0) | (jm & ~3);
         {
             std::lock_guard<std::mutex> g(plan->jit_mu);
             if ((st = jit_prepare(*plan, variant)) != QSV_OK) return st;

@@ -841,11 +841,11 @@ std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int var
     const bool norm = (variant & 8) != 0;
     const bool dp = (variant & kJitDouble) != 0;
     const bool batched = (variant & kJitBatched) != 0;
-    const bool loop = (variant & kJitLoop) != 0 && !batched;
     std::string src = kPrelude;
     for (size_t p = 0; p < plan.passes.size(); ++p) {
         Gen g(plan.passes[p].prog, plan.R, plan.T, dp);
         bool uses_lds = false;
+        const bool loop = jit_pass_loop(variant, p) && !batched;
         src += g.emit("qsv_pass_" + std::to_string(p), uses_lds, p == 0 ? init_kind : -1,
                       norm && !batched && p + 1 == plan.passes.size(), plan.n, batched, loop);
         if (lds_bytes) lds_bytes->push_back(uses_lds ? size_t(g.lds_elems) * (dp ? 16 : 8) : 0);
@@ -927,7 +927,7 @@ qsv_status jit_prepare(Plan &plan, int variant) {
 }
 
 qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, uint64_t branch,
-                      uint64_t basis, double *part, hipStream_t s) {
+                      uint64_t basis, double *part, hipStream_t s, std::vector<float> *pass_ms) {
     auto vit = plan.jit_variants.find(variant);
     if (vit == plan.jit_variants.end()) return fail(QSV_EINTERNAL, "jit variant not prepared");
     const CacheEntry &e = *static_cast<const CacheEntry *>(vit->second.get());
@@ -939,8 +939,15 @@ qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, 
         return fail(QSV_EINTERNAL, "out-of-place plan without a usable buffer schedule");
     // Out-of-place plans alternate between the two buffers so that the last
     // pass writes the caller's: pass p writes amps when np - p is odd.
+    std::vector<hipEvent_t> ev;
+    if (pass_ms) {  // timing of each pass (autotuner)
+        ev.resize(np + 1);
+        for (auto &x : ev)
+            if (hipEventCreate(&x) != hipSuccess) return fail(QSV_EHIP, "jit_launch: event create");
+    }
     void *in = amps;
     for (size_t p = 0; p < np; ++p) {
+        if (pass_ms && hipEventRecord(ev[p], s) != hipSuccess) return fail(QSV_EHIP, "jit_launch: event");
         void *outb = (!plan.oop || (np - p) % 2 == 1) ? amps : scratch;
         for (uint64_t t0 = 0; t0 < tiles; t0 += chunk) {
             const uint64_t cnt = (tiles - t0 < chunk) ? tiles - t0 : chunk;
@@ -949,13 +956,20 @@ qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, 
             double *pt = part;
             void *args[] = {&src, &dst, &br, &tt, &bs, &pt, &nt};
             // a looping kernel gets as many workgroups as the device holds at once
-            const uint64_t grid = (variant & kJitLoop) ? std::min<uint64_t>(cnt, e.resident[p]) : cnt;
+            const uint64_t grid = jit_pass_loop(variant, p) ? std::min<uint64_t>(cnt, e.resident[p]) : cnt;
             hipError_t he = hipModuleLaunchKernel(e.fns[p], unsigned(grid), 1, 1, 1u << plan.T, 1, 1,
                                                   unsigned(e.lds[p]), s, args, nullptr);
             if (he != hipSuccess)
                 return fail(QSV_EHIP, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(he));
         }
         in = outb;
+    }
+    if (pass_ms) {
+        bool ok = hipEventRecord(ev[np], s) == hipSuccess && hipEventSynchronize(ev[np]) == hipSuccess;
+        pass_ms->assign(np, 0.f);
+        for (size_t p = 0; p < np && ok; ++p) ok = hipEventElapsedTime(&(*pass_ms)[p], ev[p], ev[p + 1]) == hipSuccess;
+        for (auto &x : ev) hipEventDestroy(x);
+        if (!ok) return fail(QSV_EHIP, "jit_launch: pass timing");
     }
     return QSV_OK;
 }

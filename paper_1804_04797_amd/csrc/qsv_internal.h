@@ -1,6 +1,8 @@
 // Internal declarations of the qsv library (host side).
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 #include <map>
 #include <memory>
@@ -151,6 +153,9 @@ void gates_in_range(const qsv_circuit &c, int lb, int le, std::vector<int> &idx)
 
 // tune.cpp: the shape sv_tune picked for this circuit and layer range, if any
 bool tuned_opts(const qsv_circuit *c, int lb, int le, qsv_fuse_opts *out);
+// capi.cpp: per-pass times of the compiled sweep from |+>^n (for the tuner)
+qsv_status time_sweep_passes(const qsv_circuit *c, int lb, int le, const qsv_fuse_opts *opts,
+                             void *amps, hipStream_t s, std::vector<float> &ms);
 
 // dense.cpp
 qsv_status build_dense_plan(const qsv_circuit &c, int lb, int le, int k, uint64_t branch,

@@ -43,7 +43,7 @@ class QsvError(RuntimeError):
 class FuseOpts(ctypes.Structure):
     _fields_ = [("reg_qubits", ctypes.c_int), ("thread_qubits", ctypes.c_int),
                 ("low_qubits", ctypes.c_int), ("plain", ctypes.c_int), ("jit", ctypes.c_int),
-                ("out_of_place", ctypes.c_int)]
+                ("out_of_place", ctypes.c_int), ("pass_forms", ctypes.c_uint32)]
 
 
 _lib = None
@@ -360,7 +360,7 @@ def sv_tune(amps_scratch, c, layer_begin=0, layer_end=-1, stream=None):
                          ctypes.byref(ms), _stream(stream)))
     return ({"reg_qubits": o.reg_qubits, "thread_qubits": o.thread_qubits,
              "low_qubits": o.low_qubits, "plain": 0, "jit": o.jit,
-             "out_of_place": o.out_of_place}, ms.value)
+             "out_of_place": o.out_of_place, "pass_forms": o.pass_forms}, ms.value)
 
 
 def sv_apply_dense(amps, c, k, branch=0, layer_begin=0, layer_end=-1, stream=None):

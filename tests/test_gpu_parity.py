@@ -505,6 +505,23 @@ def test_out_of_place_sweeps(shape, jit):
         assert abs(nrm.item() - n2.item()) <= 1e-12
 
 
+@pytest.mark.parametrize("forms", [0b101, 0b010, 0b1])
+def test_per_pass_kernel_forms(forms):
+    """jit = 3: each pass in its own kernel form (bit p of pass_forms = pass p
+    persistent), in place and out of place, against the oracle."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("4x5-d10")
+    n = lat.n
+    ref = sim.simulate(_oracle_gates(c), n)
+    for oop in (1, -1):
+        o = dict(reg_qubits=4, thread_qubits=6, low_qubits=5, plain=0, jit=3, out_of_place=oop,
+                 pass_forms=forms)
+        assert qsv.sv_plan_info(c, opts=o)["n_passes"] >= 3
+        a = _state(n)
+        qsv.sv_apply_fused(a, c, opts=o)
+        _check_full(a, ref, n)
+
+
 @pytest.mark.parametrize("shape", [(5, 8, 4), (4, 7, 4)])
 def test_persistent_kernels_many_tiles(shape):
     """24 qubits: 2^11 or 2^13 tiles, several per resident workgroup, so the
