@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <thread>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -74,6 +76,13 @@ void drop_graph(qsv_batch *b) {
     b->exec = nullptr;
 }
 
+// Size classes: states of 2^23 amplitudes or more stream from HBM and are
+// swept by compiled kernels of their own plan (unless jit = -1); smaller ones
+// share the batch's tile shape and the generic kernel (or compiled kernels per
+// plan shared by >= 8 entries).
+constexpr int kBigState = 23;
+bool big_state(const qsv_batch *b, int n) { return b->jit_mode >= 0 && n >= kBigState; }
+
 // Plans and device tables for layers [lb, end) of every entry.
 qsv_status build_tables(qsv_batch *b, int lb) {
     drop_graph(b);
@@ -85,7 +94,11 @@ qsv_status build_tables(qsv_batch *b, int lb) {
         auto it = idx.find(b->circs[i]);
         if (it == idx.end()) {
             qsv_circuit *c = const_cast<qsv_circuit *>(b->circs[i]);
-            PlanKey key{lb, -1, b->R, b->T, b->c, false};
+            // states of the HBM-streaming class get their own compiled
+            // kernels with the single-state default tile shape
+            TileShape sh{b->R, b->T, b->c};
+            if (big_state(b, c->n)) sh = default_shape(c->n);
+            PlanKey key{lb, -1, sh.R, sh.T, sh.c, false};
             std::shared_ptr<Plan> p;
             {
                 std::lock_guard<std::mutex> g(c->mu);
@@ -94,7 +107,7 @@ qsv_status build_tables(qsv_batch *b, int lb) {
                     p = pit->second;
                 } else {
                     p = std::make_shared<Plan>();
-                    qsv_status st = build_plan(*c, lb, -1, TileShape{b->R, b->T, b->c}, *p);
+                    qsv_status st = build_plan(*c, lb, -1, sh, *p);
                     if (st != QSV_OK) return st;
                     c->plans[key] = p;
                 }
@@ -110,8 +123,10 @@ qsv_status build_tables(qsv_batch *b, int lb) {
     b->d_group_ents.assign(b->plans.size(), nullptr);
     for (size_t p = 0; p < b->plans.size(); ++p) {
         const bool shared = b->group[p].size() >= 8;
+        const bool big = big_state(b, b->plans[p]->n);
         b->plan_jit[p] = !b->plans[p]->passes.empty() &&
-                         (b->jit_mode > 0 || (b->jit_mode == 0 && shared)) && b->group[p].size() < 65536;
+                         (b->jit_mode > 0 || (b->jit_mode == 0 && (shared || big))) &&
+                         b->group[p].size() < 65536;
         if (b->plan_jit[p]) {
             hipError_t e = hipMalloc(reinterpret_cast<void **>(&b->d_group_ents[p]),
                                      b->group[p].size() * sizeof(BatchEntry));
@@ -255,6 +270,7 @@ qsv_status sv_batch_run(qsv_batch *b, void *const *amps_dev, int init_plus,
         e = hipMemcpy(b->d_ents, b->h_ents.data(), count * sizeof(BatchEntry), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hipfail(e, "sv_batch_run: entry upload");
         const int variant = kJitBatched | (init_plus ? (kJitInit | QSV_INIT_PLUS) : 0);
+        std::vector<size_t> jp;
         for (size_t p = 0; p < b->plans.size(); ++p) {
             if (!b->plan_jit[p]) continue;
             std::vector<BatchEntry> ge;
@@ -262,8 +278,27 @@ qsv_status sv_batch_run(qsv_batch *b, void *const *amps_dev, int init_plus,
             e = hipMemcpy(b->d_group_ents[p], ge.data(), ge.size() * sizeof(BatchEntry),
                           hipMemcpyHostToDevice);
             if (e != hipSuccess) return hipfail(e, "sv_batch_run: group entry upload");
-            std::lock_guard<std::mutex> g(b->plans[p]->jit_mu);
-            if ((st = jit_prepare(*b->plans[p], variant)) != QSV_OK) return st;
+            jp.push_back(p);
+        }
+        // compile the plans' kernels concurrently
+        {
+            int dev = 0;
+            if ((e = hipGetDevice(&dev)) != hipSuccess) return hipfail(e, "sv_batch_run");
+            const unsigned nth = std::max(1u, std::min<unsigned>(16, std::thread::hardware_concurrency()));
+            std::atomic<size_t> next{0};
+            std::vector<qsv_status> res(jp.size(), QSV_OK);
+            std::vector<std::thread> pool;
+            for (unsigned w = 0; w < std::min<size_t>(nth, jp.size()); ++w)
+                pool.emplace_back([&, dev] {
+                    (void)hipSetDevice(dev);
+                    for (size_t k; (k = next++) < jp.size();) {
+                        std::lock_guard<std::mutex> g(b->plans[jp[k]]->jit_mu);
+                        res[k] = jit_prepare(*b->plans[jp[k]], variant);
+                    }
+                });
+            for (auto &th : pool) th.join();
+            for (qsv_status r : res)
+                if (r != QSV_OK) return fail(r, "sv_batch_run: compiling pass kernels failed");
         }
         e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hipfail(e, "sv_batch_run: begin capture");

@@ -872,6 +872,9 @@ qsv_status jit_compile_only(const Plan &plan, size_t *code_bytes, double *second
     return QSV_OK;
 }
 
+// Compiles outside the cache lock, so that several plans can be prepared
+// from concurrent threads (the batch does); a source compiled twice by racing
+// threads keeps the first module.
 qsv_status jit_prepare(Plan &plan, int variant) {
     if (plan.jit_variants.count(variant)) return QSV_OK;
     int dev = 0;
@@ -888,41 +891,46 @@ qsv_status jit_prepare(Plan &plan, int variant) {
     }
     std::vector<size_t> lds;
     std::string src = jit_source(plan, &lds, variant);
-    std::lock_guard<std::mutex> g(g_mu);
     auto key = std::make_pair(dev, src);
-    auto it = g_cache.find(key);
-    if (it == g_cache.end()) {
-        auto e = std::make_shared<CacheEntry>();
-        std::vector<char> code;
-        std::string log;
-        auto t0 = std::chrono::steady_clock::now();
-        qsv_status st = compile_source(src, code, log);
-        if (st != QSV_OK) return st;
-        he = hipModuleLoadData(&e->mod, code.data());
-        if (he != hipSuccess)
-            return fail(QSV_EHIP, std::string("hipModuleLoadData: ") + hipGetErrorString(he));
-        for (size_t p = 0; p < plan.passes.size(); ++p) {
-            hipFunction_t f;
-            he = hipModuleGetFunction(&f, e->mod, ("qsv_pass_" + std::to_string(p)).c_str());
-            if (he != hipSuccess)
-                return fail(QSV_EHIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(he));
-            e->fns.push_back(f);
-            int per_cu = 0, cus = 0;
-            he = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 1 << plan.T, lds[p]);
-            if (he != hipSuccess)
-                return fail(QSV_EHIP, std::string("occupancy query: ") + hipGetErrorString(he));
-            he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-            if (he != hipSuccess)
-                return fail(QSV_EHIP, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(he));
-            e->resident.push_back(unsigned(std::max(1, per_cu) * std::max(1, cus)));
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            g_pcache[pkey] = it->second;
+            plan.jit_variants[variant] = it->second;
+            return QSV_OK;
         }
-        e->lds = lds;
-        e->compile_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        g_total_compile_s += e->compile_s;
-        it = g_cache.emplace(key, e).first;
     }
-    g_pcache[pkey] = it->second;
-    plan.jit_variants[variant] = it->second;
+    auto e = std::make_shared<CacheEntry>();
+    std::vector<char> code;
+    std::string log;
+    auto t0 = std::chrono::steady_clock::now();
+    qsv_status st = compile_source(src, code, log);
+    if (st != QSV_OK) return st;
+    he = hipModuleLoadData(&e->mod, code.data());
+    if (he != hipSuccess) return fail(QSV_EHIP, std::string("hipModuleLoadData: ") + hipGetErrorString(he));
+    int cus = 0;
+    he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (he != hipSuccess) return fail(QSV_EHIP, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(he));
+    for (size_t p = 0; p < plan.passes.size(); ++p) {
+        hipFunction_t f;
+        he = hipModuleGetFunction(&f, e->mod, ("qsv_pass_" + std::to_string(p)).c_str());
+        if (he != hipSuccess)
+            return fail(QSV_EHIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(he));
+        e->fns.push_back(f);
+        int per_cu = 0;
+        he = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 1 << plan.T, lds[p]);
+        if (he != hipSuccess) return fail(QSV_EHIP, std::string("occupancy query: ") + hipGetErrorString(he));
+        e->resident.push_back(unsigned(std::max(1, per_cu) * std::max(1, cus)));
+    }
+    e->lds = lds;
+    e->compile_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    std::lock_guard<std::mutex> g(g_mu);
+    auto ins = g_cache.emplace(key, e);
+    if (ins.second) g_total_compile_s += e->compile_s;
+    else hipModuleUnload(e->mod);  // another thread compiled the same source first
+    g_pcache[pkey] = ins.first->second;
+    plan.jit_variants[variant] = ins.first->second;
     return QSV_OK;
 }
 

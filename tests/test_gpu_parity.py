@@ -586,6 +586,27 @@ def _uneven(count, n_range, d_range, seed):
     return out
 
 
+def test_batch_size_classes():
+    """A batch mixing the generic class (12..16 qubits, shared tile shape,
+    generic kernel) and the HBM-streaming class (23, 24 qubits: compiled
+    kernels of their own plan and tile shape, compiled concurrently), every
+    state against the oracle."""
+    _gpu()
+    items = []
+    for i, (n, d) in enumerate([(12, 8), (16, 10), (23, 8), (14, 9), (24, 7)]):
+        rows, cols, pres = workloads.lattice_for_qubits(n)
+        seed = 0xC1A55 + i
+        items.append((qsv.circuit_create(rows, cols, pres, d, seed),
+                      OC.random_circuit(OC.Lattice.for_qubits(n), d, seed), n))
+    b = qsv.sv_batch_create([c for c, _, _ in items])
+    states = [torch.empty(1 << n, dtype=torch.complex64, device=DEV) for _, _, n in items]
+    qsv.sv_batch_run(b, states, init_plus=True)
+    torch.cuda.synchronize()
+    for st, (_, gates, n) in zip(states, items):
+        ref = sim.run(np.full(1 << n, 2.0 ** (-n / 2), np.complex128), n, [g for g in gates if g[3] >= 1])
+        _check_full(st, ref, n)
+
+
 @pytest.mark.parametrize("jit", [0, 1])
 @pytest.mark.parametrize("init_plus", [False, True])
 def test_batch_uneven_circuits(init_plus, jit):
