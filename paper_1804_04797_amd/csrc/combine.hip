@@ -30,7 +30,7 @@ constexpr int kTile = 128;  // output rows (x_A) and columns (x_B) per workgroup
 constexpr int kBr = 16;     // branches per LDS chunk
 constexpr int kK = 2 * kBr; // interleaved K per chunk
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_combine_gemm(const float2 *__restrict__ A, const float2 *__restrict__ B, uint64_t nbr,
                const CombineArgs P, float2 *__restrict__ out) {
     __shared__ float a1[kK][kTile], a2[kK][kTile], b1[kK][kTile];
