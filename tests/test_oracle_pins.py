@@ -6,6 +6,7 @@ published generator, dense Kronecker-product brute force, closed forms,
 invariants, and exact identities.
 """
 import cmath
+import itertools
 import math
 import random
 
@@ -438,3 +439,191 @@ def test_combine_exact_on_integers():
     got = sim.combine(a, b, signs)
     want = signs * np.sum(a * b, axis=0)
     assert np.array_equal(got, want)
+
+
+# ----------------------------------------------------------------------------
+# Three-part partition (Section 2.1.1 eqs. (2)-(3); Section 2.1.2 Algorithm 1)
+# ----------------------------------------------------------------------------
+
+from oracle import partition as PT  # noqa: E402
+
+
+def _line_sequences(lat, r0, gates, t_s, offs, upper):
+    """Every legal, non-decreasing sequence of one line's offsets (brute force)."""
+    depth, cz = PT._layers(gates)
+    cross = PT.upper_crosses if upper else PT.lower_crosses
+    positions = [p for p in itertools.product(*[range(m + 1) for m in offs])]
+    seqs = [[]]
+    for t in range(t_s, depth + 1):
+        nxt = []
+        for s in seqs:
+            prev = s[-1] if s else tuple([0] * lat.cols)
+            for p in positions:
+                if all(a >= b for a, b in zip(p, prev)) and not cross(lat, r0, p, cz[t]):
+                    nxt.append(s + [p])
+        seqs = nxt
+    return seqs
+
+
+def _brute_force_best(lat, gates, r0, max_move):
+    """Smallest 2^f + 2^g + 2^c over all separation layers and line sequences.
+
+    The objective separates: f depends on the upper line only, g on the lower
+    one, c on both final positions; free cuts are recounted per sequence from
+    the enter layers, independently of the dynamic programme.
+    """
+    depth, _ = PT._layers(gates)
+    site = PT._sites(lat)
+    up_max, dn_max = PT.max_offsets(lat, r0, max_move)
+    nA = sum(1 for q in range(lat.n) if site[q][0] < r0)
+    nB = lat.n - nA
+    best = None
+    for t_s in range(1, depth + 2):
+        cuts = PT.cuts_before(lat, gates, r0, t_s)
+        K = len(cuts)
+
+        def side_values(upper, offs):
+            vals = []
+            for seq in _line_sequences(lat, r0, gates, t_s, offs, upper):
+                fin = seq[-1] if seq else tuple([0] * lat.cols)
+                enter = {}
+                for q in range(lat.n):
+                    r, c = site[q]
+                    enter[q] = depth + 1
+                    for k, p in enumerate(seq):
+                        inside = (r0 - p[c] <= r < r0) if upper else (r0 <= r < r0 + p[c])
+                        if inside:
+                            enter[q] = t_s + k
+                            break
+                not_free = 0
+                for gi, a, b, _t in cuts:
+                    q = a if upper else b
+                    if not PT.free_after(gates, gi, q, enter[q]):
+                        not_free += 1
+                cnt = 0
+                for q in range(lat.n):
+                    r, c = site[q]
+                    if (r0 - fin[c] <= r < r0) if upper else (r0 <= r < r0 + fin[c]):
+                        cnt += 1
+                vals.append((not_free, cnt))
+            return vals
+
+        for nfa, ca in side_values(True, up_max):
+            for nfb, cb in side_values(False, dn_max):
+                obj = 2 ** (nA + nfa) + 2 ** (nB + nfb) + 2 ** (ca + cb)
+                best = obj if best is None else min(best, obj)
+    return best
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed,r0,mm", [
+    (2, 3, 6, 1, 1, 1), (3, 3, 5, 2, 1, 2), (3, 3, 6, 3, 2, 1), (3, 2, 8, 4, 1, 2), (2, 4, 7, 5, 1, 1)])
+def test_partition_dp_matches_brute_force(rows, cols, depth, seed, r0, mm):
+    lat = C.Lattice(rows, cols)
+    gates = C.random_circuit(lat, depth, seed)
+    s = PT.plan(lat, gates, r0, mm)
+    assert s["objective"] == _brute_force_best(lat, gates, r0, mm)
+    ev = PT.evaluate(lat, gates, s)          # the scheme is legal and scores what it claims
+    assert ev["objective"] == s["objective"]
+    assert (ev["f"], ev["g"], ev["c"]) == (s["f"], s["g"], s["c"])
+
+
+def test_partition_evaluate_rejects_illegal_schemes():
+    lat = C.Lattice(3, 3)
+    gates = C.random_circuit(lat, 6, 7)
+    depth = 6
+    # the lines at the initial position after t_s = 1 cut the vertical CZs of
+    # layer 3 (pattern V10 joins rows 1-2 in column 0 and 2)
+    zero = [(0, 0, 0)] * depth
+    with pytest.raises(ValueError):
+        PT.evaluate(lat, gates, {"r0": 2, "t_s": 1, "ups": zero, "dns": zero})
+    # offsets that shrink again
+    ups = [(1, 1, 1)] * 2 + [(0, 1, 1)] + [(1, 1, 1)] * 3
+    with pytest.raises(ValueError):
+        PT.evaluate(lat, gates, {"r0": 2, "t_s": 1, "ups": ups, "dns": [(1, 1, 1)] * depth})
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed,r0", [(3, 4, 8, 77, 1), (3, 4, 8, 77, 2), (4, 4, 9, 11, 2),
+                                                     (4, 3, 10, 12, 1)])
+def test_partition_state_equals_direct_simulation(rows, cols, depth, seed, r0):
+    """eqs. (2)-(3): U_C sum_l phi_l (x) xi_l is the circuit's output state."""
+    lat = C.Lattice(rows, cols)
+    gates = C.random_circuit(lat, depth, seed)
+    direct = sim.simulate(gates, lat.n)
+    schemes = [PT.plan(lat, gates, r0, 3)]
+    # no part C: the plain two-part split with every crossing CZ cut
+    schemes.append({"r0": r0, "t_s": depth + 1, "ups": [], "dns": []})
+    for s in schemes:
+        psi = PT.partition_state(lat, gates, s)
+        assert np.max(np.abs(psi - direct)) < 1e-13
+
+
+def test_partition_detects_a_dropped_part_c_gate():
+    lat = C.Lattice(3, 4)
+    gates = C.random_circuit(lat, 8, 77)
+    s = PT.plan(lat, gates, 1, 3)
+    ev, ga, gb, gc = PT.parts(lat, gates, s)
+    assert any(g[0] not in PT.DIAGONAL for g in gc)
+    # the same method with one non-diagonal gate of part C left out no longer
+    # reproduces the state: part C's gates are really applied after the combine
+    drop = next(i for i, g in enumerate(gates) if g in gc and g[0] not in PT.DIAGONAL)
+    direct = sim.simulate(gates[:drop] + gates[drop + 1:], lat.n)
+    psi = PT.partition_state(lat, gates, s)
+    assert np.max(np.abs(psi - direct)) > 1e-3
+
+
+def test_implicit_decomposition_identity():
+    """A cut free on side B: xi_l = [x_b = l] xi' (the projector is absorbed)."""
+    lat = C.Lattice(3, 4)
+    gates = C.random_circuit(lat, 8, 77)
+    s = PT.plan(lat, gates, 1, 3)
+    ev, ga, gb, gc = PT.parts(lat, gates, s)
+    free = [x for x in ev["cuts"] if x["free_b"]]
+    assert free
+    x = free[0]
+    qb = ev["qb"]
+    loc = {q: i for i, q in enumerate(qb)}
+    others = [c for c in ev["cuts"] if c is not x]
+    for l in (0, 1):
+        with_p, without = [], []
+        for g in gb:
+            if g[0] == "CUT":
+                if g[1] == x["gate"]:
+                    with_p.append(("P1" if l else "P0", x["b"], -1, x["layer"]))
+                else:  # other cuts: branch 0
+                    c = next(c for c in others if c["gate"] == g[1])
+                    with_p.append(("P0", c["b"], -1, c["layer"]))
+                    without.append(("P0", c["b"], -1, c["layer"]))
+            else:
+                with_p.append(g)
+                without.append(g)
+        lb = [(g[0], loc[g[1]], loc[g[2]] if g[2] >= 0 else -1, g[3]) for g in with_p]
+        lw = [(g[0], loc[g[1]], loc[g[2]] if g[2] >= 0 else -1, g[3]) for g in without]
+        xi = sim.simulate(lb, len(qb))
+        xi0 = sim.simulate(lw, len(qb))
+        idx = np.arange(xi.size)
+        mask = ((idx >> loc[x["b"]]) & 1) == l
+        assert np.max(np.abs(xi - np.where(mask, xi0, 0))) < 1e-14
+
+
+def test_paper_4qubit_example_partition_sizes():
+    """Fig. 3 example as a 4 x 1 lattice (qubit r at row r), lines after row 1.
+
+    The paper gives S_A = 16 and S_C = 4, and S_B = 8 by absorbing the second
+    cut (no gate at all follows it on qubit 2 in part B).  Only diagonal gates
+    (CZ^{2,3}, T^2) follow the first cut on qubit 2, so that projector commutes
+    to the end of part B as well: S_B = 4 here (xi_{l1,l2} = 0 unless
+    l1 = l2 = x_2, which the zero-invariant test above shows for l2).
+    """
+    full, part_c = _paper_4qubit_example()
+    gates = full + part_c
+    lat = C.Lattice(4, 1)
+    scheme = {"r0": 2, "t_s": 4, "ups": [(0,), (1,), (1,), (1,), (1,)],
+              "dns": [(1,), (1,), (1,), (1,), (1,)]}
+    ev = PT.evaluate(lat, gates, scheme)
+    assert len(ev["cuts"]) == 2
+    assert 2 ** ev["f"] == 16 and 2 ** ev["c"] == 4 and 2 ** ev["g"] == 4
+    assert [(x["free_a"], x["free_b"]) for x in ev["cuts"]] == [(False, True), (False, True)]
+    _, ga, gb, gc = PT.parts(lat, gates, scheme)
+    assert sorted((g[0], g[1]) for g in gc) == sorted((g[0], g[1]) for g in part_c)
+    psi = PT.partition_state(lat, gates, scheme)
+    assert np.max(np.abs(psi - sim.simulate(gates, 4))) < 1e-14
