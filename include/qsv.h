@@ -380,6 +380,89 @@ qsv_status sv_debug_jit_compile(const qsv_circuit *c, int layer_begin, int layer
                                 const qsv_fuse_opts *opts, size_t *code_bytes, double *seconds);
 
 /*
+ * Three-part partition (Section 2.1.1: implicit decomposition, eqs. (2)-(3);
+ * Section 2.1.2: the dynamic programme of Algorithm 1).
+ *
+ * The circuit must be a lattice circuit (rows x cols, present mask as for
+ * circuit_create, qubit = row-major rank among present sites) without branch
+ * gates.  Two splitting lines run between lattice rows.  Initially both lie
+ * between rows r0-1 and r0: part A's qubits are the sites with row < r0,
+ * part B's the others.  From the separation layer t_s (1..depth+1) on, the
+ * upper line sits ups[k] rows higher and the lower line dns[k] rows lower in
+ * column k (non-decreasing over layers); at a layer t >= t_s a site (r, k)
+ * belongs to A if r < r0 - ups[k], to B if r >= r0 + dns[k], else to part C.
+ * Every CZ of layers 1..t_s-1 joining the two sides is cut (CZ = sum_l Z^l
+ * (x) P_l); from t_s on no CZ may join two different parts.  Then
+ * psi_out = U_C sum_l phi_l (x) xi_l: the gates of part C act on the block of
+ * each fixed value of the other qubits independently.
+ *
+ * A cut is free on a side when its qubit there receives no non-diagonal gate
+ * of that part after the cut: the projector is then absorbed (that side needs
+ * no branch bit; the other side's branch is selected by the qubit's value).
+ * A cut free on both sides is the output sign (-1)^{x_a x_b}.  Space exponents
+ * f = n_A + (cuts not free on A), g = n_B + (cuts not free on B), n_c = size
+ * of part C after the last layer.
+ *
+ * circuit_partition_plan: Algorithm 1 for both lines (offsets capped by
+ *   max_move and the rows available) for every separation layer; keeps the
+ *   scheme with the smallest 2^f + 2^g + 2^n_c.
+ * circuit_partition_create: an explicit scheme; ups / dns hold
+ *   (depth + 1 - t_s) x cols offsets (layer-major); QSV_EINVAL if illegal.
+ * circuit_partition_offsets: the scheme's offsets (cap >= (depth+1-t_s)*cols).
+ * circuit_partition_parts: copies of the three part circuits (caller
+ *   destroys them).  A and B use local qubit numbers (qubits_a / qubits_b,
+ *   may be NULL, receive the global qubit of each local one, n_a / n_b
+ *   entries); their branch index holds the shared bits first, then the
+ *   selector bits.  C uses global numbers.
+ * All of these are host-only.
+ */
+typedef struct qsv_partition qsv_partition;  /* opaque, host-owned */
+typedef struct {
+    int r0, t_s, depth, cols;
+    int n_a, n_b, n_c;       /* qubits of parts A, B and (after the last layer) C */
+    int cuts;                /* cut CZ gates */
+    int explicit_bits;       /* cuts with a branch bit on both sides */
+    int sel_a, sel_b;        /* A (B) qubits whose value selects B's (A's) branch */
+    int folded;              /* cuts folded into the output sign */
+    int f, g;                /* space exponents of parts A and B */
+    double objective;        /* 2^f + 2^g + 2^n_c */
+    uint64_t branches_a;     /* branch states of part A: 2^(explicit_bits + sel_b) */
+    uint64_t branches_b;     /* branch states of part B: 2^(explicit_bits + sel_a) */
+} qsv_partition_info;
+
+qsv_status circuit_partition_plan(const qsv_circuit *c, int rows, int cols, const uint8_t *present,
+                                  int r0, int max_move, qsv_partition **out);
+qsv_status circuit_partition_create(const qsv_circuit *c, int rows, int cols, const uint8_t *present,
+                                    int r0, int t_s, const uint8_t *ups, const uint8_t *dns,
+                                    qsv_partition **out);
+qsv_status circuit_partition_info(const qsv_partition *p, qsv_partition_info *out);
+qsv_status circuit_partition_offsets(const qsv_partition *p, uint8_t *ups, uint8_t *dns, size_t cap);
+qsv_status circuit_partition_parts(const qsv_partition *p, qsv_circuit **a, qsv_circuit **b,
+                                   qsv_circuit **c, int32_t *qubits_a, int32_t *qubits_b);
+void circuit_partition_destroy(qsv_partition *p);
+
+/*
+ * sv_partition_simulate - psi_out of the circuit through its partition
+ * (eqs. (2)-(3)) into out_state (device complex64[2^n], natural order):
+ *   1. every branch state of parts A and B, from |+> with layer 0 folded in,
+ *      into workspace: one batch (sv_batch_*) for the parts of 11 or more
+ *      qubits, one sv_simulate call per branch for a smaller part;
+ *   2. psi_in = s(x) sum_e phi_{e,u(x)}[x_A] xi_{e,w(x)}[x_B] (e = shared
+ *      branch bits, u / w = the selector qubits' values) as complex GEMMs on
+ *      FP32 matrix cores, one per value of the selector qubits;
+ *   3. the gates of part C with sv_apply_fused on out_state.
+ * workspace: device memory of sv_partition_workspace_bytes bytes (A's branch
+ * states, then B's), caller-owned; the partition keeps the batch it built for
+ * this workspace until it is destroyed, so the workspace must stay alive as
+ * long as the partition is used with it.  Limits: n <= 34, n_a - sel_a >= 7,
+ * 7 <= n_b - sel_b <= 22 (QSV_EUNSUPPORTED otherwise).  Asynchronous on
+ * stream (the first call per workspace builds and captures the batch).
+ */
+qsv_status sv_partition_workspace_bytes(const qsv_partition *p, size_t *bytes);
+qsv_status sv_partition_simulate(qsv_partition *p, void *workspace, size_t ws_bytes, void *out_state,
+                                 void *stream);
+
+/*
  * qsv_release_device_buffers - free the device memory the library keeps on
  * the current device between calls: the second state buffer of out-of-place
  * sweeps (8 * 2^n bytes, allocated at the first such sweep) and the FP64

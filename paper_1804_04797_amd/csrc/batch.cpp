@@ -224,7 +224,8 @@ qsv_status sv_batch_create(const qsv_circuit *const *circs, const uint64_t *bran
         b->R = opts->reg_qubits;
         b->T = opts->thread_qubits;
     }
-    if (b->R == 0) return fail(QSV_EUNSUPPORTED, "sv_batch_create: states need >= 11 qubits");
+    if (b->R == 0 || nmin < kBatchMinQubits)
+        return fail(QSV_EUNSUPPORTED, "sv_batch_create: states need >= 11 qubits");
     const bool ok = (b->R == 5 && (b->T == 8 || b->T == 7)) || (b->R == 4 && (b->T == 8 || b->T == 7));
     if (!ok) return fail(QSV_EUNSUPPORTED, "sv_batch_create: no batch kernel for this tile shape");
     if (b->R + b->T > nmin) return fail(QSV_EUNSUPPORTED, "sv_batch_create: tile larger than a state");

@@ -487,8 +487,10 @@ qsv_status sv_branch_combine_full(const void *a_states, const void *b_states, si
         if (reinterpret_cast<uintptr_t>(p) % 8) return fail(QSV_EINVAL, "sv_branch_combine_full: misaligned buffer");
     CombineArgs P;
     std::memset(&P, 0, sizeof(P));
-    P.na = n_a;
-    P.nb = n_b;
+    P.na = P.na_blk = n_a;
+    P.nb = P.nb_blk = n_b;
+    P.a_stride = 1ull << n_a;
+    P.b_stride = 1ull << n_b;
     int local[64];
     {
         int ka = 0, kb = 0;
@@ -511,6 +513,106 @@ qsv_status sv_branch_combine_full(const void *a_states, const void *b_states, si
                                        n_branches, P, static_cast<float2 *>(out_state),
                                        static_cast<hipStream_t>(stream));
     return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_branch_combine_full");
+}
+
+qsv_status sv_partition_workspace_bytes(const qsv_partition *p, size_t *bytes) {
+    if (!p || !bytes) return fail(QSV_EINVAL, "sv_partition_workspace_bytes: null argument");
+    PartitionLayout L;
+    partition_layout(p, L);
+    const int ea = L.na + L.eb + L.kb, eb = L.nb + L.eb + L.ka;
+    if (ea > 40 || eb > 40) return fail(QSV_ERANGE, "sv_partition_workspace_bytes: parts too large");
+    *bytes = sizeof(float) * 2 * ((size_t(1) << ea) + (size_t(1) << eb));
+    return QSV_OK;
+}
+
+qsv_status sv_partition_simulate(qsv_partition *p, void *workspace, size_t ws_bytes, void *out_state,
+                                 void *stream) {
+    if (!p || !workspace || !out_state) return fail(QSV_EINVAL, "sv_partition_simulate: null argument");
+    PartitionLayout L;
+    partition_layout(p, L);
+    qsv_status st = check_state(out_state, L.n);
+    if (st != QSV_OK) return st;
+    size_t need = 0;
+    if ((st = sv_partition_workspace_bytes(p, &need)) != QSV_OK) return st;
+    if (ws_bytes < need) return fail(QSV_EINVAL, "sv_partition_simulate: workspace too small");
+    if (reinterpret_cast<uintptr_t>(workspace) % 16) return fail(QSV_EINVAL, "sv_partition_simulate: misaligned workspace");
+    const int rows_blk = L.na - L.ka, cols_blk = L.nb - L.kb;
+    if (rows_blk < 7 || cols_blk < 7 || cols_blk > 22)
+        return fail(QSV_EUNSUPPORTED, "sv_partition_simulate: needs n_a - sel_a >= 7 and 7 <= n_b - sel_b <= 22");
+    if (L.fold_a.size() > 64) return fail(QSV_ERANGE, "sv_partition_simulate: more than 64 folded pairs");
+    if ((st = check_device()) != QSV_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t nbr_a = size_t(1) << (L.eb + L.kb), nbr_b = size_t(1) << (L.eb + L.ka);
+    float2 *wa = static_cast<float2 *>(workspace);
+    float2 *wb = wa + (nbr_a << L.na);
+    // 1. branch states of both parts from |+> (layer 0 folded): one batch
+    // (built once per workspace) for the parts of kBatchMinQubits or more,
+    // one sv_simulate call per branch for a smaller part
+    void **bws = nullptr;
+    qsv_batch **batch = partition_batch(p, &bws);
+    if (*batch && *bws != workspace) {
+        sv_batch_destroy(*batch);
+        *batch = nullptr;
+    }
+    const bool bat_a = L.na >= kBatchMinQubits, bat_b = L.nb >= kBatchMinQubits;
+    std::vector<void *> ptrs;
+    std::vector<const qsv_circuit *> circs;
+    std::vector<uint64_t> ids;
+    for (int side = 0; side < 2; ++side) {
+        const bool bat = side ? bat_b : bat_a;
+        const size_t nbr = side ? nbr_b : nbr_a;
+        const int nq = side ? L.nb : L.na;
+        float2 *w = side ? wb : wa;
+        for (size_t i = 0; i < nbr; ++i) {
+            if (bat) {
+                ptrs.push_back(w + (i << nq));
+                circs.push_back(partition_part(p, side));
+                ids.push_back(i);
+            } else if ((st = sv_simulate(w + (i << nq), partition_part(p, side), i, QSV_INIT_PLUS, 0, 1, -1,
+                                         nullptr, nullptr, nullptr, 0, nullptr, 0, stream)) != QSV_OK) {
+                return st;
+            }
+        }
+    }
+    if (!ptrs.empty()) {
+        if (!*batch) {
+            if ((st = sv_batch_create(circs.data(), ids.data(), circs.size(), nullptr, batch)) != QSV_OK)
+                return st;
+            *bws = workspace;
+        }
+        if ((st = sv_batch_run(*batch, ptrs.data(), 1, nullptr, 0, nullptr, stream)) != QSV_OK) return st;
+    }
+    // 2. psi_in, one GEMM per value (v_a, v_b) of the selector qubits
+    CombineArgs P;
+    std::memset(&P, 0, sizeof(P));
+    P.na = L.na;
+    P.nb = L.nb;
+    P.na_blk = rows_blk;
+    P.nb_blk = cols_blk;
+    P.a_stride = 1ull << L.na;
+    P.b_stride = 1ull << L.nb;
+    std::vector<int> loc(L.n, -1);
+    for (int i = 0; i < L.na; ++i) { P.pos_a[i] = uint8_t(L.qa[i]); loc[L.qa[i]] = i; }
+    for (int i = 0; i < L.nb; ++i) { P.pos_b[i] = uint8_t(L.qb[i]); loc[L.qb[i]] = i; }
+    for (size_t f = 0; f < L.fold_a.size(); ++f) {
+        P.fold_a[f] = uint8_t(loc[L.fold_a[f]]);
+        P.fold_b[f] = uint8_t(loc[L.fold_b[f]]);
+    }
+    P.n_fold = int32_t(L.fold_a.size());
+    const uint64_t ne = 1ull << L.eb;
+    for (uint64_t va = 0; va < (1ull << L.ka); ++va)
+        for (uint64_t vb = 0; vb < (1ull << L.kb); ++vb) {
+            P.row_base = va << rows_blk;
+            P.col_base = vb << cols_blk;
+            // A's branch (e, u = vb), B's branch (e, w = va)
+            P.a_off = ((vb << L.eb) << L.na) + P.row_base;
+            P.b_off = ((va << L.eb) << L.nb) + P.col_base;
+            hipError_t e = launch_combine_gemm(wa, wb, ne, P, static_cast<float2 *>(out_state), s);
+            if (e != hipSuccess) return hip_fail(e, "sv_partition_simulate: combine");
+        }
+    // 3. part C on the complete state
+    if (L.c_gates == 0) return QSV_OK;
+    return sv_apply_fused(out_state, partition_part(p, 2), 0, 0, -1, nullptr, stream);
 }
 
 qsv_status sv_branch_combine(const void *a_tab, const void *b_tab, size_t n_branches, size_t m,

@@ -14,7 +14,9 @@
 // MFMA blocks for each of Mr, Mi).  Branch chunks of 16 are staged in LDS as
 // k-major planes; the next chunk's global loads are issued before the current
 // chunk's MFMA work so that they overlap it.  The epilogue applies s(x) and
-// scatters the tile to the state's natural index order.
+// scatters the tile to the state's natural index order.  A launch covers one
+// block of rows and columns (CombineArgs): the whole matrix for a two-part
+// split, one value of the selector qubits for a three-part partition.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -35,7 +37,6 @@ k_combine_gemm(const float2 *__restrict__ A, const float2 *__restrict__ B, uint6
                const CombineArgs P, float2 *__restrict__ out) {
     __shared__ float a1[kK][kTile], a2[kK][kTile], b1[kK][kTile];
     const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
-    const uint64_t rowsA = 1ull << P.na, rowsB = 1ull << P.nb;
     const uint64_t i0 = uint64_t(blockIdx.x) * kTile, j0 = uint64_t(blockIdx.y) * kTile;
     const uint32_t wr = w & 1u, wc = w >> 1;  // quadrant of this wave
     const uint32_t lr = lane & 15u, lk = lane >> 4;
@@ -56,8 +57,8 @@ k_combine_gemm(const float2 *__restrict__ A, const float2 *__restrict__ B, uint6
             na_[q] = make_float2(0.f, 0.f);
             nb_[q] = make_float2(0.f, 0.f);
             if (b0 + b < nbr) {
-                na_[q] = A[(b0 + b) * rowsA + i0 + r];
-                nb_[q] = B[(b0 + b) * rowsB + j0 + r];
+                na_[q] = A[P.a_off + (b0 + b) * P.a_stride + i0 + r];
+                nb_[q] = B[P.b_off + (b0 + b) * P.b_stride + j0 + r];
             }
         }
     };
@@ -99,7 +100,7 @@ k_combine_gemm(const float2 *__restrict__ A, const float2 *__restrict__ B, uint6
     for (int m = 0; m < 4; ++m) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const uint64_t i = i0 + wr * 64 + m * 16 + 4 * lk + r;
+            const uint64_t i = P.row_base + i0 + wr * 64 + m * 16 + 4 * lk + r;
             uint64_t xa = 0, fmask = 0;
             for (int q = 0; q < P.na; ++q)
                 if ((i >> q) & 1ull) xa |= 1ull << P.pos_a[q];
@@ -107,7 +108,7 @@ k_combine_gemm(const float2 *__restrict__ A, const float2 *__restrict__ B, uint6
                 if ((i >> P.fold_a[f]) & 1ull) fmask ^= 1ull << P.fold_b[f];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const uint64_t j = j0 + wc * 64 + c * 16 + lr;
+                const uint64_t j = P.col_base + j0 + wc * 64 + c * 16 + lr;
                 uint64_t x = xa;
                 for (int q = 0; q < P.nb; ++q)
                     if ((j >> q) & 1ull) x |= 1ull << P.pos_b[q];
@@ -116,14 +117,13 @@ k_combine_gemm(const float2 *__restrict__ A, const float2 *__restrict__ B, uint6
             }
         }
     }
-    (void)rowsB;
 }
 
 }  // namespace
 
 hipError_t launch_combine_gemm(const float2 *A, const float2 *B, uint64_t nbr, const CombineArgs &P,
                                float2 *out, hipStream_t s) {
-    const dim3 grid(unsigned(1ull << (P.na - 7)), unsigned(1ull << (P.nb - 7)));
+    const dim3 grid(unsigned(1ull << (P.na_blk - 7)), unsigned(1ull << (P.nb_blk - 7)));
     hipLaunchKernelGGL(k_combine_gemm, grid, dim3(256), 0, s, A, B, nbr, P, out);
     return hipGetLastError();
 }

@@ -33,8 +33,14 @@ hipError_t launch_dot(const float2 *a, const float2 *b, int n, double *out, doub
 // Full-state branch combine (combine.hip).  Local bit q of side A / B sits at
 // global bit pos_a[q] / pos_b[q]; folded pair f couples local A bit fold_a[f]
 // with local B bit fold_b[f].
+// One block of the full-state combine: rows row_base + [0, 2^na_blk) of side
+// A's local index and columns col_base + [0, 2^nb_blk) of side B's.  Branch
+// b's rows start at A + a_off + b * a_stride (likewise for B); pos_a / pos_b
+// map local bits (of the full local index) to output bits.
 struct CombineArgs {
     int32_t na, nb, n_fold, pad;
+    int32_t na_blk, nb_blk, pad2[2];
+    uint64_t a_off, a_stride, b_off, b_stride, row_base, col_base;
     uint8_t pos_a[64], pos_b[64];
     uint8_t fold_a[64], fold_b[64];
 };

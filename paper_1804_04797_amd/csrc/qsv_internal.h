@@ -16,6 +16,7 @@
 namespace qsv {
 
 constexpr int kMaxQubits = 34;   // 2^34 complex64 = 128 GiB per state
+constexpr int kBatchMinQubits = 11;  // smallest state of a batch (tile 2^(4+7))
 constexpr int kMaxSlots = 16;    // register + thread slots of one tile
 constexpr int kMaxOps = 192;     // op words per pass program (kernel argument)
 
@@ -150,6 +151,18 @@ struct TileShape { int R, T, c; bool oop = false; };
 qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Plan &out);
 TileShape default_shape(int n);
 void gates_in_range(const qsv_circuit &c, int lb, int le, std::vector<int> &idx);
+
+// partition.cpp: the parts of a three-part partition and the combine's
+// branch layout (for sv_partition_simulate)
+struct PartitionLayout {
+    int n = 0, na = 0, nb = 0, eb = 0, ka = 0, kb = 0;
+    std::vector<int> qa, qb;              // local -> global qubit (selectors on top)
+    std::vector<int32_t> fold_a, fold_b;  // folded pairs (global)
+    size_t c_gates = 0;
+};
+const qsv_circuit *partition_part(const qsv_partition *p, int which);  // 0 A, 1 B, 2 C
+void partition_layout(const qsv_partition *p, PartitionLayout &L);
+qsv_batch **partition_batch(qsv_partition *p, void ***ws);
 
 // tune.cpp: the shape sv_tune picked for this circuit and layer range, if any
 bool tuned_opts(const qsv_circuit *c, int lb, int le, qsv_fuse_opts *out);

@@ -31,6 +31,9 @@ EXPORTS = ["circuit_create", "circuit_destroy", "circuit_info", "circuit_gates",
            "sv_batch_destroy", "sv_plan_info", "sv_debug_emulate", "sv_debug_jit_compile",
            "sv_tune", "sv_apply_dense", "sv_debug_emulate_dense", "qsv_release_device_buffers",
            "circuit_inverse", "sv_inner_product", "sv_branch_combine_full",
+           "circuit_partition_plan", "circuit_partition_create", "circuit_partition_info",
+           "circuit_partition_offsets", "circuit_partition_parts", "circuit_partition_destroy",
+           "sv_partition_workspace_bytes", "sv_partition_simulate",
            "qsv_last_error", "qsv_version"]
 
 
@@ -44,6 +47,12 @@ class FuseOpts(ctypes.Structure):
     _fields_ = [("reg_qubits", ctypes.c_int), ("thread_qubits", ctypes.c_int),
                 ("low_qubits", ctypes.c_int), ("plain", ctypes.c_int), ("jit", ctypes.c_int),
                 ("out_of_place", ctypes.c_int), ("pass_forms", ctypes.c_uint32)]
+
+
+class PartitionInfo(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int) for k in ("r0", "t_s", "depth", "cols", "n_a", "n_b", "n_c", "cuts",
+                                            "explicit_bits", "sel_a", "sel_b", "folded", "f", "g")] + [
+        ("objective", ctypes.c_double), ("branches_a", ctypes.c_uint64), ("branches_b", ctypes.c_uint64)]
 
 
 _lib = None
@@ -86,6 +95,14 @@ def lib():
         "sv_tune": (st, [vp, vp, i32, i32, vp, P(ctypes.c_double), vp]),
         "sv_apply_dense": (st, [vp, vp, u64, i32, i32, i32, P(i32), vp]),
         "sv_debug_emulate_dense": (st, [vp, vp, u64, i32, i32, i32, P(i32)]),
+        "circuit_partition_plan": (st, [vp, i32, i32, vp, i32, i32, P(vp)]),
+        "circuit_partition_create": (st, [vp, i32, i32, vp, i32, i32, vp, vp, P(vp)]),
+        "circuit_partition_info": (st, [vp, vp]),
+        "circuit_partition_offsets": (st, [vp, vp, vp, sz]),
+        "circuit_partition_parts": (st, [vp, P(vp), P(vp), P(vp), vp, vp]),
+        "circuit_partition_destroy": (None, [vp]),
+        "sv_partition_workspace_bytes": (st, [vp, P(sz)]),
+        "sv_partition_simulate": (st, [vp, vp, sz, vp, vp]),
         "qsv_last_error": (ctypes.c_char_p, []),
         "qsv_version": (ctypes.c_char_p, []),
     }
@@ -380,3 +397,82 @@ def sv_debug_emulate_dense(amps_host, c, k, branch=0, layer_begin=0, layer_end=-
 
 def version() -> str:
     return lib().qsv_version().decode()
+
+
+class Partition:
+    """Owning handle of a qsv_partition (keeps its circuit alive)."""
+
+    def __init__(self, handle, circuit):
+        self.handle = handle
+        self.circuit = circuit
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.circuit_partition_destroy(self.handle)
+            self.handle = None
+
+    @property
+    def _as_parameter_(self):
+        return ctypes.c_void_p(self.handle)
+
+
+def _present(present):
+    if present is None:
+        return None
+    return np.ascontiguousarray(np.asarray(present, dtype=np.uint8).reshape(-1))
+
+
+def circuit_partition_plan(c, rows, cols, present, r0, max_move=3) -> Partition:
+    pres = _present(present)
+    out = ctypes.c_void_p()
+    _check(lib().circuit_partition_plan(c, rows, cols, _ptr(pres) if pres is not None else None, r0,
+                                        max_move, ctypes.byref(out)))
+    return Partition(out.value, c)
+
+
+def circuit_partition_create(c, rows, cols, present, r0, t_s, ups, dns) -> Partition:
+    pres = _present(present)
+    u = np.ascontiguousarray(np.asarray(ups, dtype=np.uint8).reshape(-1))
+    d = np.ascontiguousarray(np.asarray(dns, dtype=np.uint8).reshape(-1))
+    out = ctypes.c_void_p()
+    _check(lib().circuit_partition_create(c, rows, cols, _ptr(pres) if pres is not None else None, r0,
+                                          t_s, _ptr(u) if u.size else None, _ptr(d) if d.size else None,
+                                          ctypes.byref(out)))
+    return Partition(out.value, c)
+
+
+def circuit_partition_info(p) -> dict:
+    info = PartitionInfo()
+    _check(lib().circuit_partition_info(p, ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in PartitionInfo._fields_}
+
+
+def circuit_partition_offsets(p):
+    """(ups, dns): uint8 arrays of shape (depth + 1 - t_s, cols)."""
+    info = circuit_partition_info(p)
+    nl = info["depth"] + 1 - info["t_s"]
+    ups = np.zeros((nl, info["cols"]), np.uint8)
+    dns = np.zeros((nl, info["cols"]), np.uint8)
+    _check(lib().circuit_partition_offsets(p, _ptr(ups), _ptr(dns), ups.size))
+    return ups, dns
+
+
+def circuit_partition_parts(p):
+    """(A, B, C, qubits_a, qubits_b): the part circuits and the local-to-global maps."""
+    info = circuit_partition_info(p)
+    a, b, c = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+    qa = np.zeros(info["n_a"], np.int32)
+    qb = np.zeros(info["n_b"], np.int32)
+    _check(lib().circuit_partition_parts(p, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                         _ptr(qa), _ptr(qb)))
+    return Circuit(a.value), Circuit(b.value), Circuit(c.value), qa, qb
+
+
+def sv_partition_workspace_bytes(p) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().sv_partition_workspace_bytes(p, ctypes.byref(n)))
+    return n.value
+
+
+def sv_partition_simulate(p, workspace, ws_bytes, out_state, stream=None):
+    _check(lib().sv_partition_simulate(p, _ptr(workspace), ws_bytes, _ptr(out_state), _stream(stream)))

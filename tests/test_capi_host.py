@@ -333,3 +333,129 @@ def test_circuit_inverse_matches_oracle():
     assert [g[:3] for g in got] == [g[:3] for g in want]
     assert [g[3] for g in got] == [top - g[3] for g in want]
     assert inv.info()[0] == c.info()[0]
+
+
+# --- three-part partition (host side) ----------------------------------------
+
+from oracle import partition as OPT  # noqa: E402
+
+
+def _branch_gates(gates, branch):
+    """Library branch gates (PB / ZB with bit `arg`) as plain oracle gates for one branch."""
+    out = []
+    for g in gates:
+        name = qsv.KIND_NAME[int(g["kind"])]
+        q0, t = int(g["q0"]), int(g["layer"])
+        if name in ("PB", "ZB"):
+            bit = (branch >> int(g["arg"])) & 1
+            if name == "PB":
+                out.append(("P1" if bit else "P0", q0, -1, t))
+            elif bit:
+                out.append(("Z", q0, -1, t))
+            continue
+        out.append((name, q0, int(g["q1"]) if name == "CZ" else -1, t))
+    return out
+
+
+PART_CASES = [(3, 4, 8, 77, 1), (3, 4, 8, 77, 2), (4, 5, 10, 5, 2), (4, 5, 10, 5, 3), (3, 5, 12, 9, 1),
+              (4, 4, 12, 21, 2)]
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed,r0", PART_CASES)
+def test_partition_plan_matches_oracle(rows, cols, depth, seed, r0):
+    lat = OC.Lattice(rows, cols)
+    gates = OC.random_circuit(lat, depth, seed)
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    want = OPT.plan(lat, gates, r0, 2)
+    p = qsv.circuit_partition_plan(c, rows, cols, None, r0, 2)
+    info = qsv.circuit_partition_info(p)
+    # the optimum is unique, the scheme reaching it need not be
+    assert info["objective"] == want["objective"]
+    ups, dns = qsv.circuit_partition_offsets(p)
+    ev = OPT.evaluate(lat, gates, {"r0": r0, "t_s": info["t_s"], "ups": ups.tolist(), "dns": dns.tolist()})
+    assert (ev["f"], ev["g"], ev["c"]) == (info["f"], info["g"], info["n_c"])
+    assert info["cuts"] == len(ev["cuts"])
+    fa = sum(1 for x in ev["cuts"] if x["free_a"] and not x["free_b"])
+    fb = sum(1 for x in ev["cuts"] if x["free_b"] and not x["free_a"])
+    both = sum(1 for x in ev["cuts"] if x["free_a"] and x["free_b"])
+    assert info["folded"] == both
+    assert info["explicit_bits"] == info["cuts"] - fa - fb - both
+    assert info["sel_a"] <= fa and info["sel_b"] <= fb
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed,r0", PART_CASES[:4])
+def test_partition_parts_reproduce_state(rows, cols, depth, seed, r0):
+    """The library's part circuits, run per branch with the oracle simulator and
+    combined with the documented branch layout, give the circuit's state."""
+    lat = OC.Lattice(rows, cols)
+    gates = OC.random_circuit(lat, depth, seed)
+    n = lat.n
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    p = qsv.circuit_partition_plan(c, rows, cols, None, r0, 2)
+    info = qsv.circuit_partition_info(p)
+    A, B, Cc, qa, qb = qsv.circuit_partition_parts(p)
+    na, nb, eb = info["n_a"], info["n_b"], info["explicit_bits"]
+    ka, kb = info["sel_a"], info["sel_b"]
+    phi = [sim.simulate(_branch_gates(A.gates(), i), na) for i in range(info["branches_a"])]
+    xi = [sim.simulate(_branch_gates(B.gates(), i), nb) for i in range(info["branches_b"])]
+    xs = np.arange(1 << n)
+    xa = np.zeros_like(xs)
+    xb = np.zeros_like(xs)
+    for i, q in enumerate(qa):
+        xa |= ((xs >> int(q)) & 1) << i
+    for i, q in enumerate(qb):
+        xb |= ((xs >> int(q)) & 1) << i
+    u = xb >> (nb - kb)   # B selector qubits pick A's extra branch bits
+    w = xa >> (na - ka)   # A selector qubits pick B's extra branch bits
+    ev = OPT.evaluate(lat, gates, {"r0": r0, "t_s": info["t_s"],
+                                   "ups": qsv.circuit_partition_offsets(p)[0].tolist(),
+                                   "dns": qsv.circuit_partition_offsets(p)[1].tolist()})
+    sign = np.ones(1 << n)
+    for x in ev["cuts"]:
+        if x["free_a"] and x["free_b"]:
+            sign *= np.where(((xs >> x["a"]) & 1) & ((xs >> x["b"]) & 1), -1.0, 1.0)
+    PA = np.array(phi)
+    PB = np.array(xi)
+    psi = np.zeros(1 << n, np.complex128)
+    for e in range(1 << eb):
+        psi += PA[e | (u << eb), xa] * PB[e | (w << eb), xb]
+    psi *= sign
+    cg = _to_oracle(Cc.gates())
+    sim.run(psi, n, cg)
+    direct = sim.simulate(gates, n)
+    assert np.max(np.abs(psi - direct)) < 1e-13
+
+
+def test_partition_create_checks_the_scheme():
+    rows, cols, depth, seed = 3, 4, 8, 77
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    p = qsv.circuit_partition_plan(c, rows, cols, None, 1, 2)
+    info = qsv.circuit_partition_info(p)
+    ups, dns = qsv.circuit_partition_offsets(p)
+    q = qsv.circuit_partition_create(c, rows, cols, None, 1, info["t_s"], ups, dns)
+    assert qsv.circuit_partition_info(q) == info
+    # no part C at all: every crossing CZ is cut
+    q2 = qsv.circuit_partition_create(c, rows, cols, None, 1, depth + 1, [], [])
+    assert qsv.circuit_partition_info(q2)["n_c"] == 0
+    with pytest.raises(qsv.QsvError):   # lines at rest cut later CZs
+        qsv.circuit_partition_create(c, rows, cols, None, 1, 1, np.zeros((depth, cols)), np.zeros((depth, cols)))
+    if len(ups) > 1 and ups[-1].any():
+        bad = ups.copy()
+        bad[-1] = 0                      # offsets that shrink
+        with pytest.raises(qsv.QsvError):
+            qsv.circuit_partition_create(c, rows, cols, None, 1, info["t_s"], bad, dns)
+    with pytest.raises(qsv.QsvError):   # lattice does not match the circuit
+        qsv.circuit_partition_plan(c, rows, cols + 1, None, 1, 2)
+    with pytest.raises(qsv.QsvError):   # r0 outside 1..rows-1
+        qsv.circuit_partition_plan(c, rows, cols, None, rows, 2)
+
+
+def test_partition_simulate_rejects_small_blocks():
+    """Blocks of fewer than 2^7 rows are refused before any device work."""
+    c = qsv.circuit_create(4, 5, None, 10, 5)
+    p = qsv.circuit_partition_plan(c, 4, 5, None, 1, 2)  # part A: 5 qubits
+    assert qsv.circuit_partition_info(p)["n_a"] < 7
+    ws = qsv.sv_partition_workspace_bytes(p)
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.sv_partition_simulate(p, 1 << 20, ws, 1 << 30, stream=0)
+    assert e.value.status == 5  # QSV_EUNSUPPORTED

@@ -955,3 +955,56 @@ def test_split_7x7_branches_full_size():
         ref = sim.simulate(gb, 21)
         qsv.sv_simulate(bst, hb, branch=br, init_kind=qsv.INIT_ZERO)
         _check_full(bst, ref, 21)
+
+
+# --- three-part partition: branch sweeps, block combines, part C -------------
+
+def _partition_run(c, rows, cols, present, r0, max_move=2):
+    p = qsv.circuit_partition_plan(c, rows, cols, present, r0, max_move)
+    info = qsv.circuit_partition_info(p)
+    n = info["n_a"] + info["n_b"]
+    ws_bytes = qsv.sv_partition_workspace_bytes(p)
+    ws = torch.empty(ws_bytes // 8, dtype=torch.complex64, device=DEV)
+    out = torch.empty(1 << n, dtype=torch.complex64, device=DEV)
+    qsv.sv_partition_simulate(p, ws, ws_bytes, out)
+    return p, info, ws, out
+
+
+@pytest.mark.parametrize("depth,seed", [(10, 3), (16, 2), (12, 2)])
+def test_partition_simulate_4x5(depth, seed):
+    """Complete 20-qubit state through the three-part partition (lines after
+    row 1): all branch states of parts A and B in one batch, one combine GEMM
+    per value of the selector qubits, part C swept on the result; every
+    amplitude against the oracle's direct simulation.  The cases hold shared
+    branch bits, selector qubits on both sides and folded signs."""
+    _gpu()
+    rows, cols = 4, 5
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    p, info, ws, out = _partition_run(c, rows, cols, None, 2)
+    assert info["explicit_bits"] and info["sel_a"] and info["sel_b"] and info["folded"] and info["n_c"]
+    ref = sim.simulate(OC.random_circuit(OC.Lattice(rows, cols), depth, seed), rows * cols)
+    _check_full(out, ref, rows * cols)
+    # a second call reuses the batch captured for this workspace
+    out.zero_()
+    qsv.sv_partition_simulate(p, ws, ws.numel() * 8, out)
+    _check_full(out, ref, rows * cols)
+
+
+def test_partition_simulate_5x6_d20():
+    """The 30-qubit workload through the partition planned by Algorithm 1
+    (lines after row 1: 12 | 18 qubits, 64 shared branches, 18 qubits in part
+    C), against the stored oracle amplitudes; FP64 norm of the result."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("5x6-d20")
+    xs, ref = _golden("5x6-d20")
+    n = lat.n
+    p, info, ws, out = _partition_run(c, spec["rows"], spec["cols"], workloads.present_mask(spec), 2, 3)
+    assert info["explicit_bits"] == 6 and info["n_c"] == 18
+    got = out[torch.from_numpy(xs.view(np.int64)).to(DEV)].cpu().numpy()
+    d = np.max(np.abs(got - ref))
+    assert d <= TOL and d * 2 ** (n / 2) <= TOL_SCALED, d
+    nrm = torch.zeros(1, dtype=torch.float64, device=DEV)
+    qsv.sv_norm_fp64(out, n, nrm)
+    assert abs(nrm.item() - 1) <= 1e-5
+    del ws, out
+    torch.cuda.empty_cache()
