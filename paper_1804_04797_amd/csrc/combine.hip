@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 
 #include "kernels.h"
 
@@ -48,32 +49,40 @@ k_combine_gemm(const float2 *__restrict__ A, const float2 *__restrict__ B, uint6
             accr[m][c] = v4f{0, 0, 0, 0};
             acci[m][c] = v4f{0, 0, 0, 0};
         }
+    // staging: thread t always loads in-tile row tr of branches tb, tb + 2, ...
+    // of a chunk, so one pointer per side and a uniform stride address them
     constexpr int kPer = kBr * kTile / 256;  // staged elements per thread and side
+    static_assert(kTile == 128 && kPer * 2 == kBr, "staging assumes 256 threads over 128-row tiles");
+    const uint32_t tb = t >> 7, tr = t & 127u;
+    const float2 *pa = A + P.a_off + tb * P.a_stride + i0 + tr;
+    const float2 *pb = B + P.b_off + tb * P.b_stride + j0 + tr;
+    const uint64_t sa = 2 * P.a_stride, sb = 2 * P.b_stride;
     float2 na_[kPer], nb_[kPer];
     auto fetch = [&](uint64_t b0) {
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
-            const uint32_t e = t + uint32_t(q) * 256u, b = e / kTile, r = e % kTile;
             na_[q] = make_float2(0.f, 0.f);
             nb_[q] = make_float2(0.f, 0.f);
-            if (b0 + b < nbr) {
-                na_[q] = A[P.a_off + (b0 + b) * P.a_stride + i0 + r];
-                nb_[q] = B[P.b_off + (b0 + b) * P.b_stride + j0 + r];
+            if (b0 + tb + 2 * q < nbr) {
+                na_[q] = pa[q * sa];
+                nb_[q] = pb[q * sb];
             }
         }
+        pa += kBr * P.a_stride;
+        pb += kBr * P.b_stride;
     };
     fetch(0);
     for (uint64_t b0 = 0; b0 < nbr; b0 += kBr) {
         __syncthreads();  // previous chunk's fragments are read
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
-            const uint32_t e = t + uint32_t(q) * 256u, b = e / kTile, r = e % kTile;
-            a1[2 * b][r] = na_[q].x;
-            a1[2 * b + 1][r] = -na_[q].y;
-            a2[2 * b][r] = na_[q].y;
-            a2[2 * b + 1][r] = na_[q].x;
-            b1[2 * b][r] = nb_[q].x;
-            b1[2 * b + 1][r] = nb_[q].y;
+            const uint32_t b = tb + 2 * q;
+            a1[2 * b][tr] = na_[q].x;
+            a1[2 * b + 1][tr] = -na_[q].y;
+            a2[2 * b][tr] = na_[q].y;
+            a2[2 * b + 1][tr] = na_[q].x;
+            b1[2 * b][tr] = nb_[q].x;
+            b1[2 * b + 1][tr] = nb_[q].y;
         }
         __syncthreads();
         if (b0 + kBr < nbr) fetch(b0 + kBr);  // in flight during the MFMA work
@@ -95,36 +104,74 @@ k_combine_gemm(const float2 *__restrict__ A, const float2 *__restrict__ B, uint6
                 }
         }
     }
-    // epilogue: block (m, c) element r of this lane is row 4*lk + r, column lr
+    // epilogue: block (m, c) element r of this lane is row 4*lk + r, column lr.
+    // An index is the tile's base row / column (a multiple of 128, the same
+    // for the whole workgroup) plus 7 in-tile bits; their output bits and the
+    // sign mask of the base row are formed once.
+    const uint64_t i0b = P.row_base + i0, j0b = P.col_base + j0;
+    uint64_t xa0 = 0, xb0 = 0, f0 = 0;
+    for (int q = 7; q < P.na; ++q)
+        if ((i0b >> q) & 1ull) xa0 |= 1ull << P.pos_a[q];
+    for (int q = 7; q < P.nb; ++q)
+        if ((j0b >> q) & 1ull) xb0 |= 1ull << P.pos_b[q];
+    for (int f = 0; f < P.n_fold; ++f)
+        if ((i0b >> P.fold_a[f]) & 1ull) f0 ^= 1ull << P.fold_b[f];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int c = 0; c < 4; ++c) {
+        const uint32_t jl = wc * 64 + c * 16 + lr;
+        uint64_t xb = xb0;
+        for (int q = 0; q < 7; ++q)
+            if ((jl >> q) & 1u) xb |= 1ull << P.pos_b[q];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const uint64_t i = P.row_base + i0 + wr * 64 + m * 16 + 4 * lk + r;
-            uint64_t xa = 0, fmask = 0;
-            for (int q = 0; q < P.na; ++q)
-                if ((i >> q) & 1ull) xa |= 1ull << P.pos_a[q];
-            for (int f = 0; f < P.n_fold; ++f)
-                if ((i >> P.fold_a[f]) & 1ull) fmask ^= 1ull << P.fold_b[f];
+        for (int m = 0; m < 4; ++m) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const uint64_t j = P.col_base + j0 + wc * 64 + c * 16 + lr;
-                uint64_t x = xa;
-                for (int q = 0; q < P.nb; ++q)
-                    if ((j >> q) & 1ull) x |= 1ull << P.pos_b[q];
-                const float sgn = (__popcll(fmask & j) & 1) ? -1.f : 1.f;
-                out[x] = make_float2(sgn * accr[m][c][r], sgn * acci[m][c][r]);
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t il = wr * 64 + m * 16 + 4 * lk + r;
+                uint64_t xa = xa0, fm = f0;
+                for (int q = 0; q < 7; ++q)
+                    if ((il >> q) & 1u) xa |= 1ull << P.pos_a[q];
+                for (int f = 0; f < P.n_fold; ++f)
+                    if (P.fold_a[f] < 7 && ((il >> P.fold_a[f]) & 1u)) fm ^= 1ull << P.fold_b[f];
+                const float sgn = (__popcll(fm & (j0b | jl)) & 1) ? -1.f : 1.f;
+                out[xa | xb] = make_float2(sgn * accr[m][c][r], sgn * acci[m][c][r]);
             }
         }
     }
 }
 
+// Leading local bits of a side that land on output bits 0, 1, 2, ... in order.
+static int low_run(const uint8_t *pos, int n) {
+    int k = 0;
+    while (k < n && pos[k] == k) ++k;
+    return k;
+}
+
 }  // namespace
 
+// The 16 lanes of an accumulator row hold 16 consecutive columns, so the
+// epilogue's stores are contiguous when the column side carries the lowest
+// output bits: the product is symmetric in the two sides (A_b B_b = B_b A_b,
+// the sign is symmetric), so the sides are exchanged when side A holds the
+// longer run of low output bits.
 hipError_t launch_combine_gemm(const float2 *A, const float2 *B, uint64_t nbr, const CombineArgs &P,
                                float2 *out, hipStream_t s) {
-    const dim3 grid(unsigned(1ull << (P.na_blk - 7)), unsigned(1ull << (P.nb_blk - 7)));
-    hipLaunchKernelGGL(k_combine_gemm, grid, dim3(256), 0, s, A, B, nbr, P, out);
+    CombineArgs Q = P;
+    const float2 *X = A, *Y = B;
+    if (low_run(P.pos_a, P.na) > low_run(P.pos_b, P.nb) && P.na_blk <= 22) {
+        X = B;
+        Y = A;
+        Q.na = P.nb; Q.nb = P.na;
+        Q.na_blk = P.nb_blk; Q.nb_blk = P.na_blk;
+        Q.a_off = P.b_off; Q.b_off = P.a_off;
+        Q.a_stride = P.b_stride; Q.b_stride = P.a_stride;
+        Q.row_base = P.col_base; Q.col_base = P.row_base;
+        std::memcpy(Q.pos_a, P.pos_b, sizeof(Q.pos_a));
+        std::memcpy(Q.pos_b, P.pos_a, sizeof(Q.pos_b));
+        std::memcpy(Q.fold_a, P.fold_b, sizeof(Q.fold_a));
+        std::memcpy(Q.fold_b, P.fold_a, sizeof(Q.fold_b));
+    }
+    const dim3 grid(unsigned(1ull << (Q.na_blk - 7)), unsigned(1ull << (Q.nb_blk - 7)));
+    hipLaunchKernelGGL(k_combine_gemm, grid, dim3(256), 0, s, X, Y, nbr, Q, out);
     return hipGetLastError();
 }
 
