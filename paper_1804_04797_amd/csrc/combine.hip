@@ -14,7 +14,8 @@
 // MFMA blocks for each of Mr, Mi).  Branch chunks of 16 are staged in LDS as
 // k-major planes; the next chunk's global loads are issued before the current
 // chunk's MFMA work so that they overlap it.  The epilogue applies s(x) and
-// scatters the tile to the state's natural index order.  A launch covers one
+// scatters the tile to the state's natural index order through per-tile
+// tables of the rows' and columns' output bits.  A launch covers one
 // block of rows and columns (CombineArgs): the whole matrix for a two-part
 // split, one value of the selector qubits for a three-part partition.
 #include <hip/hip_runtime.h>
@@ -105,35 +106,48 @@ k_combine_gemm(const float2 *__restrict__ A, const float2 *__restrict__ B, uint6
         }
     }
     // epilogue: block (m, c) element r of this lane is row 4*lk + r, column lr.
-    // An index is the tile's base row / column (a multiple of 128, the same
-    // for the whole workgroup) plus 7 in-tile bits; their output bits and the
-    // sign mask of the base row are formed once.
-    const uint64_t i0b = P.row_base + i0, j0b = P.col_base + j0;
-    uint64_t xa0 = 0, xb0 = 0, f0 = 0;
-    for (int q = 7; q < P.na; ++q)
-        if ((i0b >> q) & 1ull) xa0 |= 1ull << P.pos_a[q];
-    for (int q = 7; q < P.nb; ++q)
-        if ((j0b >> q) & 1ull) xb0 |= 1ull << P.pos_b[q];
-    for (int f = 0; f < P.n_fold; ++f)
-        if ((i0b >> P.fold_a[f]) & 1ull) f0 ^= 1ull << P.fold_b[f];
+    // The output bits of the tile's 128 rows and 128 columns and the sign mask
+    // of each row are tabulated once in the (now free) LDS staging area.
+    __syncthreads();  // last chunk's fragments are read
+    uint64_t *rowx = reinterpret_cast<uint64_t *>(&a1[0][0]);
+    uint64_t *rowf = rowx + kTile;
+    uint64_t *colx = rowf + kTile;
+    {
+        const uint32_t k = t & 127u;
+        if (t < 128) {
+            const uint64_t i = P.row_base + i0 + k;
+            uint64_t x = 0, f = 0;
+            for (int q = 0; q < P.na; ++q)
+                if ((i >> q) & 1ull) x |= 1ull << P.pos_a[q];
+            for (int g = 0; g < P.n_fold; ++g)
+                if ((i >> P.fold_a[g]) & 1ull) f ^= 1ull << P.fold_b[g];
+            rowx[k] = x;
+            rowf[k] = f;
+        } else {
+            const uint64_t j = P.col_base + j0 + k;
+            uint64_t x = 0;
+            for (int q = 0; q < P.nb; ++q)
+                if ((j >> q) & 1ull) x |= 1ull << P.pos_b[q];
+            colx[k] = x;
+        }
+    }
+    __syncthreads();
+    const uint64_t j0b = P.col_base + j0;
+    uint64_t xb[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const uint32_t jl = wc * 64 + c * 16 + lr;
-        uint64_t xb = xb0;
-        for (int q = 0; q < 7; ++q)
-            if ((jl >> q) & 1u) xb |= 1ull << P.pos_b[q];
+    for (int c = 0; c < 4; ++c) xb[c] = colx[wc * 64 + c * 16 + lr];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < 4; ++m) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const uint32_t il = wr * 64 + m * 16 + 4 * lk + r;
-                uint64_t xa = xa0, fm = f0;
-                for (int q = 0; q < 7; ++q)
-                    if ((il >> q) & 1u) xa |= 1ull << P.pos_a[q];
-                for (int f = 0; f < P.n_fold; ++f)
-                    if (P.fold_a[f] < 7 && ((il >> P.fold_a[f]) & 1u)) fm ^= 1ull << P.fold_b[f];
-                const float sgn = (__popcll(fm & (j0b | jl)) & 1) ? -1.f : 1.f;
-                out[xa | xb] = make_float2(sgn * accr[m][c][r], sgn * acci[m][c][r]);
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t il = wr * 64 + m * 16 + 4 * lk + r;
+            const uint64_t xa = rowx[il], fm = rowf[il] & j0b;
+            const uint32_t fl = uint32_t(rowf[il]) & 127u;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const uint32_t jl = wc * 64 + c * 16 + lr;
+                const float sgn = ((__popcll(fm) + __popc(fl & jl)) & 1) ? -1.f : 1.f;
+                out[xa | xb[c]] = make_float2(sgn * accr[m][c][r], sgn * acci[m][c][r]);
             }
         }
     }
