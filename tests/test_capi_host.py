@@ -459,3 +459,27 @@ def test_partition_simulate_rejects_small_blocks():
     with pytest.raises(qsv.QsvError) as e:
         qsv.sv_partition_simulate(p, 1 << 20, ws, 1 << 30, stream=0)
     assert e.value.status == 5  # QSV_EUNSUPPORTED
+
+
+def test_partition_with_absent_sites():
+    """Lattice with two absent sites (qubits renumbered over the present ones):
+    the planner matches the oracle's optimum and its parts reproduce the state."""
+    rows, cols, depth, seed, r0 = 4, 4, 10, 31, 2
+    grid = [[True] * cols for _ in range(rows)]
+    grid[0][0] = False
+    grid[3][2] = False
+    pres = np.array(grid, np.uint8)
+    lat = OC.Lattice(rows, cols, grid)
+    gates = OC.random_circuit(lat, depth, seed)
+    c = qsv.circuit_create(rows, cols, pres, depth, seed)
+    assert _to_oracle(c.gates()) == gates
+    want = OPT.plan(lat, gates, r0, 2)
+    p = qsv.circuit_partition_plan(c, rows, cols, pres, r0, 2)
+    info = qsv.circuit_partition_info(p)
+    assert info["objective"] == want["objective"]
+    ups, dns = qsv.circuit_partition_offsets(p)
+    ev = OPT.evaluate(lat, gates, {"r0": r0, "t_s": info["t_s"], "ups": ups.tolist(), "dns": dns.tolist()})
+    assert (ev["f"], ev["g"], ev["c"]) == (info["f"], info["g"], info["n_c"])
+    A, B, Cc, qa, qb = qsv.circuit_partition_parts(p)
+    assert sorted(list(qa) + list(qb)) == list(range(lat.n))
+    assert all(lat.qubit[(r, k)] in qa for (r, k) in lat.qubit if r < r0)
