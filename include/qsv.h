@@ -226,6 +226,20 @@ qsv_status sv_simulate_c128(void *amps, const qsv_circuit *c, uint64_t branch, i
                             void *stream);
 
 /*
+ * sv_apply_fused_from - dst = U(layers [layer_begin, layer_end), branch) src
+ * out of place: the same sweep as sv_apply_fused, with the first pass reading
+ * src, which is never written (any pass count ends in dst).  For branch
+ * trees of a cut circuit (Section 2, CU = P0 (x) I + P1 (x) U): branches
+ * share every gate before their first differing cut, so the state at a cut
+ * layer is computed once and each child continues from it.  src, dst:
+ * device complex64[2^n], 16-byte aligned, must not overlap (src == dst runs
+ * in place).  With the generic kernel (jit = -1) or the per-gate path, src
+ * is copied to dst first.  Asynchronous on stream.
+ */
+qsv_status sv_apply_fused_from(const void *src, void *dst, const qsv_circuit *c, uint64_t branch,
+                               int layer_begin, int layer_end, const qsv_fuse_opts *opts, void *stream);
+
+/*
  * sv_apply_plain - the unfused comparator: one full-state (or, for diagonal
  * gates, partial) kernel per gate, the gate-by-gate method that Section 2.4
  * and Table "28qubit" measure their speedup against.  Same arguments and

@@ -431,6 +431,49 @@ qsv_status sv_apply_fused(void *amps, const qsv_circuit *c, uint64_t branch, int
     return QSV_OK;
 }
 
+qsv_status sv_apply_fused_from(const void *src, void *dst, const qsv_circuit *c, uint64_t branch,
+                               int layer_begin, int layer_end, const qsv_fuse_opts *opts, void *stream) {
+    if (!c) return fail(QSV_EINVAL, "sv_apply_fused_from: null circuit");
+    qsv_status st = check_state(src, c->n);
+    if (st != QSV_OK) return st;
+    if ((st = check_state(dst, c->n)) != QSV_OK) return st;
+    if (src == dst) return sv_apply_fused(dst, c, branch, layer_begin, layer_end, opts, stream);
+    const size_t bytes = sizeof(float) * 2 * (size_t(1) << c->n);
+    const char *a = static_cast<const char *>(src), *b = static_cast<const char *>(dst);
+    if (a < b + bytes && b < a + bytes) return fail(QSV_EINVAL, "sv_apply_fused_from: src and dst overlap");
+    if (layer_begin < 0) return fail(QSV_EINVAL, "sv_apply_fused_from: layer_begin < 0");
+    qsv_fuse_opts tuned;
+    opts = effective_opts(c, opts, layer_begin, layer_end, &tuned);
+    if ((st = check_device()) != QSV_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TileShape sh;
+    bool fused = !(opts && opts->plain);
+    if (fused) {
+        if ((st = resolve_shape(c, opts, sh, layer_begin, layer_end)) != QSV_OK) return st;
+        fused = sh.R != 0;
+    }
+    const int jm = fused ? jit_mode(c, opts) : 0;
+    if (jm) {
+        // the first pass reads src and writes dst or the second buffer, so
+        // any pass count ends in dst and src is never written
+        std::shared_ptr<Plan> plan;
+        void *scratch = nullptr;
+        if ((st = get_fused_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jm), false, plan,
+                                 &scratch)) != QSV_OK)
+            return st;
+        const int variant = kJitPlain | (jm & ~3);
+        {
+            std::lock_guard<std::mutex> g(plan->jit_mu);
+            if ((st = jit_prepare(*plan, variant)) != QSV_OK) return st;
+        }
+        return jit_launch(*plan, variant, dst, scratch, branch, 0, nullptr, s, nullptr, src);
+    }
+    // generic kernel or per-gate path: copy, then sweep dst in place
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "sv_apply_fused_from: copy");
+    return sv_apply_fused(dst, c, branch, layer_begin, layer_end, opts, stream);
+}
+
 qsv_status sv_amplitudes(const void *amps, int n_qubits, const uint64_t *bitstrings_dev, size_t m,
                          void *out_dev, int out_c128, void *stream) {
     qsv_status st = check_state(amps, n_qubits);

@@ -935,7 +935,8 @@ qsv_status jit_prepare(Plan &plan, int variant) {
 }
 
 qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, uint64_t branch,
-                      uint64_t basis, double *part, hipStream_t s, std::vector<float> *pass_ms) {
+                      uint64_t basis, double *part, hipStream_t s, std::vector<float> *pass_ms,
+                      const void *src0) {
     auto vit = plan.jit_variants.find(variant);
     if (vit == plan.jit_variants.end()) return fail(QSV_EINTERNAL, "jit variant not prepared");
     const CacheEntry &e = *static_cast<const CacheEntry *>(vit->second.get());
@@ -943,7 +944,7 @@ qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, 
     const uint64_t tiles = 1ull << (plan.n - L);
     const uint64_t chunk = 1ull << 30;
     const size_t np = plan.passes.size();
-    if (plan.oop && (!scratch || (!(variant & kJitInit) && np % 2)))
+    if (plan.oop && (!scratch || (!(variant & kJitInit) && !src0 && np % 2)))
         return fail(QSV_EINTERNAL, "out-of-place plan without a usable buffer schedule");
     // Out-of-place plans alternate between the two buffers so that the last
     // pass writes the caller's: pass p writes amps when np - p is odd.
@@ -953,7 +954,7 @@ qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, 
         for (auto &x : ev)
             if (hipEventCreate(&x) != hipSuccess) return fail(QSV_EHIP, "jit_launch: event create");
     }
-    void *in = amps;
+    void *in = src0 ? const_cast<void *>(src0) : amps;  // never written: pass 0 writes amps or scratch
     for (size_t p = 0; p < np; ++p) {
         if (pass_ms && hipEventRecord(ev[p], s) != hipSuccess) return fail(QSV_EHIP, "jit_launch: event");
         void *outb = (!plan.oop || (np - p) % 2 == 1) ? amps : scratch;

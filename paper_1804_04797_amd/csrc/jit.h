@@ -29,10 +29,11 @@ inline bool jit_pass_loop(int variant, size_t p) {
 std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int variant);
 // Compile (cached by source text and device) and attach the kernels to plan.
 qsv_status jit_prepare(Plan &plan, int variant);
-// Launch all passes of a prepared plan on stream s.
+// Launch all passes of a prepared plan on stream s.  src0 (optional): the
+// first pass reads this state instead of amps, which it leaves unchanged.
 qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, uint64_t branch,
                       uint64_t basis, double *part, hipStream_t s,
-                      std::vector<float> *pass_ms = nullptr);
+                      std::vector<float> *pass_ms = nullptr, const void *src0 = nullptr);
 // Launch all passes over `count` batch entries (BatchEntry table on the device).
 qsv_status jit_launch_batched(const Plan &plan, int variant, const void *ents, unsigned count,
                               hipStream_t s);

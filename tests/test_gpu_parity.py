@@ -1008,3 +1008,104 @@ def test_partition_simulate_5x6_d20():
     assert abs(nrm.item() - 1) <= 1e-5
     del ws, out
     torch.cuda.empty_cache()
+
+
+# --- out-of-place sweeps from a parent state; branch-tree prefix sharing ------
+
+@pytest.mark.parametrize("rows,cols,depth,oop", [(4, 5, 10, 0), (4, 5, 10, 1), (4, 6, 12, 0)])
+def test_apply_fused_from(rows, cols, depth, oop):
+    """dst = U(layer range) src with src untouched, against the in-place sweep
+    of a copy and against the oracle (in-place and two-buffer plans)."""
+    _gpu()
+    n = rows * cols
+    seed = 41
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    gates = OC.random_circuit(OC.Lattice(rows, cols), depth, seed)
+    opts = None if not oop else dict(out_of_place=1, jit=1)
+    src = torch.empty(1 << n, dtype=torch.complex64, device=DEV)
+    qsv.sv_simulate(src, c, init_kind=qsv.INIT_PLUS, layer_begin=1, layer_end=4)
+    keep = src.clone()
+    for lb, le in [(4, 9), (4, -1), (9, -1)]:
+        if lb == 9:
+            qsv.sv_apply_fused(src, c, layer_begin=4, layer_end=9)
+            keep = src.clone()
+        dst = torch.empty_like(src)
+        qsv.sv_apply_fused_from(src, dst, c, layer_begin=lb, layer_end=le, opts=opts)
+        ref_dev = src.clone()
+        qsv.sv_apply_fused(ref_dev, c, layer_begin=lb, layer_end=le, opts=opts)
+        torch.cuda.synchronize()
+        assert torch.equal(src, keep)  # the parent state is never written
+        d = (dst - ref_dev).abs().max().item()
+        assert d <= 1e-6, d
+        if le == -1:
+            ref = sim.simulate(gates, n)
+            _check_full(dst, ref, n)
+
+
+def _cut_levels(half):
+    g = half.gates()
+    br = [(int(x["layer"]), int(x["arg"])) for x in g if int(x["kind"]) in (qsv.KIND["PB"], qsv.KIND["ZB"])]
+    layers = sorted({l for l, _ in br})
+    return layers, {l: sorted({b for l2, b in br if l2 == l}) for l in layers}
+
+
+def _branch_tree(half, bufs, leaf, opts=None):
+    """Every branch state of a cut half from a tree of shared prefixes: the
+    state at each cut layer is computed once and each child continues from
+    it with sv_apply_fused_from."""
+    layers, bits_at = _cut_levels(half)
+    qsv.sv_simulate(bufs[0], half, init_kind=qsv.INIT_PLUS, layer_begin=1,
+                    layer_end=layers[0] if layers else -1, opts=opts)
+    if not layers:
+        leaf(bufs[0], 0)
+        return
+
+    def rec(level, parent, prefix):
+        lb = layers[level - 1]
+        le = layers[level] if level < len(layers) else -1
+        bits = bits_at[lb]
+        for v in range(1 << len(bits)):
+            br = prefix
+            for i, b in enumerate(bits):
+                br |= ((v >> i) & 1) << b
+            qsv.sv_apply_fused_from(parent, bufs[level], half, branch=br, layer_begin=lb, layer_end=le,
+                                    opts=opts)
+            if level == len(layers):
+                leaf(bufs[level], br)
+            else:
+                rec(level + 1, bufs[level], br)
+    rec(1, bufs[0], 0)
+
+
+@pytest.mark.parametrize("depth,col,oop", [(12, 2, 0), (12, 2, 1), (9, 3, 0)])
+def test_branch_tree_prefix_sharing(depth, col, oop):
+    """All branch states of the 12-qubit (or 16-qubit) half of a cut 4x6
+    circuit from the prefix tree, each against its own full sweep; two
+    branches against the oracle's split halves."""
+    _gpu()
+    rows, cols, seed = 4, 6, 77
+    n = rows * cols
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    mask = workloads.column_cut_mask(rows, cols, col)
+    ha, hb, ceff, folded = qsv.circuit_split(c, mask)
+    layers, _ = _cut_levels(ha)
+    assert len(layers) >= 2  # a real tree
+    na = ha.n
+    opts = None if not oop else dict(out_of_place=1, jit=1)
+    bufs = [torch.empty(1 << na, dtype=torch.complex64, device=DEV) for _ in range(len(layers) + 1)]
+    one = torch.empty(1 << na, dtype=torch.complex64, device=DEV)
+    seen = []
+    info = sim.split_circuit(OC.random_circuit(OC.Lattice(rows, cols), depth, seed), n,
+                             [q for q in range(n) if (mask >> q) & 1])
+
+    def leaf(st, br):
+        qsv.sv_simulate(one, ha, branch=br, init_kind=qsv.INIT_PLUS, layer_begin=1, opts=opts)
+        d = (st - one).abs().max().item()
+        assert d <= 1e-6, (br, d)
+        if len(seen) < 2:
+            l = tuple((br >> j) & 1 for j in range(ceff))
+            ga, _ = info["half"](l)
+            _check_full(st, sim.simulate(ga, na), na)
+        seen.append(br)
+    _branch_tree(ha, bufs, leaf, opts)
+    assert sorted(seen) == list(range(1 << ceff))
