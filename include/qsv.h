@@ -471,6 +471,8 @@ void circuit_partition_destroy(qsv_partition *p);
  * long as the partition is used with it.  Limits: n <= 34, n_a - sel_a >= 7,
  * 7 <= n_b - sel_b <= 22 (QSV_EUNSUPPORTED otherwise).  Asynchronous on
  * stream (the first call per workspace builds and captures the batch).
+ * Calls on one partition must not overlap (they share its batch); part C
+ * runs out of place in the library's second state buffer for n >= 24.
  */
 qsv_status sv_partition_workspace_bytes(const qsv_partition *p, size_t *bytes);
 qsv_status sv_partition_simulate(qsv_partition *p, void *workspace, size_t ws_bytes, void *out_state,
