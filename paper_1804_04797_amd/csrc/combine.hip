@@ -37,7 +37,8 @@ constexpr int kK = 2 * kBr; // interleaved K per chunk
 __global__ void __launch_bounds__(256, 2)
 k_combine_gemm(const float2 *__restrict__ A, const float2 *__restrict__ B, uint64_t nbr,
                const CombineArgs P, float2 *__restrict__ out) {
-    __shared__ float a1[kK][kTile], a2[kK][kTile], b1[kK][kTile];
+    __shared__ __attribute__((aligned(16))) float a1[kK][kTile];  // also the epilogue's 64-bit tables
+    __shared__ float a2[kK][kTile], b1[kK][kTile];
     const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
     const uint64_t i0 = uint64_t(blockIdx.x) * kTile, j0 = uint64_t(blockIdx.y) * kTile;
     const uint32_t wr = w & 1u, wc = w >> 1;  // quadrant of this wave

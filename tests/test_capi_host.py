@@ -483,3 +483,17 @@ def test_partition_with_absent_sites():
     A, B, Cc, qa, qb = qsv.circuit_partition_parts(p)
     assert sorted(list(qa) + list(qb)) == list(range(lat.n))
     assert all(lat.qubit[(r, k)] in qa for (r, k) in lat.qubit if r < r0)
+
+
+def test_apply_fused_from_argument_checks():
+    """Overlapping or misaligned buffers are refused before any device work."""
+    c = qsv.circuit_create(4, 5, None, 6, 3)
+    base = 1 << 32
+    size = 8 << 20  # 2^20 complex64
+    for src, dst in [(base, base + size // 2), (base + size // 2, base)]:
+        with pytest.raises(qsv.QsvError) as e:
+            qsv.sv_apply_fused_from(src, dst, c, stream=0)
+        assert e.value.status == 1  # QSV_EINVAL
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.sv_apply_fused_from(base + 8, base + 2 * size, c, stream=0)
+    assert e.value.status == 1
