@@ -416,6 +416,7 @@ qsv_status sv_apply_fused(void *amps, const qsv_circuit *c, uint64_t branch, int
         if ((st = get_fused_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jm), true, plan,
                                  &scratch)) != QSV_OK)
             return st;
+        if (plan->passes.empty()) return QSV_OK;  // no gates in the range
         const int variant = kJitPlain | (jm & ~3);
         {
             std::lock_guard<std::mutex> g(plan->jit_mu);
@@ -461,6 +462,10 @@ qsv_status sv_apply_fused_from(const void *src, void *dst, const qsv_circuit *c,
         if ((st = get_fused_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jm), false, plan,
                                  &scratch)) != QSV_OK)
             return st;
+        if (plan->passes.empty()) {  // no gates in the range: dst = src
+            hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+            return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_apply_fused_from: copy");
+        }
         const int variant = kJitPlain | (jm & ~3);
         {
             std::lock_guard<std::mutex> g(plan->jit_mu);

@@ -1025,6 +1025,10 @@ def test_apply_fused_from(rows, cols, depth, oop):
     src = torch.empty(1 << n, dtype=torch.complex64, device=DEV)
     qsv.sv_simulate(src, c, init_kind=qsv.INIT_PLUS, layer_begin=1, layer_end=4)
     keep = src.clone()
+    empty = torch.empty_like(src)
+    qsv.sv_apply_fused_from(src, empty, c, layer_begin=4, layer_end=4, opts=opts)  # no gates: a copy
+    torch.cuda.synchronize()
+    assert torch.equal(empty, src)
     for lb, le in [(4, 9), (4, -1), (9, -1)]:
         if lb == 9:
             qsv.sv_apply_fused(src, c, layer_begin=4, layer_end=9)
