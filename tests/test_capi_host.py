@@ -497,3 +497,15 @@ def test_apply_fused_from_argument_checks():
     with pytest.raises(qsv.QsvError) as e:
         qsv.sv_apply_fused_from(base + 8, base + 2 * size, c, stream=0)
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed,r0", [(3, 4, 8, 77, 1), (4, 5, 10, 5, 2)])
+def test_partition_plan_without_moves(rows, cols, depth, seed, r0):
+    """max_move = 0: the lines cannot leave the initial row, so part C stays
+    empty and only the separation layer is chosen; same optimum as the oracle."""
+    lat = OC.Lattice(rows, cols)
+    gates = OC.random_circuit(lat, depth, seed)
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    want = OPT.plan(lat, gates, r0, 0)
+    info = qsv.circuit_partition_info(qsv.circuit_partition_plan(c, rows, cols, None, r0, 0))
+    assert info["objective"] == want["objective"] and info["n_c"] == 0 == want["c"]
