@@ -89,7 +89,9 @@ typedef struct qsv_batch qsv_batch;      /* opaque */
  *                  compute the current one; 3 = per pass: pass p persistent iff
  *                  bit p of pass_forms is set (p < 23); -1 = always use the
  *                  generic pass kernel; 0 = 1 for states of 2^24 amplitudes or
- *                  more, else -1
+ *                  more, else -1 (the environment variable QSV_JIT=0 makes 0
+ *                  mean -1 everywhere; QSV_JIT_DUMP=<file> writes the last
+ *                  generated source there, a debugging aid)
  *   out_of_place   compiled kernels only.  1 = every pass reads one buffer and
  *                  writes the other (the caller's state and a second state
  *                  buffer the library allocates once per device and keeps), so
