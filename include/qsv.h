@@ -87,7 +87,7 @@ typedef struct qsv_batch qsv_batch;      /* opaque */
  *                  per workgroup; 2 = the same kernels as persistent workgroups
  *                  that prefetch their next tile into registers while they
  *                  compute the current one; 3 = per pass: pass p persistent iff
- *                  bit p of pass_forms is set (p < 23); -1 = always use the
+ *                  bit p of pass_forms is set (p < 22); -1 = always use the
  *                  generic pass kernel; 0 = 1 for states of 2^24 amplitudes or
  *                  more, else -1 (the environment variable QSV_JIT=0 makes 0
  *                  mean -1 everywhere; QSV_JIT_DUMP=<file> writes the last
@@ -214,6 +214,24 @@ qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int in
                        uint64_t basis, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
                        double *norm_out_dev, const uint64_t *bitstrings_dev, size_t m,
                        void *amps_out_dev, int out_c128, void *stream);
+
+/*
+ * sv_simulate_dot - <U |init> | other> in FP64 without storing U |init>:
+ * the sweep of sv_simulate (initial state generated by its first pass) whose
+ * last pass reads `other` at the addresses it would write and accumulates
+ * conj(result) * other, every product of the FP32 values exact in FP64,
+ * summed in a fixed order (per tile, then over tiles).  With U = (layers
+ * [h, end])^dagger (circuit_inverse), init = |x> and other = U1 |+> this is
+ * the Task-2 amplitude <x| U2 U1 |+> of Section 2.2 in one call after the
+ * forward half.  amps: work buffer for the passes before the last
+ * (complex64[2^n], contents unspecified afterwards); other: device
+ * complex64[2^n], not written; out_dev: device double[2] = (re, im).  With
+ * the generic kernel the result is stored to amps and sv_inner_product
+ * follows.  Asynchronous on stream.
+ */
+qsv_status sv_simulate_dot(void *amps, const qsv_circuit *c, uint64_t branch, int init_kind,
+                           uint64_t basis, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
+                           const void *other, double *out_dev, void *stream);
 
 /*
  * sv_simulate_c128 - the same sweep on a complex128 state (device

@@ -220,7 +220,7 @@ int jit_mode(const qsv_circuit *c, const qsv_fuse_opts *opts) {
         j = 1;
     }
     if (j < 0) return 0;
-    if (j == 3) return 1 | kJitPerPass | int((opts->pass_forms & 0x7fffffu) << 8);
+    if (j == 3) return 1 | kJitPerPass | int((opts->pass_forms & ((1u << kJitPassBits) - 1u)) << 8);
     return j >= 2 ? (1 | kJitLoop) : 1;
 }
 
@@ -743,6 +743,60 @@ qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int in
         if (e != hipSuccess) return hip_fail(e, "sv_simulate");
     }
     return QSV_OK;
+}
+
+qsv_status sv_simulate_dot(void *amps, const qsv_circuit *c, uint64_t branch, int init_kind,
+                           uint64_t basis, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
+                           const void *other, double *out_dev, void *stream) {
+    if (!c) return fail(QSV_EINVAL, "sv_simulate_dot: null circuit");
+    qsv_status st = check_state(amps, c->n);
+    if (st != QSV_OK) return st;
+    if ((st = check_state(other, c->n)) != QSV_OK) return st;
+    if (!out_dev) return fail(QSV_EINVAL, "sv_simulate_dot: null output");
+    if (other == amps) return fail(QSV_EINVAL, "sv_simulate_dot: other must not be the work buffer");
+    if (init_kind < 0 || init_kind > 2) return fail(QSV_EINVAL, "sv_simulate_dot: unknown init kind");
+    if (init_kind == QSV_INIT_BASIS && basis >= (1ull << c->n))
+        return fail(QSV_ERANGE, "sv_simulate_dot: basis index >= 2^n");
+    if (init_kind == QSV_INIT_ZERO) basis = 0;
+    if (layer_begin < 0) return fail(QSV_EINVAL, "sv_simulate_dot: layer_begin < 0");
+    qsv_fuse_opts tuned;
+    opts = effective_opts(c, opts, layer_begin, layer_end, &tuned);
+    if ((st = check_device()) != QSV_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TileShape sh;
+    bool fused = !(opts && opts->plain);
+    if (fused) {
+        if ((st = resolve_shape(c, opts, sh, layer_begin, layer_end)) != QSV_OK) return st;
+        fused = sh.R != 0;
+    }
+    const int jm = fused ? jit_mode(c, opts) : 0;
+    std::shared_ptr<Plan> plan;
+    void *scratch = nullptr;
+    if (jm && (st = get_fused_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jm), false, plan,
+                                   &scratch)) != QSV_OK)
+        return st;
+    if (!jm || plan->passes.empty()) {
+        // the sweep into amps, then the inner product (two kernels)
+        if ((st = sv_simulate(amps, c, branch, init_kind, basis, layer_begin, layer_end, opts, nullptr, nullptr,
+                              0, nullptr, 0, stream)) != QSV_OK)
+            return st;
+        return sv_inner_product(amps, other, c->n, out_dev, stream);
+    }
+    // initial state from the first pass; the last pass stores nothing and
+    // writes the FP64 partials of <result|other>
+    const int variant = kJitInit | init_kind | kJitDot | (jm & ~3);
+    {
+        std::lock_guard<std::mutex> g(plan->jit_mu);
+        if ((st = jit_prepare(*plan, variant)) != QSV_OK) return st;
+    }
+    const uint64_t tiles = 1ull << (c->n - sh.R - sh.T);
+    double *part = nullptr;
+    if ((st = norm_partials(2 * tiles, &part)) != QSV_OK) return st;
+    if ((st = jit_launch(*plan, variant, amps, scratch, branch, basis, part, s, nullptr, nullptr, other)) != QSV_OK)
+        return st;
+    hipError_t e = launch_sum_partials(part, tiles, out_dev, s);
+    if (e == hipSuccess) e = launch_sum_partials(part + tiles, tiles, out_dev + 1, s);
+    return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_simulate_dot");
 }
 
 qsv_status sv_simulate_c128(void *amps, const qsv_circuit *c, uint64_t branch, int init_kind,

@@ -671,6 +671,48 @@ struct Gen {
         for (int w = 0; w < waves; ++w) o << "s += red[" << half << " + " << w << "u];\n";
         o << "part[tile] = s;}\n}\n";
     }
+    // FP64 <result|other> of the tile: the other state (the kernel's `a`) is
+    // read at the addresses the store would write; conj(v) * w with exact
+    // FP64 products of the FP32 values, summed in the fixed order of
+    // emit_norm into part[tile] (re) and part[ntile + tile] (im).
+    void emit_dot(bool loop, const std::vector<int> &tst) {
+        o << "{double dre = 0.0, dim = 0.0;\n";
+        if (dp) {
+            o << "const v2d* oth = (const v2d*)(a + (bst | " << scatter_expr("t", tst, true) << "));\n";
+            for (int j = 0; j < N; ++j)
+                o << "{const v2d w = __builtin_nontemporal_load(oth + " << hex64(reg_offset(j, P.st_phys, 0))
+                  << ");dre += v[" << j << "].x*w.x + v[" << j << "].y*w.y;dim += v[" << j << "].x*w.y - v["
+                  << j << "].y*w.x;}\n";
+        } else {
+            o << "const v4f* oth = (const v4f*)(a + (bst | " << scatter_expr("t", tst, true) << "));\n";
+            for (int j = 0; j < N; j += 2) {
+                o << "{const v4f w = __builtin_nontemporal_load(oth + " << hex64(reg_offset(j, P.st_phys, 1) / 2)
+                  << ");\n";
+                for (int h2 = 0; h2 < 2; ++h2) {
+                    const std::string vx = "(double)v[" + std::to_string(j + h2) + "].x";
+                    const std::string vy = "(double)v[" + std::to_string(j + h2) + "].y";
+                    const std::string wx = h2 ? "(double)w.z" : "(double)w.x";
+                    const std::string wy = h2 ? "(double)w.w" : "(double)w.y";
+                    o << "dre += " << vx << "*" << wx << " + " << vy << "*" << wy << ";dim += " << vx << "*" << wy
+                      << " - " << vy << "*" << wx << ";\n";
+                }
+                o << "}\n";
+            }
+        }
+        const int waves = (1 << T) >= 64 ? (1 << T) / 64 : 1;
+        const int width = (1 << T) >= 64 ? 64 : (1 << T);
+        for (int off = width / 2; off >= 1; off /= 2)
+            o << "dre += __shfl_xor(dre, " << off << ", " << width << ");dim += __shfl_xor(dim, " << off << ", "
+              << width << ");\n";
+        o << "__shared__ double rdot[" << 4 * waves << "];\n";
+        const std::string half = loop ? "(unsigned(it & 1u) * " + std::to_string(2 * waves) + "u)" : "0u";
+        o << "if ((t & " << (width - 1) << "u) == 0u) {rdot[" << half << " + t / " << width << "u] = dre;rdot["
+          << half << " + " << waves << "u + t / " << width << "u] = dim;}\n";
+        o << "__syncthreads();\nif (t == 0u) {double sr = 0.0, si = 0.0;\n";
+        for (int w = 0; w < waves; ++w)
+            o << "sr += rdot[" << half << " + " << w << "u];si += rdot[" << half << " + " << waves + w << "u];\n";
+        o << "part[tile - tile0] = sr;part[ntile + (tile - tile0)] = si;}\n}\n";
+    }
     void emit_ops() {
         bool scaled = false;
         for (int pc = 0; pc < P.n_ops; ++pc) {
@@ -712,7 +754,7 @@ struct Gen {
     // ... below tile0 + ntile, loading the next tile into a second register
     // set while it computes the current one.
     std::string emit(const std::string &name, bool &uses_lds, int init_kind = -1, bool norm = false,
-                     int n = 0, bool batched = false, bool loop = false) {
+                     int n = 0, bool batched = false, bool loop = false, bool dot = false) {
         uses_lds = false;
         persistent = loop;
         for (int pc = 0; pc < P.n_ops; ++pc) {
@@ -770,8 +812,12 @@ struct Gen {
         }
         o << "unsigned e = 0u, alive = 1u;\n(void)e; (void)alive;\n";
         emit_ops();
-        emit_store(tst);
-        if (norm) emit_norm(loop);
+        if (dot) {
+            emit_dot(loop, tst);
+        } else {
+            emit_store(tst);
+            if (norm) emit_norm(loop);
+        }
         if (loop) o << "}\n";
         o << "}\n";
         return o.str();
@@ -839,6 +885,7 @@ qsv_status compile_source(const std::string &src, std::vector<char> &code, std::
 std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int variant) {
     const int init_kind = (variant & 4) ? (variant & 3) : -1;
     const bool norm = (variant & 8) != 0;
+    const bool dot = (variant & kJitDot) != 0;
     const bool dp = (variant & kJitDouble) != 0;
     const bool batched = (variant & kJitBatched) != 0;
     std::string src = kPrelude;
@@ -846,8 +893,9 @@ std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int var
         Gen g(plan.passes[p].prog, plan.R, plan.T, dp);
         bool uses_lds = false;
         const bool loop = jit_pass_loop(variant, p) && !batched;
+        const bool last = p + 1 == plan.passes.size();
         src += g.emit("qsv_pass_" + std::to_string(p), uses_lds, p == 0 ? init_kind : -1,
-                      norm && !batched && p + 1 == plan.passes.size(), plan.n, batched, loop);
+                      norm && !batched && last, plan.n, batched, loop, dot && !batched && last);
         if (lds_bytes) lds_bytes->push_back(uses_lds ? size_t(g.lds_elems) * (dp ? 16 : 8) : 0);
     }
     return src;
@@ -862,6 +910,11 @@ qsv_status jit_compile_only(const Plan &plan, size_t *code_bytes, double *second
     qsv_status st = compile_source(jit_source(plan, &lds, kJitDouble | kJitInit | 1 | kJitNorm), code, log);
     if (st != QSV_OK) return st;
     st = compile_source(jit_source(plan, &lds, kJitInit | 1 | kJitNorm | kJitLoop), code, log);
+    if (st != QSV_OK) return st;
+    // the inner-product epilogue, both forms
+    st = compile_source(jit_source(plan, &lds, kJitInit | 2 | kJitDot), code, log);
+    if (st != QSV_OK) return st;
+    st = compile_source(jit_source(plan, &lds, kJitInit | 2 | kJitDot | kJitLoop), code, log);
     if (st != QSV_OK) return st;
     std::string src = jit_source(plan, &lds, kJitInit | 1 | kJitNorm);
     st = compile_source(src, code, log);
@@ -936,7 +989,7 @@ qsv_status jit_prepare(Plan &plan, int variant) {
 
 qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, uint64_t branch,
                       uint64_t basis, double *part, hipStream_t s, std::vector<float> *pass_ms,
-                      const void *src0) {
+                      const void *src0, const void *dot_other) {
     auto vit = plan.jit_variants.find(variant);
     if (vit == plan.jit_variants.end()) return fail(QSV_EINTERNAL, "jit variant not prepared");
     const CacheEntry &e = *static_cast<const CacheEntry *>(vit->second.get());
@@ -963,6 +1016,12 @@ qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, 
             unsigned long long br = branch, tt = t0, bs = basis, nt = cnt;
             void *src = in, *dst = outb;
             double *pt = part;
+            if ((variant & kJitDot) && p + 1 == np) {
+                // the dot pass reads the other state; its partials are indexed
+                // from t0 (re at [0, cnt), im at [cnt, 2 cnt) of this chunk's block)
+                dst = const_cast<void *>(dot_other);
+                pt = part + 2 * t0;
+            }
             void *args[] = {&src, &dst, &br, &tt, &bs, &pt, &nt};
             // a looping kernel gets as many workgroups as the device holds at once
             const uint64_t grid = jit_pass_loop(variant, p) ? std::min<uint64_t>(cnt, e.resident[p]) : cnt;

@@ -19,10 +19,12 @@ constexpr int kJitNorm = 8;
 constexpr int kJitDouble = 16;  // complex128 state (validation instantiation)
 constexpr int kJitBatched = 32; // state and branch per blockIdx.y from a batch entry table
 constexpr int kJitLoop = 64;    // persistent workgroups, next tile prefetched into registers
-constexpr int kJitPerPass = 128; // pass p persistent iff bit (8 + p) of the variant (p < 23)
+constexpr int kJitPerPass = 128; // pass p persistent iff bit (8 + p) of the variant (p < 22)
+constexpr int kJitPassBits = 22;
+constexpr int kJitDot = 1 << 30; // the last pass stores nothing: FP64 <result|other> partials per tile
 inline bool jit_pass_loop(int variant, size_t p) {
     if (variant & kJitLoop) return true;
-    return (variant & kJitPerPass) && p < 23 && ((variant >> (8 + p)) & 1);
+    return (variant & kJitPerPass) && p < size_t(kJitPassBits) && ((variant >> (8 + p)) & 1);
 }
 
 // HIP source of every pass of the plan as kernels qsv_pass_<p>.
@@ -31,9 +33,13 @@ std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int var
 qsv_status jit_prepare(Plan &plan, int variant);
 // Launch all passes of a prepared plan on stream s.  src0 (optional): the
 // first pass reads this state instead of amps, which it leaves unchanged.
+// kJitDot variants: the last pass reads dot_other at its store addresses and
+// writes the FP64 partials of <result|other> to part (re of every tile, then
+// im of every tile) instead of storing the result.
 qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, uint64_t branch,
                       uint64_t basis, double *part, hipStream_t s,
-                      std::vector<float> *pass_ms = nullptr, const void *src0 = nullptr);
+                      std::vector<float> *pass_ms = nullptr, const void *src0 = nullptr,
+                      const void *dot_other = nullptr);
 // Launch all passes over `count` batch entries (BatchEntry table on the device).
 qsv_status jit_launch_batched(const Plan &plan, int variant, const void *ents, unsigned count,
                               hipStream_t s);

@@ -34,6 +34,7 @@ EXPORTS = ["circuit_create", "circuit_destroy", "circuit_info", "circuit_gates",
            "circuit_partition_plan", "circuit_partition_create", "circuit_partition_info",
            "circuit_partition_offsets", "circuit_partition_parts", "circuit_partition_destroy",
            "sv_partition_workspace_bytes", "sv_partition_simulate", "sv_apply_fused_from",
+           "sv_simulate_dot",
            "qsv_last_error", "qsv_version"]
 
 
@@ -78,6 +79,7 @@ def lib():
         "sv_apply_fused": (st, [vp, vp, u64, i32, i32, vp, vp]),
         "sv_apply_plain": (st, [vp, vp, u64, i32, i32, vp]),
         "sv_apply_fused_from": (st, [vp, vp, vp, u64, i32, i32, vp, vp]),
+        "sv_simulate_dot": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, vp, vp]),
         "sv_simulate": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, vp, sz, vp, i32, vp]),
         "sv_simulate_c128": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, sz, vp, vp]),
         "sv_amplitudes": (st, [vp, i32, vp, sz, vp, i32, vp]),
@@ -260,6 +262,14 @@ def sv_simulate_c128(amps, c, branch=0, init_kind=INIT_ZERO, basis=0, layer_begi
 def sv_apply_fused_from(src, dst, c, branch=0, layer_begin=0, layer_end=-1, opts=None, stream=None):
     _check(lib().sv_apply_fused_from(_ptr(src), _ptr(dst), c, ctypes.c_uint64(branch), layer_begin,
                                      layer_end, _opts(opts), _stream(stream)))
+
+
+def sv_simulate_dot(amps, c, other, out_dev, branch=0, init_kind=INIT_ZERO, basis=0, layer_begin=0,
+                    layer_end=-1, opts=None, stream=None):
+    """out_dev (device float64[2]) = <U init | other>; amps is a work buffer."""
+    _check(lib().sv_simulate_dot(_ptr(amps), c, ctypes.c_uint64(branch), init_kind, ctypes.c_uint64(basis),
+                                 layer_begin, layer_end, _opts(opts), _ptr(other), _ptr(out_dev),
+                                 _stream(stream)))
 
 
 def sv_apply_plain(amps, c, branch=0, layer_begin=0, layer_end=-1, stream=None):

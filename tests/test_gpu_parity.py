@@ -1113,3 +1113,52 @@ def test_branch_tree_prefix_sharing(depth, col, oop):
         seen.append(br)
     _branch_tree(ha, bufs, leaf, opts)
     assert sorted(seen) == list(range(1 << ceff))
+
+
+# --- Task-2 amplitude with the inner product in the last pass ------------------
+
+def _dot_amplitudes(c, n, xs, h, opts=None):
+    inv = qsv.circuit_inverse(c)
+    top = max(int(g["layer"]) for g in c.gates())
+    psi = torch.empty(1 << n, dtype=torch.complex64, device=DEV)
+    qsv.sv_simulate(psi, c, init_kind=qsv.INIT_PLUS, layer_begin=1, layer_end=h, opts=opts)
+    work = torch.empty_like(psi)
+    dot = torch.zeros(2, dtype=torch.float64, device=DEV)
+    out = []
+    for x in xs:
+        qsv.sv_simulate_dot(work, inv, psi, dot, init_kind=qsv.INIT_BASIS, basis=int(x), layer_begin=0,
+                            layer_end=top - h + 1, opts=opts)
+        d = dot.cpu().numpy()
+        out.append(complex(d[0], d[1]))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("jit", [-1, 1, 2])
+def test_task2_dot_epilogue_4x5(jit):
+    """<x|U2 U1|+> with the FP64 inner product accumulated by the adjoint
+    sweep's last pass (no store), against the oracle and against the two-step
+    method (sweep, store, sv_inner_product) on identical FP32 values."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("4x5-d10")
+    n = lat.n
+    ref = sim.run(np.full(1 << n, 2.0 ** (-n / 2), np.complex128), n,
+                  [g for g in _oracle_gates(c) if g[3] >= 1])
+    xs = workloads.bitstrings(n, 12, 21)
+    opts = _opts(None, jit)
+    got = _dot_amplitudes(c, n, xs, 5, opts)
+    assert np.max(np.abs(got - ref[xs])) <= TOL
+    two = _half_sweep_amplitudes(c, n, xs, 5, opts)
+    assert np.max(np.abs(got - two)) <= 1e-12
+
+
+def test_task2_dot_epilogue_5x6_d20_golden():
+    """Full size: 16 amplitudes of the 30-qubit workload from the forward half
+    and one adjoint sweep each with the inner-product epilogue, against the
+    stored oracle amplitudes."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("5x6-d20")
+    xs, ref = _golden("5x6-d20")
+    n = lat.n
+    got = _dot_amplitudes(c, n, xs[:16], 11)
+    d = np.max(np.abs(got - ref[:16]))
+    assert d <= TOL and d * 2 ** (n / 2) <= TOL_SCALED, d
