@@ -87,7 +87,7 @@ typedef struct qsv_batch qsv_batch;      /* opaque */
  *                  per workgroup; 2 = the same kernels as persistent workgroups
  *                  that prefetch their next tile into registers while they
  *                  compute the current one; 3 = per pass: pass p persistent iff
- *                  bit p of pass_forms is set (p < 22); -1 = always use the
+ *                  bit p of pass_forms is set (p < 21); -1 = always use the
  *                  generic pass kernel; 0 = 1 for states of 2^24 amplitudes or
  *                  more, else -1 (the environment variable QSV_JIT=0 makes 0
  *                  mean -1 everywhere; QSV_JIT_DUMP=<file> writes the last
@@ -281,6 +281,31 @@ qsv_status sv_apply_plain(void *amps, const qsv_circuit *c, uint64_t branch,
  */
 qsv_status sv_apply_dense(void *amps, const qsv_circuit *c, uint64_t branch, int layer_begin,
                           int layer_end, int k, int *n_blocks, void *stream);
+
+/*
+ * Sampling from a parent state: amplitudes of U src at a fixed set of m
+ * bitstrings, where U = the gates of layers [layer_begin, layer_end) with
+ * the branch bits of each run.  For the leaves of a branch tree (Task 2 over
+ * cut circuits, Section 2.2 / Fig. 2) only sampled amplitudes of each leaf
+ * are needed: the last pass of the sweep runs only the tiles that hold a
+ * requested index (at most m of them) and writes those amplitudes instead
+ * of the state, so the leaf's state is never stored.
+ * sv_sampler_create: plans the sweep, groups the bitstrings (host array,
+ *   each < 2^n, copied) by the last pass's tile and prepares the kernels;
+ *   the circuit must stay alive until sv_sampler_destroy.
+ * sv_sampler_run: out_dev[k] (device complex64[m]) = (U src)[bitstrings[k]];
+ *   src: device complex64[2^n], not written; work: another device
+ *   complex64[2^n] for the passes before the last (contents unspecified
+ *   afterwards).  With the generic kernel the sweep is stored to work and
+ *   gathered.  Asynchronous on stream; calls that overlap on one device
+ *   share the library's second state buffer.
+ */
+typedef struct qsv_sampler qsv_sampler;  /* opaque */
+qsv_status sv_sampler_create(const qsv_circuit *c, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
+                             const uint64_t *bitstrings, size_t m, qsv_sampler **out);
+qsv_status sv_sampler_run(qsv_sampler *s, const void *src, void *work, uint64_t branch, void *out_dev,
+                          void *stream);
+void sv_sampler_destroy(qsv_sampler *s);
 
 /*
  * sv_amplitudes - gather alpha_x for m bitstrings (Task 2 of Section 1).

@@ -1,6 +1,7 @@
 // C-ABI entry points of the qsv library (declared in include/qsv.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -478,6 +479,133 @@ qsv_status sv_apply_fused_from(const void *src, void *dst, const qsv_circuit *c,
     if (e != hipSuccess) return hip_fail(e, "sv_apply_fused_from: copy");
     return sv_apply_fused(dst, c, branch, layer_begin, layer_end, opts, stream);
 }
+
+}  // extern "C"
+
+struct qsv_sampler {
+    const qsv_circuit *c = nullptr;
+    int lb = 0, le = -1;
+    bool has_opts = false;
+    qsv_fuse_opts opts{};
+    uint64_t m = 0, ntiles = 0;
+    bool compiled = false;     // sampling pass kernels; else sweep + gather
+    TileShape sh{};
+    int jm = 0;
+    std::shared_ptr<Plan> plan;
+    void *d_mem = nullptr;     // SampleTab + its arrays
+    uint64_t *d_xs = nullptr;  // bitstrings for the gather form
+    ~qsv_sampler() {
+        if (d_mem) hipFree(d_mem);
+        if (d_xs) hipFree(d_xs);
+    }
+};
+
+extern "C" {
+
+qsv_status sv_sampler_create(const qsv_circuit *c, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
+                             const uint64_t *bitstrings, size_t m, qsv_sampler **out) {
+    if (!c || !out || (m && !bitstrings)) return fail(QSV_EINVAL, "sv_sampler_create: null argument");
+    if (m == 0 || m > (size_t(1) << 32)) return fail(QSV_ERANGE, "sv_sampler_create: m out of range");
+    if (layer_begin < 0) return fail(QSV_EINVAL, "sv_sampler_create: layer_begin < 0");
+    for (size_t k = 0; k < m; ++k)
+        if (bitstrings[k] >> c->n) return fail(QSV_ERANGE, "sv_sampler_create: bitstring >= 2^n");
+    qsv_status st = check_device();
+    if (st != QSV_OK) return st;
+    auto S = std::unique_ptr<qsv_sampler>(new qsv_sampler);
+    S->c = c; S->lb = layer_begin; S->le = layer_end; S->m = m;
+    if (opts) { S->opts = *opts; S->has_opts = true; }
+    qsv_fuse_opts tuned;
+    const qsv_fuse_opts *eo = effective_opts(c, opts, layer_begin, layer_end, &tuned);
+    bool fused = !(eo && eo->plain);
+    if (fused) {
+        if ((st = resolve_shape(c, eo, S->sh, layer_begin, layer_end)) != QSV_OK) return st;
+        fused = S->sh.R != 0;
+    }
+    S->jm = fused ? jit_mode(c, eo) : 0;
+    hipError_t e;
+    if (S->jm) {
+        void *scratch = nullptr;
+        if ((st = get_fused_plan(c, layer_begin, layer_end, S->sh, oop_mode(c, eo, S->jm), false, S->plan,
+                                 &scratch)) != QSV_OK)
+            return st;
+        S->compiled = !S->plan->passes.empty();
+    }
+    if (S->compiled) {
+        // entries sorted by the tile of the last pass that holds them
+        const PassProg &L = S->plan->passes.back().prog;
+        std::vector<std::pair<uint64_t, uint32_t>> ent(m);
+        for (size_t k = 0; k < m; ++k) {
+            uint64_t tile = 0;
+            for (int i = 0; i < L.n_glob; ++i) tile |= ((bitstrings[k] >> L.glob_st[i]) & 1ull) << i;
+            ent[k] = {tile, uint32_t(k)};
+        }
+        std::sort(ent.begin(), ent.end());
+        std::vector<uint64_t> tiles, xs(m);
+        std::vector<uint32_t> start, slot(m);
+        for (size_t k = 0; k < m; ++k) {
+            if (tiles.empty() || tiles.back() != ent[k].first) {
+                tiles.push_back(ent[k].first);
+                start.push_back(uint32_t(k));
+            }
+            xs[k] = bitstrings[ent[k].second];
+            slot[k] = ent[k].second;
+        }
+        start.push_back(uint32_t(m));
+        S->ntiles = tiles.size();
+        const size_t off_t = 64, off_s = off_t + 8 * tiles.size(), off_x = (off_s + 4 * start.size() + 7) / 8 * 8,
+                     off_l = off_x + 8 * m, bytes = off_l + 4 * m;
+        if ((e = hipMalloc(&S->d_mem, bytes)) != hipSuccess) return hip_fail(e, "sv_sampler_create");
+        char *d = static_cast<char *>(S->d_mem);
+        SampleTab head{reinterpret_cast<const uint64_t *>(d + off_t), reinterpret_cast<const uint32_t *>(d + off_s),
+                       reinterpret_cast<const uint64_t *>(d + off_x), reinterpret_cast<const uint32_t *>(d + off_l)};
+        std::vector<char> h(bytes, 0);
+        std::memcpy(h.data(), &head, sizeof(head));
+        std::memcpy(h.data() + off_t, tiles.data(), 8 * tiles.size());
+        std::memcpy(h.data() + off_s, start.data(), 4 * start.size());
+        std::memcpy(h.data() + off_x, xs.data(), 8 * m);
+        std::memcpy(h.data() + off_l, slot.data(), 4 * m);
+        if ((e = hipMemcpy(S->d_mem, h.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "sv_sampler_create");
+        std::lock_guard<std::mutex> g(S->plan->jit_mu);
+        if ((st = jit_prepare(*S->plan, kJitPlain | kJitSample | (S->jm & ~3))) != QSV_OK) return st;
+    } else {
+        if ((e = hipMalloc(&S->d_xs, 8 * m)) != hipSuccess) return hip_fail(e, "sv_sampler_create");
+        if ((e = hipMemcpy(S->d_xs, bitstrings, 8 * m, hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "sv_sampler_create");
+    }
+    *out = S.release();
+    return QSV_OK;
+}
+
+qsv_status sv_sampler_run(qsv_sampler *S, const void *src, void *work, uint64_t branch, void *out_dev,
+                          void *stream) {
+    if (!S || !out_dev) return fail(QSV_EINVAL, "sv_sampler_run: null argument");
+    const qsv_circuit *c = S->c;
+    qsv_status st = check_state(src, c->n);
+    if (st != QSV_OK) return st;
+    if ((st = check_state(work, c->n)) != QSV_OK) return st;
+    if (src == work) return fail(QSV_EINVAL, "sv_sampler_run: work must not be src");
+    if ((st = check_device()) != QSV_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const qsv_fuse_opts *opts = S->has_opts ? &S->opts : nullptr;
+    if (!S->compiled) {
+        if ((st = sv_apply_fused_from(src, work, c, branch, S->lb, S->le, opts, stream)) != QSV_OK) return st;
+        hipError_t e = launch_gather(static_cast<const float2 *>(work), c->n, S->d_xs, S->m, out_dev, 0, s);
+        return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_sampler_run");
+    }
+    qsv_fuse_opts tuned;
+    const qsv_fuse_opts *eo = effective_opts(c, opts, S->lb, S->le, &tuned);
+    std::shared_ptr<Plan> plan;
+    void *scratch = nullptr;  // fetched per run: the second buffer may have been regrown
+    if ((st = get_fused_plan(c, S->lb, S->le, S->sh, oop_mode(c, eo, S->jm), false, plan, &scratch)) != QSV_OK)
+        return st;
+    if (plan != S->plan) return fail(QSV_EINTERNAL, "sv_sampler_run: the circuit's plan changed");
+    const int variant = kJitPlain | kJitSample | (S->jm & ~3);
+    return jit_launch(*plan, variant, work, scratch, branch, 0, nullptr, s, nullptr, src, nullptr,
+                      static_cast<const SampleTab *>(S->d_mem), S->ntiles, out_dev);
+}
+
+void sv_sampler_destroy(qsv_sampler *S) { delete S; }
 
 qsv_status sv_amplitudes(const void *amps, int n_qubits, const uint64_t *bitstrings_dev, size_t m,
                          void *out_dev, int out_c128, void *stream) {

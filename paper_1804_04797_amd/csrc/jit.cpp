@@ -44,6 +44,12 @@ __device__ __forceinline__ float2 xsign(float2 a, unsigned m) {
     return make_float2(__uint_as_float(__float_as_uint(a.x) ^ m),
                        __uint_as_float(__float_as_uint(a.y) ^ m));
 }
+struct SampleTabJ {  // layout of the library's sampling table
+    const unsigned long long *tiles;
+    const unsigned *start;
+    const unsigned long long *xs;
+    const unsigned *slot;
+};
 struct BatchEntryJ {  // layout of the library's batch entry table
     void *amps;
     unsigned long long branch;
@@ -671,6 +677,23 @@ struct Gen {
         for (int w = 0; w < waves; ++w) o << "s += red[" << half << " + " << w << "u];\n";
         o << "part[tile] = s;}\n}\n";
     }
+    // Sampling pass: for each listed output index x of this tile, the thread
+    // whose slots hold x writes its amplitude to part (complex64) at the
+    // entry's slot; x's thread and register coordinates are its bits at the
+    // store positions of the thread and register slots.
+    void emit_sample() {
+        o << "{" << CT << "* outp = (" << CT << "*)part;\n";
+        o << "const unsigned e1 = tab->start[blockIdx.x + 1u];\n";
+        o << "for (unsigned e = tab->start[blockIdx.x]; e < e1; ++e) {\n";
+        o << "const unsigned long long x = tab->xs[e];\nunsigned tt = 0u, jj = 0u;\n";
+        for (int u = 0; u < T; ++u)
+            o << "tt |= unsigned((x >> " << int(P.st_phys[R + u]) << ") & 1ull) << " << u << ";\n";
+        for (int q = 0; q < R; ++q)
+            o << "jj |= unsigned((x >> " << int(P.st_phys[q]) << ") & 1ull) << " << q << ";\n";
+        o << "if (tt == t) {" << CT << " val = v[0];\nswitch (jj) {\n";
+        for (int j = 1; j < N; ++j) o << "case " << j << "u: val = v[" << j << "]; break;\n";
+        o << "default: break;\n}\noutp[tab->slot[e]] = val;}\n}\n}\n";
+    }
     // FP64 <result|other> of the tile: the other state (the kernel's `a`) is
     // read at the addresses the store would write; conj(v) * w with exact
     // FP64 products of the FP32 values, summed in the fixed order of
@@ -754,7 +777,9 @@ struct Gen {
     // ... below tile0 + ntile, loading the next tile into a second register
     // set while it computes the current one.
     std::string emit(const std::string &name, bool &uses_lds, int init_kind = -1, bool norm = false,
-                     int n = 0, bool batched = false, bool loop = false, bool dot = false) {
+                     int n = 0, bool batched = false, bool loop = false, bool dot = false,
+                     bool sample = false) {
+        if (sample) loop = false;  // one workgroup per listed tile
         uses_lds = false;
         persistent = loop;
         for (int pc = 0; pc < P.n_ops; ++pc) {
@@ -779,7 +804,14 @@ struct Gen {
         }
         if (uses_lds) o << "extern __shared__ " << CT << " lds[];\n";
         o << "const unsigned t = threadIdx.x;\n(void)basis; (void)part; (void)branch; (void)srcp;\n";
-        if (!loop) {
+        if (sample) {
+            o << "const SampleTabJ* tab = (const SampleTabJ*)a;\n";
+            o << "const unsigned long long tile = tab->tiles[blockIdx.x];\n";
+            o << "const unsigned long long base = " << scatter_expr("tile", glob, true) << ";\n";
+            o << CT << " v[" << N << "];\n";
+            if (init_kind >= 0) emit_init(init_kind, n, tld);
+            else emit_load("v", "base", tld);
+        } else if (!loop) {
             o << "const unsigned long long tile = tile0 + blockIdx.x;\n";
             o << "const unsigned long long base = " << scatter_expr("tile", glob, true) << ";\n";
             o << "const unsigned long long bst = " << scatter_expr("tile", globst, true) << ";\n";
@@ -812,7 +844,9 @@ struct Gen {
         }
         o << "unsigned e = 0u, alive = 1u;\n(void)e; (void)alive;\n";
         emit_ops();
-        if (dot) {
+        if (sample) {
+            emit_sample();
+        } else if (dot) {
             emit_dot(loop, tst);
         } else {
             emit_store(tst);
@@ -886,6 +920,7 @@ std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int var
     const int init_kind = (variant & 4) ? (variant & 3) : -1;
     const bool norm = (variant & 8) != 0;
     const bool dot = (variant & kJitDot) != 0;
+    const bool sample = (variant & kJitSample) != 0;
     const bool dp = (variant & kJitDouble) != 0;
     const bool batched = (variant & kJitBatched) != 0;
     std::string src = kPrelude;
@@ -895,7 +930,8 @@ std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int var
         const bool loop = jit_pass_loop(variant, p) && !batched;
         const bool last = p + 1 == plan.passes.size();
         src += g.emit("qsv_pass_" + std::to_string(p), uses_lds, p == 0 ? init_kind : -1,
-                      norm && !batched && last, plan.n, batched, loop, dot && !batched && last);
+                      norm && !batched && last, plan.n, batched, loop, dot && !batched && last,
+                      sample && !batched && last);
         if (lds_bytes) lds_bytes->push_back(uses_lds ? size_t(g.lds_elems) * (dp ? 16 : 8) : 0);
     }
     return src;
@@ -915,6 +951,8 @@ qsv_status jit_compile_only(const Plan &plan, size_t *code_bytes, double *second
     st = compile_source(jit_source(plan, &lds, kJitInit | 2 | kJitDot), code, log);
     if (st != QSV_OK) return st;
     st = compile_source(jit_source(plan, &lds, kJitInit | 2 | kJitDot | kJitLoop), code, log);
+    if (st != QSV_OK) return st;
+    st = compile_source(jit_source(plan, &lds, kJitSample), code, log);  // sampling last pass
     if (st != QSV_OK) return st;
     std::string src = jit_source(plan, &lds, kJitInit | 1 | kJitNorm);
     st = compile_source(src, code, log);
@@ -989,7 +1027,8 @@ qsv_status jit_prepare(Plan &plan, int variant) {
 
 qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, uint64_t branch,
                       uint64_t basis, double *part, hipStream_t s, std::vector<float> *pass_ms,
-                      const void *src0, const void *dot_other) {
+                      const void *src0, const void *dot_other, const SampleTab *sample_tab,
+                      uint64_t sample_tiles, void *sample_out) {
     auto vit = plan.jit_variants.find(variant);
     if (vit == plan.jit_variants.end()) return fail(QSV_EINTERNAL, "jit variant not prepared");
     const CacheEntry &e = *static_cast<const CacheEntry *>(vit->second.get());
@@ -1011,6 +1050,20 @@ qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, 
     for (size_t p = 0; p < np; ++p) {
         if (pass_ms && hipEventRecord(ev[p], s) != hipSuccess) return fail(QSV_EHIP, "jit_launch: event");
         void *outb = (!plan.oop || (np - p) % 2 == 1) ? amps : scratch;
+        if ((variant & kJitSample) && p + 1 == np) {
+            // the listed tiles only; writes the listed amplitudes
+            if (sample_tiles) {
+                unsigned long long br = branch, tt = 0, bs = basis, nt = sample_tiles;
+                void *src = in, *dst = const_cast<SampleTab *>(sample_tab);
+                double *pt = static_cast<double *>(sample_out);
+                void *args[] = {&src, &dst, &br, &tt, &bs, &pt, &nt};
+                hipError_t he = hipModuleLaunchKernel(e.fns[p], unsigned(sample_tiles), 1, 1, 1u << plan.T, 1, 1,
+                                                      unsigned(e.lds[p]), s, args, nullptr);
+                if (he != hipSuccess)
+                    return fail(QSV_EHIP, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(he));
+            }
+            break;
+        }
         for (uint64_t t0 = 0; t0 < tiles; t0 += chunk) {
             const uint64_t cnt = (tiles - t0 < chunk) ? tiles - t0 : chunk;
             unsigned long long br = branch, tt = t0, bs = basis, nt = cnt;

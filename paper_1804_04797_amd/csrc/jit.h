@@ -19,8 +19,9 @@ constexpr int kJitNorm = 8;
 constexpr int kJitDouble = 16;  // complex128 state (validation instantiation)
 constexpr int kJitBatched = 32; // state and branch per blockIdx.y from a batch entry table
 constexpr int kJitLoop = 64;    // persistent workgroups, next tile prefetched into registers
-constexpr int kJitPerPass = 128; // pass p persistent iff bit (8 + p) of the variant (p < 22)
-constexpr int kJitPassBits = 22;
+constexpr int kJitPerPass = 128; // pass p persistent iff bit (8 + p) of the variant (p < 21)
+constexpr int kJitPassBits = 21;
+constexpr int kJitSample = 1 << 29; // the last pass runs only listed tiles and writes listed amplitudes
 constexpr int kJitDot = 1 << 30; // the last pass stores nothing: FP64 <result|other> partials per tile
 inline bool jit_pass_loop(int variant, size_t p) {
     if (variant & kJitLoop) return true;
@@ -36,10 +37,20 @@ qsv_status jit_prepare(Plan &plan, int variant);
 // kJitDot variants: the last pass reads dot_other at its store addresses and
 // writes the FP64 partials of <result|other> to part (re of every tile, then
 // im of every tile) instead of storing the result.
+// kJitSample variants: the last pass runs sample_tiles workgroups over the
+// tile list of the device table sample_tab and writes the listed amplitudes
+// to sample_out (complex64) instead of storing the state.
+struct SampleTab {  // device layout read by the sampling pass
+    const uint64_t *tiles;   // tile index of workgroup b
+    const uint32_t *start;   // entries of workgroup b: [start[b], start[b + 1])
+    const uint64_t *xs;      // output index of each entry
+    const uint32_t *slot;    // position of each entry in the output array
+};
 qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, uint64_t branch,
                       uint64_t basis, double *part, hipStream_t s,
                       std::vector<float> *pass_ms = nullptr, const void *src0 = nullptr,
-                      const void *dot_other = nullptr);
+                      const void *dot_other = nullptr, const SampleTab *sample_tab = nullptr,
+                      uint64_t sample_tiles = 0, void *sample_out = nullptr);
 // Launch all passes over `count` batch entries (BatchEntry table on the device).
 qsv_status jit_launch_batched(const Plan &plan, int variant, const void *ents, unsigned count,
                               hipStream_t s);

@@ -34,7 +34,7 @@ EXPORTS = ["circuit_create", "circuit_destroy", "circuit_info", "circuit_gates",
            "circuit_partition_plan", "circuit_partition_create", "circuit_partition_info",
            "circuit_partition_offsets", "circuit_partition_parts", "circuit_partition_destroy",
            "sv_partition_workspace_bytes", "sv_partition_simulate", "sv_apply_fused_from",
-           "sv_simulate_dot",
+           "sv_simulate_dot", "sv_sampler_create", "sv_sampler_run", "sv_sampler_destroy",
            "qsv_last_error", "qsv_version"]
 
 
@@ -80,6 +80,9 @@ def lib():
         "sv_apply_plain": (st, [vp, vp, u64, i32, i32, vp]),
         "sv_apply_fused_from": (st, [vp, vp, vp, u64, i32, i32, vp, vp]),
         "sv_simulate_dot": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, vp, vp]),
+        "sv_sampler_create": (st, [vp, i32, i32, vp, vp, sz, P(vp)]),
+        "sv_sampler_run": (st, [vp, vp, vp, u64, vp, vp]),
+        "sv_sampler_destroy": (None, [vp]),
         "sv_simulate": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, vp, sz, vp, i32, vp]),
         "sv_simulate_c128": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, sz, vp, vp]),
         "sv_amplitudes": (st, [vp, i32, vp, sz, vp, i32, vp]),
@@ -492,3 +495,34 @@ def sv_partition_workspace_bytes(p) -> int:
 
 def sv_partition_simulate(p, workspace, ws_bytes, out_state, stream=None):
     _check(lib().sv_partition_simulate(p, _ptr(workspace), ws_bytes, _ptr(out_state), _stream(stream)))
+
+
+class Sampler:
+    """Owning handle of a qsv_sampler (keeps its circuit alive)."""
+
+    def __init__(self, handle, circuit, m):
+        self.handle = handle
+        self.circuit = circuit
+        self.m = m
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.sv_sampler_destroy(self.handle)
+            self.handle = None
+
+    @property
+    def _as_parameter_(self):
+        return ctypes.c_void_p(self.handle)
+
+
+def sv_sampler_create(c, bitstrings, layer_begin=0, layer_end=-1, opts=None) -> Sampler:
+    xs = np.ascontiguousarray(np.asarray(bitstrings, dtype=np.uint64))
+    out = ctypes.c_void_p()
+    _check(lib().sv_sampler_create(c, layer_begin, layer_end, _opts(opts), _ptr(xs), xs.size,
+                                   ctypes.byref(out)))
+    return Sampler(out.value, c, xs.size)
+
+
+def sv_sampler_run(sampler, src, work, out, branch=0, stream=None):
+    _check(lib().sv_sampler_run(sampler, _ptr(src), _ptr(work), ctypes.c_uint64(branch), _ptr(out),
+                                _stream(stream)))

@@ -1162,3 +1162,80 @@ def test_task2_dot_epilogue_5x6_d20_golden():
     got = _dot_amplitudes(c, n, xs[:16], 11)
     d = np.max(np.abs(got - ref[:16]))
     assert d <= TOL and d * 2 ** (n / 2) <= TOL_SCALED, d
+
+
+# --- sampling pass: only the tiles holding requested amplitudes ---------------
+
+@pytest.mark.parametrize("rows,cols,depth,lb,jit,oop", [(4, 5, 10, 4, 1, 0), (4, 5, 10, 4, 2, 1),
+                                                        (4, 6, 12, 6, 1, 1), (4, 6, 12, 9, 2, 0)])
+def test_sampler_matches_full_sweep(rows, cols, depth, lb, jit, oop):
+    """Amplitudes of U src at m bitstrings from the sampling last pass, against
+    the stored out-of-place sweep of the same plan and the gather (identical
+    arithmetic, so bit-identical), src untouched; and against the oracle."""
+    _gpu()
+    n = rows * cols
+    seed = 43
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    opts = dict(jit=jit, out_of_place=1 if oop else -1)
+    src = torch.empty(1 << n, dtype=torch.complex64, device=DEV)
+    qsv.sv_simulate(src, c, init_kind=qsv.INIT_PLUS, layer_begin=1, layer_end=lb)
+    keep = src.clone()
+    xs = workloads.bitstrings(n, 37, 5)
+    xs = np.concatenate([xs, xs[:3]])  # repeated bitstrings are each written
+    smp = qsv.sv_sampler_create(c, xs, layer_begin=lb, opts=opts)
+    work = torch.empty_like(src)
+    out = torch.empty(xs.size, dtype=torch.complex64, device=DEV)
+    qsv.sv_sampler_run(smp, src, work, out)
+    full = torch.empty_like(src)
+    qsv.sv_apply_fused_from(src, full, c, layer_begin=lb, opts=opts)
+    ref_dev = torch.empty(xs.size, dtype=torch.complex64, device=DEV)
+    qsv.sv_amplitudes(full, n, torch.from_numpy(xs.view(np.int64)).to(DEV), ref_dev)
+    torch.cuda.synchronize()
+    assert torch.equal(src, keep)
+    assert torch.equal(out, ref_dev)
+    ref = sim.simulate(OC.random_circuit(OC.Lattice(rows, cols), depth, seed), n)
+    assert np.max(np.abs(out.cpu().numpy() - ref[xs])) <= TOL
+
+
+def test_sampler_branch_tree_leaves():
+    """Leaves of a branch tree sampled without storing them: every branch's
+    sampled amplitudes against its full sweep."""
+    _gpu()
+    rows, cols, depth, seed = 4, 6, 12, 77
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    mask = workloads.column_cut_mask(rows, cols, 2)
+    ha, hb, ceff, folded = qsv.circuit_split(c, mask)
+    layers, bits_at = _cut_levels(ha)
+    na = ha.n
+    xs = workloads.bitstrings(na, 50, 9)
+    xt = torch.from_numpy(xs.view(np.int64)).to(DEV)
+    opts = dict(jit=1, out_of_place=1)
+    smp = qsv.sv_sampler_create(ha, xs, layer_begin=layers[-1], opts=opts)
+    bufs = [torch.empty(1 << na, dtype=torch.complex64, device=DEV) for _ in range(len(layers))]
+    work = torch.empty(1 << na, dtype=torch.complex64, device=DEV)
+    out = torch.empty(xs.size, dtype=torch.complex64, device=DEV)
+    one = torch.empty(1 << na, dtype=torch.complex64, device=DEV)
+    ref_o = torch.empty(xs.size, dtype=torch.complex64, device=DEV)
+    qsv.sv_simulate(bufs[0], ha, init_kind=qsv.INIT_PLUS, layer_begin=1, layer_end=layers[0], opts=opts)
+    seen = []
+
+    def rec(level, parent, prefix):
+        lb = layers[level - 1]
+        last = level == len(layers)
+        for v in range(1 << len(bits_at[lb])):
+            br = prefix
+            for i, b in enumerate(bits_at[lb]):
+                br |= ((v >> i) & 1) << b
+            if last:
+                qsv.sv_sampler_run(smp, parent, work, out, branch=br)
+                qsv.sv_simulate(one, ha, branch=br, init_kind=qsv.INIT_PLUS, layer_begin=1, opts=opts)
+                qsv.sv_amplitudes(one, na, xt, ref_o)
+                d = (out - ref_o).abs().max().item()
+                assert d <= 1e-6, (br, d)
+                seen.append(br)
+            else:
+                qsv.sv_apply_fused_from(parent, bufs[level], ha, branch=br, layer_begin=lb,
+                                        layer_end=layers[level], opts=opts)
+                rec(level + 1, bufs[level], br)
+    rec(1, bufs[0], 0)
+    assert sorted(seen) == list(range(1 << ceff))
