@@ -509,3 +509,14 @@ def test_partition_plan_without_moves(rows, cols, depth, seed, r0):
     want = OPT.plan(lat, gates, r0, 0)
     info = qsv.circuit_partition_info(qsv.circuit_partition_plan(c, rows, cols, None, r0, 0))
     assert info["objective"] == want["objective"] and info["n_c"] == 0 == want["c"]
+
+
+def test_sampler_argument_checks():
+    """Bitstrings >= 2^n and an empty set are refused before any device work."""
+    c = qsv.circuit_create(4, 5, None, 6, 3)
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.sv_sampler_create(c, np.array([1, 1 << 20], np.uint64))
+    assert e.value.status == 2  # QSV_ERANGE
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.sv_sampler_create(c, np.array([], np.uint64))
+    assert e.value.status == 2
