@@ -916,6 +916,15 @@ qsv_status compile_source(const std::string &src, std::vector<char> &code, std::
 
 }  // namespace
 
+// Kernel name of pass p: the last pass of an inner-product or sampling
+// variant is named for what it does, so traces tell the kinds apart.
+std::string pass_name(const Plan &plan, int variant, size_t p) {
+    const bool last = p + 1 == plan.passes.size() && !(variant & kJitBatched);
+    const char *kind = (last && (variant & kJitDot)) ? "qsv_dot_" : (last && (variant & kJitSample)) ? "qsv_sample_"
+                                                                                                    : "qsv_pass_";
+    return kind + std::to_string(p);
+}
+
 std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int variant) {
     const int init_kind = (variant & 4) ? (variant & 3) : -1;
     const bool norm = (variant & 8) != 0;
@@ -929,7 +938,7 @@ std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int var
         bool uses_lds = false;
         const bool loop = jit_pass_loop(variant, p) && !batched;
         const bool last = p + 1 == plan.passes.size();
-        src += g.emit("qsv_pass_" + std::to_string(p), uses_lds, p == 0 ? init_kind : -1,
+        src += g.emit(pass_name(plan, variant, p), uses_lds, p == 0 ? init_kind : -1,
                       norm && !batched && last, plan.n, batched, loop, dot && !batched && last,
                       sample && !batched && last);
         if (lds_bytes) lds_bytes->push_back(uses_lds ? size_t(g.lds_elems) * (dp ? 16 : 8) : 0);
@@ -1005,7 +1014,7 @@ qsv_status jit_prepare(Plan &plan, int variant) {
     if (he != hipSuccess) return fail(QSV_EHIP, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(he));
     for (size_t p = 0; p < plan.passes.size(); ++p) {
         hipFunction_t f;
-        he = hipModuleGetFunction(&f, e->mod, ("qsv_pass_" + std::to_string(p)).c_str());
+        he = hipModuleGetFunction(&f, e->mod, pass_name(plan, variant, p).c_str());
         if (he != hipSuccess)
             return fail(QSV_EHIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(he));
         e->fns.push_back(f);
