@@ -174,6 +174,35 @@ qsv_status circuit_split(const qsv_circuit *c, uint64_t side_a_mask,
 qsv_status circuit_inverse(const qsv_circuit *c, qsv_circuit **out);
 
 /*
+ * Branch stages for prefix sharing among the branches of a split half (the
+ * CZ decomposition of Section 2, Fig. 2: every branch runs the same gates
+ * apart from the PB / ZB gates of its branch bits).
+ *
+ * The layers that hold PB / ZB gates, in ascending order, define levels
+ * 1..L: level k fixes the branch bits of the k-th such layer.  Every gate
+ * belongs to the deepest level among the branch bits it depends on through a
+ * chain of gates that share a qubit and do not commute (two diagonal gates
+ * commute), level 0 if it depends on none.
+ *
+ * circuit_branch_levels: *n_levels = L; level_bits[k] = mask of the branch
+ * bits fixed at level k + 1, for k < min(L, cap) (level_bits may be NULL when
+ * cap is 0).
+ *
+ * circuit_branch_stage: *out = new host-owned circuit (same n, depth and
+ * layer numbers) with the gates of levels [level_begin, level_end) in their
+ * original order; level_end = -1 means L + 1.  For any branch b and any
+ * 0 = l0 < l1 < ... < lk = L + 1, running the stages [l0, l1), ...,
+ * [l(k-1), lk) one after the other with branch b gives the same state as the
+ * whole circuit with branch b (a gate only moves ahead of gates of a deeper
+ * level, and only when the two commute).  A branch tree computes each stage
+ * once per value of the branch bits of the levels before its end: the gates
+ * of level 0 once, those of level 1 once per value of the level-1 bits, and
+ * so on.  Errors: QSV_EINVAL for an empty range or one outside [0, L + 1).
+ */
+qsv_status circuit_branch_levels(const qsv_circuit *c, int *n_levels, uint64_t *level_bits, size_t cap);
+qsv_status circuit_branch_stage(const qsv_circuit *c, int level_begin, int level_end, qsv_circuit **out);
+
+/*
  * sv_init - write a basis or uniform state into amps (device complex64[2^n]).
  *   kind 0 = |0...0>, 1 = |+>^n (every amplitude 2^{-n/2}, i.e. layer 0
  *   applied), 2 = |basis>.

@@ -197,6 +197,81 @@ extern "C" qsv_status circuit_split(const qsv_circuit *c, uint64_t side_a_mask,
     return QSV_OK;
 }
 
+// Branch levels of a circuit with PB / ZB gates (a circuit_split half).  The
+// layers holding PB / ZB gates, ascending, define levels 1..L; every gate gets
+// the deepest level among the branch bits it depends on through a chain of
+// gates that share a qubit and do not commute, 0 if none (two diagonal gates
+// commute, so only a non-diagonal gate on either side of a shared qubit links
+// them).  hot[q]: level that every later gate on q inherits (the deepest
+// non-diagonal gate on q so far); diag[q]: level that a later non-diagonal
+// gate on q inherits (the deepest diagonal gate on q so far).
+static void branch_levels(const qsv_circuit &c, std::vector<int> &lev, std::vector<int> &cut_layers,
+                          std::vector<uint64_t> &bits) {
+    cut_layers.clear();
+    for (const qsv_gate &g : c.gates)
+        if (g.kind == QSV_PB || g.kind == QSV_ZB) cut_layers.push_back(g.layer);
+    std::sort(cut_layers.begin(), cut_layers.end());
+    cut_layers.erase(std::unique(cut_layers.begin(), cut_layers.end()), cut_layers.end());
+    bits.assign(cut_layers.size(), 0);
+    std::vector<int> hot(size_t(c.n), 0), diag(size_t(c.n), 0);
+    lev.resize(c.gates.size());
+    for (size_t i = 0; i < c.gates.size(); ++i) {
+        const qsv_gate &g = c.gates[i];
+        const bool nd = !gate_is_diagonal(g.kind), two = g.kind == QSV_CZ;
+        int l = 0;
+        if (g.kind == QSV_PB || g.kind == QSV_ZB) {
+            l = 1 + int(std::lower_bound(cut_layers.begin(), cut_layers.end(), int(g.layer)) - cut_layers.begin());
+            bits[size_t(l - 1)] |= 1ull << g.arg;
+        }
+        l = std::max(l, hot[g.q0]);
+        if (two) l = std::max(l, hot[g.q1]);
+        if (nd) l = std::max(l, diag[g.q0]);
+        lev[i] = l;
+        if (nd) {
+            hot[g.q0] = l;
+        } else {
+            diag[g.q0] = std::max(diag[g.q0], l);
+            if (two) diag[g.q1] = std::max(diag[g.q1], l);
+        }
+    }
+}
+
+extern "C" qsv_status circuit_branch_levels(const qsv_circuit *c, int *n_levels, uint64_t *level_bits,
+                                            size_t cap) {
+    if (!c || !n_levels) return fail(QSV_EINVAL, "circuit_branch_levels: null argument");
+    if (cap && !level_bits) return fail(QSV_EINVAL, "circuit_branch_levels: level_bits is null but cap > 0");
+    std::vector<int> lev, layers;
+    std::vector<uint64_t> bits;
+    branch_levels(*c, lev, layers, bits);
+    *n_levels = int(layers.size());
+    for (size_t k = 0; k < bits.size() && k < cap; ++k) level_bits[k] = bits[k];
+    return QSV_OK;
+}
+
+// The gates of levels [level_begin, level_end) in their original order.  For
+// every branch, the stages [0, l1), [l1, l2), ..., [lk, L + 1) run one after
+// the other give the circuit's state: a gate moves ahead of another only if
+// its level is lower, and then the two commute (otherwise the later one
+// would have inherited the level).
+extern "C" qsv_status circuit_branch_stage(const qsv_circuit *c, int level_begin, int level_end,
+                                           qsv_circuit **out) {
+    if (!c || !out) return fail(QSV_EINVAL, "circuit_branch_stage: null argument");
+    std::vector<int> lev, layers;
+    std::vector<uint64_t> bits;
+    branch_levels(*c, lev, layers, bits);
+    const int top = int(layers.size()) + 1;
+    if (level_end < 0) level_end = top;
+    if (level_begin < 0 || level_end > top || level_begin >= level_end)
+        return fail(QSV_EINVAL, "circuit_branch_stage: level range outside [0, levels + 1)");
+    auto r = std::unique_ptr<qsv_circuit>(new qsv_circuit);
+    r->n = c->n;
+    r->depth = c->depth;
+    for (size_t i = 0; i < c->gates.size(); ++i)
+        if (lev[i] >= level_begin && lev[i] < level_end) r->gates.push_back(c->gates[i]);
+    *out = r.release();
+    return QSV_OK;
+}
+
 // Adjoint circuit: reversed order, each gate replaced by its adjoint (T <-> T^dagger,
 // X^1/2 <-> (X^1/2)^dagger, Y^1/2 <-> (Y^1/2)^dagger; H, CZ, Z, ZB self-adjoint; the
 // projectors P0, P1, PB are self-adjoint).  Layer numbers are mirrored so that

@@ -35,6 +35,7 @@ EXPORTS = ["circuit_create", "circuit_destroy", "circuit_info", "circuit_gates",
            "circuit_partition_offsets", "circuit_partition_parts", "circuit_partition_destroy",
            "sv_partition_workspace_bytes", "sv_partition_simulate", "sv_apply_fused_from",
            "sv_simulate_dot", "sv_sampler_create", "sv_sampler_run", "sv_sampler_destroy",
+           "circuit_branch_levels", "circuit_branch_stage",
            "qsv_last_error", "qsv_version"]
 
 
@@ -96,6 +97,8 @@ def lib():
         "sv_debug_jit_compile": (st, [vp, i32, i32, vp, P(sz), P(ctypes.c_double)]),
         "qsv_release_device_buffers": (st, []),
         "circuit_inverse": (st, [vp, P(vp)]),
+        "circuit_branch_levels": (st, [vp, P(i32), vp, sz]),
+        "circuit_branch_stage": (st, [vp, i32, i32, P(vp)]),
         "sv_inner_product": (st, [vp, vp, i32, vp, vp]),
         "sv_branch_combine_full": (st, [vp, vp, sz, i32, i32, u64, vp, vp, sz, vp, vp]),
         "sv_tune": (st, [vp, vp, i32, i32, vp, P(ctypes.c_double), vp]),
@@ -362,6 +365,20 @@ def sv_debug_jit_compile(c, layer_begin=0, layer_end=-1, opts=None):
 def circuit_inverse(c) -> Circuit:
     out = ctypes.c_void_p()
     _check(lib().circuit_inverse(c, ctypes.byref(out)))
+    return Circuit(out.value)
+
+
+def circuit_branch_levels(c) -> list:
+    """Branch-bit masks of levels 1..L (see qsv.h)."""
+    n = ctypes.c_int()
+    bits = np.zeros(64, np.uint64)
+    _check(lib().circuit_branch_levels(c, ctypes.byref(n), _ptr(bits), bits.size))
+    return [int(x) for x in bits[: n.value]]
+
+
+def circuit_branch_stage(c, level_begin, level_end=-1) -> Circuit:
+    out = ctypes.c_void_p()
+    _check(lib().circuit_branch_stage(c, level_begin, level_end, ctypes.byref(out)))
     return Circuit(out.value)
 
 

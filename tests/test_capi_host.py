@@ -520,3 +520,58 @@ def test_sampler_argument_checks():
     with pytest.raises(qsv.QsvError) as e:
         qsv.sv_sampler_create(c, np.array([], np.uint64))
     assert e.value.status == 2
+
+
+# --- branch stages (prefix sharing among the branches of a split half) -------
+
+STAGE_CASES = [(3, 4, 14, 21, 1, 0), (3, 4, 14, 21, 1, 1), (4, 4, 16, 5, 1, 0), (3, 5, 16, 9, 2, 1),
+               (4, 5, 12, 3, 2, 0)]
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed,after_col,side", STAGE_CASES)
+def test_branch_stages_reproduce_every_branch(rows, cols, depth, seed, after_col, side):
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    ha, hb, ceff, _ = qsv.circuit_split(c, workloads.column_cut_mask(rows, cols, after_col))
+    h = (ha, hb)[side]
+    n = h.n
+    full = h.gates()
+    levels = qsv.circuit_branch_levels(h)
+    L = len(levels)
+    assert L >= 2
+    # the level masks partition the branch bits; each level's PB / ZB gates sit in one layer
+    assert sum(levels) == (1 << ceff) - 1 and all(a & b == 0 for i, a in enumerate(levels)
+                                                  for b in levels[i + 1:])
+    stages = [qsv.circuit_branch_stage(h, k, k + 1).gates() for k in range(L + 1)]
+    assert sum(len(s) for s in stages) == len(full)
+    for k, s in enumerate(stages):
+        bb = [int(g["arg"]) for g in s if qsv.KIND_NAME[int(g["kind"])] in ("PB", "ZB")]
+        assert sum(1 << b for b in set(bb)) == (levels[k - 1] if k else 0)
+        # original order kept: s is a subsequence of the whole gate list
+        it = iter(full.tobytes()[i * full.itemsize:(i + 1) * full.itemsize] for i in range(len(full)))
+        assert all(any(x == y for y in it) for x in (s.tobytes()[i * s.itemsize:(i + 1) * s.itemsize]
+                                                       for i in range(len(s))))
+    # the stage order really moves gates (the check below is not vacuous)
+    assert np.concatenate(stages).tobytes() != full.tobytes()
+    groupings = [list(range(L + 2)), [0, 1, L + 1], [0, L, L + 1], [0, L + 1]]
+    rng = np.random.default_rng(seed)
+    for br in sorted({0, (1 << ceff) - 1} | {int(x) for x in rng.integers(0, 1 << ceff, 6)}):
+        want = sim.simulate(_branch_gates(full, br), n)
+        for grp in groupings:
+            gates = []
+            for a, b in zip(grp, grp[1:]):
+                gates += _branch_gates(qsv.circuit_branch_stage(h, a, b if b <= L else -1).gates(), br)
+            got = sim.simulate(gates, n)
+            assert np.max(np.abs(got - want)) < 1e-12, (br, grp)
+
+
+def test_branch_stages_without_branches_and_bad_ranges():
+    c = qsv.circuit_create(3, 3, None, 8, 4)
+    assert qsv.circuit_branch_levels(c) == []
+    assert qsv.circuit_branch_stage(c, 0, -1).gates().tobytes() == c.gates().tobytes()
+    ha, _, _, _ = qsv.circuit_split(qsv.circuit_create(3, 4, None, 14, 21),
+                                    workloads.column_cut_mask(3, 4, 1))
+    L = len(qsv.circuit_branch_levels(ha))
+    for lb, le in [(1, 1), (2, 1), (-1, 1), (0, L + 2)]:
+        with pytest.raises(qsv.QsvError) as e:
+            qsv.circuit_branch_stage(ha, lb, le)
+        assert e.value.status == 1

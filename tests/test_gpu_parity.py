@@ -1115,6 +1115,122 @@ def test_branch_tree_prefix_sharing(depth, col, oop):
     assert sorted(seen) == list(range(1 << ceff))
 
 
+def _stage_tree(half, ranges, bufs, leaf, opts=None, sampler=None):
+    """Branch tree over branch stages: stage ranges[0] from |+> once, then for
+    every value of each later range's branch bits its stage from the parent
+    state; the last range runs as the leaf (a full sweep, or the sampler)."""
+    levels = qsv.circuit_branch_levels(half)
+    L = len(levels)
+    stages = [qsv.circuit_branch_stage(half, a, b if b <= L else -1) for a, b in ranges]
+    bits = [[]] + [[b for b in range(64) if (sum(levels[k - 1] for k in range(a, e)) >> b) & 1]
+                   for a, e in ranges[1:]]
+    qsv.sv_simulate(bufs[0], stages[0], init_kind=qsv.INIT_PLUS, layer_begin=1, opts=opts)
+
+    def rec(t, parent, prefix):
+        for v in range(1 << len(bits[t])):
+            br = prefix
+            for i, b in enumerate(bits[t]):
+                br |= ((v >> i) & 1) << b
+            if t == len(ranges) - 1 and sampler is not None:
+                leaf(sampler(parent, br), br)
+                continue
+            qsv.sv_apply_fused_from(parent, bufs[t], stages[t], branch=br, opts=opts)
+            if t == len(ranges) - 1:
+                leaf(bufs[t], br)
+            else:
+                rec(t + 1, bufs[t], br)
+    if len(ranges) == 1:
+        leaf(bufs[0], 0)
+    else:
+        rec(1, bufs[0], 0)
+    return stages
+
+
+@pytest.mark.parametrize("depth,col,oop,merge", [(12, 2, 0, 0), (12, 2, 1, 1), (9, 3, 0, 1), (14, 1, 0, 0)])
+def test_branch_stage_tree(depth, col, oop, merge):
+    """All branch states of a cut 4x6 circuit's half from the tree over branch
+    stages (level by level, or with the deepest levels merged into the
+    leaves), each against its own full sweep; two against the oracle."""
+    _gpu()
+    rows, cols, seed = 4, 6, 77
+    n = rows * cols
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    mask = workloads.column_cut_mask(rows, cols, col)
+    ha, hb, ceff, folded = qsv.circuit_split(c, mask)
+    L = len(qsv.circuit_branch_levels(ha))
+    assert L >= 2
+    ranges = [(0, 1)] + [(k, k + 1) for k in range(1, L + 1)]
+    if merge:
+        ranges = [(0, 1), (1, L), (L, L + 1)] if L > 2 else [(0, 1), (1, L + 1)]
+    na = ha.n
+    opts = None if not oop else dict(out_of_place=1, jit=1)
+    bufs = [torch.empty(1 << na, dtype=torch.complex64, device=DEV) for _ in range(len(ranges))]
+    one = torch.empty(1 << na, dtype=torch.complex64, device=DEV)
+    seen = []
+    info = sim.split_circuit(OC.random_circuit(OC.Lattice(rows, cols), depth, seed), n,
+                             [q for q in range(n) if (mask >> q) & 1])
+
+    def leaf(st, br):
+        qsv.sv_simulate(one, ha, branch=br, init_kind=qsv.INIT_PLUS, layer_begin=1, opts=opts)
+        d = (st - one).abs().max().item()
+        assert d <= 1e-6, (br, d)
+        if len(seen) < 2:
+            l = tuple((br >> j) & 1 for j in range(ceff))
+            ga, _ = info["half"](l)
+            _check_full(st, sim.simulate(ga, na), na)
+        seen.append(br)
+    _stage_tree(ha, ranges, bufs, leaf, opts)
+    assert sorted(seen) == list(range(1 << ceff))
+
+
+def test_branch_stage_tree_sampled_leaves():
+    """The 15-qubit half of a cut 5x6 depth-16 circuit: the tree over branch
+    stages with the leaf stage run by the sampler, every branch's sampled
+    amplitudes against its own full sweep and against the oracle (four
+    branches)."""
+    _gpu()
+    rows, cols, depth, seed = 5, 6, 16, 0x5EED0004
+    n = rows * cols
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    mask = workloads.column_cut_mask(rows, cols, 2)
+    ha, hb, ceff, folded = qsv.circuit_split(c, mask)
+    L = len(qsv.circuit_branch_levels(ha))
+    assert L >= 2
+    ranges = [(0, 1)] + [(k, k + 1) for k in range(1, L - 1)] + [(L - 1, L + 1)]
+    na = ha.n
+    m = 300
+    xs = workloads.bitstrings(na, m, 99)
+    leaf_stage = qsv.circuit_branch_stage(ha, ranges[-1][0], -1)
+    smp = qsv.sv_sampler_create(leaf_stage, xs, layer_begin=0)
+    bufs = [torch.empty(1 << na, dtype=torch.complex64, device=DEV) for _ in range(len(ranges))]
+    work = torch.empty(1 << na, dtype=torch.complex64, device=DEV)
+    out = torch.empty(m, dtype=torch.complex64, device=DEV)
+    one = torch.empty(1 << na, dtype=torch.complex64, device=DEV)
+    got = torch.empty(m, dtype=torch.complex64, device=DEV)
+    xt = torch.from_numpy(xs.view(np.int64)).to(DEV)
+    info = sim.split_circuit(OC.random_circuit(OC.Lattice(rows, cols), depth, seed), n,
+                             [q for q in range(n) if (mask >> q) & 1])
+    seen = []
+
+    def run_leaf(parent, br):
+        qsv.sv_sampler_run(smp, parent, work, out, branch=br)
+        return out
+
+    def leaf(vals, br):
+        qsv.sv_simulate(one, ha, branch=br, init_kind=qsv.INIT_PLUS, layer_begin=1)
+        qsv.sv_amplitudes(one, na, xt, got)
+        d = (vals - got).abs().max().item()
+        assert d <= 1e-6, (br, d)
+        if len(seen) < 4:
+            l = tuple((br >> j) & 1 for j in range(ceff))
+            ref = sim.simulate(info["half"](l)[0], na)[xs.astype(np.int64)]
+            e = np.max(np.abs(vals.cpu().numpy() - ref))
+            assert e <= 1e-5, (br, e)
+        seen.append(br)
+    _stage_tree(ha, ranges, bufs, leaf, sampler=run_leaf)
+    assert sorted(seen) == list(range(1 << ceff))
+
+
 # --- Task-2 amplitude with the inner product in the last pass ------------------
 
 def _dot_amplitudes(c, n, xs, h, opts=None):
