@@ -328,12 +328,18 @@ qsv_status sv_apply_dense(void *amps, const qsv_circuit *c, uint64_t branch, int
  *   afterwards).  With the generic kernel the sweep is stored to work and
  *   gathered.  Asynchronous on stream; calls that overlap on one device
  *   share the library's second state buffer.
+ * sv_sampler_run_branches: sv_sampler_run for count branches of the same
+ *   src, one after the other on the stream (the sibling leaves of a branch
+ *   tree): branches = host uint64[count], out_dev = device
+ *   complex64[count * m], row i for branches[i].  Stops at the first error.
  */
 typedef struct qsv_sampler qsv_sampler;  /* opaque */
 qsv_status sv_sampler_create(const qsv_circuit *c, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
                              const uint64_t *bitstrings, size_t m, qsv_sampler **out);
 qsv_status sv_sampler_run(qsv_sampler *s, const void *src, void *work, uint64_t branch, void *out_dev,
                           void *stream);
+qsv_status sv_sampler_run_branches(qsv_sampler *s, const void *src, void *work, const uint64_t *branches,
+                                   size_t count, void *out_dev, void *stream);
 void sv_sampler_destroy(qsv_sampler *s);
 
 /*

@@ -605,6 +605,18 @@ qsv_status sv_sampler_run(qsv_sampler *S, const void *src, void *work, uint64_t 
                       static_cast<const SampleTab *>(S->d_mem), S->ntiles, out_dev);
 }
 
+qsv_status sv_sampler_run_branches(qsv_sampler *S, const void *src, void *work, const uint64_t *branches,
+                                   size_t count, void *out_dev, void *stream) {
+    if (!S || !out_dev || (count && !branches)) return fail(QSV_EINVAL, "sv_sampler_run_branches: null argument");
+    // every call below validates the same arguments; the first one reports
+    for (size_t i = 0; i < count; ++i) {
+        void *out = static_cast<char *>(out_dev) + i * S->m * sizeof(float2);
+        qsv_status st = sv_sampler_run(S, src, work, branches[i], out, stream);
+        if (st != QSV_OK) return st;
+    }
+    return QSV_OK;
+}
+
 void sv_sampler_destroy(qsv_sampler *S) { delete S; }
 
 qsv_status sv_amplitudes(const void *amps, int n_qubits, const uint64_t *bitstrings_dev, size_t m,

@@ -520,6 +520,11 @@ def test_sampler_argument_checks():
     with pytest.raises(qsv.QsvError) as e:
         qsv.sv_sampler_create(c, np.array([], np.uint64))
     assert e.value.status == 2
+    # the multi-branch run refuses a missing sampler, branch list or output on the host
+    br = np.array([0, 1], np.uint64)
+    assert qsv.lib().sv_sampler_run_branches(None, 256, 512, br.ctypes.data, 2, 1024, None) == 1
+    assert qsv.lib().sv_sampler_run_branches(None, 256, 512, None, 2, 1024, None) == 1
+    assert qsv.lib().sv_sampler_run_branches(None, 256, 512, br.ctypes.data, 2, None, None) == 1
 
 
 # --- branch stages (prefix sharing among the branches of a split half) -------

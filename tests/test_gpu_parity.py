@@ -1183,11 +1183,14 @@ def test_branch_stage_tree(depth, col, oop, merge):
     assert sorted(seen) == list(range(1 << ceff))
 
 
-def test_branch_stage_tree_sampled_leaves():
+@pytest.mark.parametrize("compiled", [0, 1])
+def test_branch_stage_tree_sampled_leaves(compiled):
     """The 15-qubit half of a cut 5x6 depth-16 circuit: the tree over branch
-    stages with the leaf stage run by the sampler, every branch's sampled
-    amplitudes against its own full sweep and against the oracle (four
-    branches)."""
+    stages with the leaf stage run by the sampler (generic kernel, or
+    compiled passes with the leaves on 2^10-amplitude tiles), every branch's
+    sampled amplitudes against its own full sweep and against the oracle
+    (four branches); the sibling leaves also in one call
+    (sv_sampler_run_branches), bit-exact against the single calls."""
     _gpu()
     rows, cols, depth, seed = 5, 6, 16, 0x5EED0004
     n = rows * cols
@@ -1201,7 +1204,11 @@ def test_branch_stage_tree_sampled_leaves():
     m = 300
     xs = workloads.bitstrings(na, m, 99)
     leaf_stage = qsv.circuit_branch_stage(ha, ranges[-1][0], -1)
-    smp = qsv.sv_sampler_create(leaf_stage, xs, layer_begin=0)
+    opts = dict(jit=1) if compiled else None
+    leaf_opts = dict(reg_qubits=4, thread_qubits=6, low_qubits=1, plain=0, jit=1) if compiled else None
+    if compiled:
+        assert qsv.sv_plan_info(leaf_stage, 0, -1, leaf_opts)["n_passes"] == 1
+    smp = qsv.sv_sampler_create(leaf_stage, xs, layer_begin=0, opts=leaf_opts)
     bufs = [torch.empty(1 << na, dtype=torch.complex64, device=DEV) for _ in range(len(ranges))]
     work = torch.empty(1 << na, dtype=torch.complex64, device=DEV)
     out = torch.empty(m, dtype=torch.complex64, device=DEV)
@@ -1225,10 +1232,23 @@ def test_branch_stage_tree_sampled_leaves():
             l = tuple((br >> j) & 1 for j in range(ceff))
             ref = sim.simulate(info["half"](l)[0], na)[xs.astype(np.int64)]
             e = np.max(np.abs(vals.cpu().numpy() - ref))
-            assert e <= 1e-5, (br, e)
+            assert e * 2 ** (na / 2) <= 2e-5, (br, e)  # scaled error
         seen.append(br)
-    _stage_tree(ha, ranges, bufs, leaf, sampler=run_leaf)
+    stages = _stage_tree(ha, ranges, bufs, leaf, opts=opts, sampler=run_leaf)
     assert sorted(seen) == list(range(1 << ceff))
+    # sibling leaves in one call: the same kernels, so the same bits
+    parent = bufs[-2]  # the last internal state the walk left: its children are the last group
+    L = len(qsv.circuit_branch_levels(ha))
+    lv = qsv.circuit_branch_levels(ha)
+    last_bits = [b for b in range(64) if (sum(lv[k - 1] for k in range(ranges[-1][0], L + 1)) >> b) & 1]
+    prefix = (1 << ceff) - 1 - sum(1 << b for b in last_bits)  # every earlier bit set: the walk's last group
+    brs = [prefix | sum(((v >> i) & 1) << b for i, b in enumerate(last_bits)) for v in range(1 << len(last_bits))]
+    many = torch.empty(len(brs) * m, dtype=torch.complex64, device=DEV)
+    qsv.sv_sampler_run_branches(smp, parent, work, many, brs)
+    for i, br in enumerate(brs):
+        qsv.sv_sampler_run(smp, parent, work, out, branch=br)
+        assert torch.equal(many[i * m:(i + 1) * m], out), br
+    assert len(stages) == len(ranges)
 
 
 # --- Task-2 amplitude with the inner product in the last pass ------------------
