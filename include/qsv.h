@@ -332,6 +332,13 @@ qsv_status sv_apply_dense(void *amps, const qsv_circuit *c, uint64_t branch, int
  *   src, one after the other on the stream (the sibling leaves of a branch
  *   tree): branches = host uint64[count], out_dev = device
  *   complex64[count * m], row i for branches[i].  Stops at the first error.
+ * sv_sampler_run_subtree: the 2^k sibling branches prefix | (bits of y
+ *   deposited on the k set bits of mask), y = 0 .. 2^k - 1, from the same
+ *   src: row y of out_dev (device complex64[2^k * m]) for the y-th.  When the
+ *   sweep is one compiled pass this is one launch whose grid holds a row of
+ *   workgroups per branch (the leaves of a branch tree at once); otherwise
+ *   one run per branch.  prefix & mask must be 0 (QSV_EINVAL); k <= 15
+ *   (QSV_ERANGE).
  */
 typedef struct qsv_sampler qsv_sampler;  /* opaque */
 qsv_status sv_sampler_create(const qsv_circuit *c, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
@@ -340,6 +347,8 @@ qsv_status sv_sampler_run(qsv_sampler *s, const void *src, void *work, uint64_t 
                           void *stream);
 qsv_status sv_sampler_run_branches(qsv_sampler *s, const void *src, void *work, const uint64_t *branches,
                                    size_t count, void *out_dev, void *stream);
+qsv_status sv_sampler_run_subtree(qsv_sampler *s, const void *src, void *work, uint64_t prefix, uint64_t mask,
+                                  void *out_dev, void *stream);
 void sv_sampler_destroy(qsv_sampler *s);
 
 /*

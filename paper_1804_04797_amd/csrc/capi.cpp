@@ -605,6 +605,49 @@ qsv_status sv_sampler_run(qsv_sampler *S, const void *src, void *work, uint64_t 
                       static_cast<const SampleTab *>(S->d_mem), S->ntiles, out_dev);
 }
 
+qsv_status sv_sampler_run_subtree(qsv_sampler *S, const void *src, void *work, uint64_t prefix, uint64_t mask,
+                                  void *out_dev, void *stream) {
+    if (!S || !out_dev) return fail(QSV_EINVAL, "sv_sampler_run_subtree: null argument");
+    if (prefix & mask) return fail(QSV_EINVAL, "sv_sampler_run_subtree: prefix and mask share bits");
+    const int k = __builtin_popcountll(mask);
+    if (k > 15) return fail(QSV_ERANGE, "sv_sampler_run_subtree: more than 15 branch bits");
+    const qsv_circuit *c = S->c;
+    qsv_status st = check_state(src, c->n);
+    if (st != QSV_OK) return st;
+    if ((st = check_state(work, c->n)) != QSV_OK) return st;
+    if (src == work) return fail(QSV_EINVAL, "sv_sampler_run_subtree: work must not be src");
+    if ((st = check_device()) != QSV_OK) return st;
+    const size_t rows = size_t(1) << k;
+    std::shared_ptr<Plan> plan;
+    void *scratch = nullptr;
+    if (S->compiled) {
+        const qsv_fuse_opts *opts = S->has_opts ? &S->opts : nullptr;
+        qsv_fuse_opts tuned;
+        const qsv_fuse_opts *eo = effective_opts(c, opts, S->lb, S->le, &tuned);
+        if ((st = get_fused_plan(c, S->lb, S->le, S->sh, oop_mode(c, eo, S->jm), false, plan, &scratch)) != QSV_OK)
+            return st;
+        if (plan != S->plan) return fail(QSV_EINTERNAL, "sv_sampler_run_subtree: the circuit's plan changed");
+    }
+    if (!S->compiled || plan->passes.size() != 1) {
+        // earlier passes are per branch: one run per row
+        for (size_t y = 0; y < rows; ++y) {
+            uint64_t br = prefix, msk = mask, yy = y;
+            while (msk) {
+                const uint64_t low = msk & (~msk + 1);
+                if (yy & 1) br |= low;
+                yy >>= 1;
+                msk ^= low;
+            }
+            void *out = static_cast<char *>(out_dev) + y * S->m * sizeof(float2);
+            if ((st = sv_sampler_run(S, src, work, br, out, stream)) != QSV_OK) return st;
+        }
+        return QSV_OK;
+    }
+    const int variant = kJitPlain | kJitSample | (S->jm & ~3);
+    return jit_launch(*plan, variant, work, scratch, prefix, mask, nullptr, static_cast<hipStream_t>(stream), nullptr,
+                      src, nullptr, static_cast<const SampleTab *>(S->d_mem), S->ntiles, out_dev, rows, S->m);
+}
+
 qsv_status sv_sampler_run_branches(qsv_sampler *S, const void *src, void *work, const uint64_t *branches,
                                    size_t count, void *out_dev, void *stream) {
     if (!S || !out_dev || (count && !branches)) return fail(QSV_EINVAL, "sv_sampler_run_branches: null argument");

@@ -442,6 +442,7 @@ struct Gen {
     };
     int lds_elems = 0;       // largest staging buffer of the pass (elements)
     bool persistent = false; // generating the persistent (prefetching) form
+    bool sample_rows = false; // sampling pass with one grid row per sibling branch
 
     uint32_t xweight(const XLayout &x, int q) const {
         if (q == x.skip) return 0;
@@ -692,7 +693,8 @@ struct Gen {
             o << "jj |= unsigned((x >> " << int(P.st_phys[q]) << ") & 1ull) << " << q << ";\n";
         o << "if (tt == t) {" << CT << " val = v[0];\nswitch (jj) {\n";
         for (int j = 1; j < N; ++j) o << "case " << j << "u: val = v[" << j << "]; break;\n";
-        o << "default: break;\n}\noutp[tab->slot[e]] = val;}\n}\n}\n";
+        o << "default: break;\n}\noutp[" << (sample_rows ? "tile0 * blockIdx.y + " : "")
+          << "tab->slot[e]] = val;}\n}\n}\n";
     }
     // FP64 <result|other> of the tile: the other state (the kernel's `a`) is
     // read at the addresses the store would write; conj(v) * w with exact
@@ -780,6 +782,7 @@ struct Gen {
                      int n = 0, bool batched = false, bool loop = false, bool dot = false,
                      bool sample = false) {
         if (sample) loop = false;  // one workgroup per listed tile
+        sample_rows = sample && init_kind < 0;
         uses_lds = false;
         persistent = loop;
         for (int pc = 0; pc < P.n_ops; ++pc) {
@@ -797,6 +800,16 @@ struct Gen {
             o << "const " << CT << "* srcp = a;\n";
             o << "const unsigned long long branch = en.branch, basis = 0ull;\n";
             o << "double* part = nullptr;\n";
+        } else if (sample_rows) {
+            // Sampling several sibling branches in one launch: row y = blockIdx.y
+            // samples branch branch0 | (the bits of y deposited on the set bits
+            // of `basis`) and writes its amplitudes at outp + y * tile0.
+            o << "(const " << CT << "* srcp, " << CT << "* a, unsigned long long branch0, unsigned long long tile0, "
+                 "unsigned long long basis, double* __restrict__ part, unsigned long long ntile) {\n";
+            o << "unsigned long long branch = branch0;\n"
+                 "{unsigned long long msk = basis, y = blockIdx.y;\n"
+                 "while (msk) {const unsigned long long low = msk & (~msk + 1ull);\n"
+                 "if (y & 1ull) branch |= low;\ny >>= 1;\nmsk ^= low;}}\n";
         } else {
             // srcp == a for passes that work in place
             o << "(const " << CT << "* srcp, " << CT << "* a, unsigned long long branch, unsigned long long tile0, "
@@ -1037,7 +1050,7 @@ qsv_status jit_prepare(Plan &plan, int variant) {
 qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, uint64_t branch,
                       uint64_t basis, double *part, hipStream_t s, std::vector<float> *pass_ms,
                       const void *src0, const void *dot_other, const SampleTab *sample_tab,
-                      uint64_t sample_tiles, void *sample_out) {
+                      uint64_t sample_tiles, void *sample_out, uint64_t sample_rows, uint64_t sample_stride) {
     auto vit = plan.jit_variants.find(variant);
     if (vit == plan.jit_variants.end()) return fail(QSV_EINTERNAL, "jit variant not prepared");
     const CacheEntry &e = *static_cast<const CacheEntry *>(vit->second.get());
@@ -1062,12 +1075,14 @@ qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, 
         if ((variant & kJitSample) && p + 1 == np) {
             // the listed tiles only; writes the listed amplitudes
             if (sample_tiles) {
-                unsigned long long br = branch, tt = 0, bs = basis, nt = sample_tiles;
+                // basis: bit mask of the sibling branches' own bits (0 for one
+                // branch); tt: the output row stride in amplitudes
+                unsigned long long br = branch, tt = sample_stride, bs = basis, nt = sample_tiles;
                 void *src = in, *dst = const_cast<SampleTab *>(sample_tab);
                 double *pt = static_cast<double *>(sample_out);
                 void *args[] = {&src, &dst, &br, &tt, &bs, &pt, &nt};
-                hipError_t he = hipModuleLaunchKernel(e.fns[p], unsigned(sample_tiles), 1, 1, 1u << plan.T, 1, 1,
-                                                      unsigned(e.lds[p]), s, args, nullptr);
+                hipError_t he = hipModuleLaunchKernel(e.fns[p], unsigned(sample_tiles), unsigned(sample_rows), 1,
+                                                      1u << plan.T, 1, 1, unsigned(e.lds[p]), s, args, nullptr);
                 if (he != hipSuccess)
                     return fail(QSV_EHIP, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(he));
             }

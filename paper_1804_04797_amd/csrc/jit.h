@@ -39,7 +39,11 @@ qsv_status jit_prepare(Plan &plan, int variant);
 // im of every tile) instead of storing the result.
 // kJitSample variants: the last pass runs sample_tiles workgroups over the
 // tile list of the device table sample_tab and writes the listed amplitudes
-// to sample_out (complex64) instead of storing the state.
+// to sample_out (complex64) instead of storing the state.  With sample_rows
+// > 1 its grid has that many rows of sibling branches: row y samples branch
+// `branch` with the bits of y deposited on the set bits of `basis`, and
+// writes at sample_out + y * sample_stride (the earlier passes, if any, run
+// for `branch` only, so callers use rows with one-pass plans).
 struct SampleTab {  // device layout read by the sampling pass
     const uint64_t *tiles;   // tile index of workgroup b
     const uint32_t *start;   // entries of workgroup b: [start[b], start[b + 1])
@@ -50,7 +54,8 @@ qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, 
                       uint64_t basis, double *part, hipStream_t s,
                       std::vector<float> *pass_ms = nullptr, const void *src0 = nullptr,
                       const void *dot_other = nullptr, const SampleTab *sample_tab = nullptr,
-                      uint64_t sample_tiles = 0, void *sample_out = nullptr);
+                      uint64_t sample_tiles = 0, void *sample_out = nullptr, uint64_t sample_rows = 1,
+                      uint64_t sample_stride = 0);
 // Launch all passes over `count` batch entries (BatchEntry table on the device).
 qsv_status jit_launch_batched(const Plan &plan, int variant, const void *ents, unsigned count,
                               hipStream_t s);

@@ -34,7 +34,7 @@ EXPORTS = ["circuit_create", "circuit_destroy", "circuit_info", "circuit_gates",
            "circuit_partition_plan", "circuit_partition_create", "circuit_partition_info",
            "circuit_partition_offsets", "circuit_partition_parts", "circuit_partition_destroy",
            "sv_partition_workspace_bytes", "sv_partition_simulate", "sv_apply_fused_from",
-           "sv_simulate_dot", "sv_sampler_create", "sv_sampler_run", "sv_sampler_destroy", "sv_sampler_run_branches",
+           "sv_simulate_dot", "sv_sampler_create", "sv_sampler_run", "sv_sampler_destroy", "sv_sampler_run_branches", "sv_sampler_run_subtree",
            "circuit_branch_levels", "circuit_branch_stage",
            "qsv_last_error", "qsv_version"]
 
@@ -85,6 +85,7 @@ def lib():
         "sv_sampler_run": (st, [vp, vp, vp, u64, vp, vp]),
         "sv_sampler_destroy": (None, [vp]),
         "sv_sampler_run_branches": (st, [vp, vp, vp, vp, sz, vp, vp]),
+        "sv_sampler_run_subtree": (st, [vp, vp, vp, u64, u64, vp, vp]),
         "sv_simulate": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, vp, sz, vp, i32, vp]),
         "sv_simulate_c128": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, sz, vp, vp]),
         "sv_amplitudes": (st, [vp, i32, vp, sz, vp, i32, vp]),
@@ -544,6 +545,11 @@ def sv_sampler_create(c, bitstrings, layer_begin=0, layer_end=-1, opts=None) -> 
 def sv_sampler_run(sampler, src, work, out, branch=0, stream=None):
     _check(lib().sv_sampler_run(sampler, _ptr(src), _ptr(work), ctypes.c_uint64(branch), _ptr(out),
                                 _stream(stream)))
+
+
+def sv_sampler_run_subtree(sampler, src, work, out, prefix, mask, stream=None):
+    _check(lib().sv_sampler_run_subtree(sampler, _ptr(src), _ptr(work), ctypes.c_uint64(prefix),
+                                        ctypes.c_uint64(mask), _ptr(out), _stream(stream)))
 
 
 def sv_sampler_run_branches(sampler, src, work, out, branches, stream=None):

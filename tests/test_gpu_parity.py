@@ -1190,7 +1190,8 @@ def test_branch_stage_tree_sampled_leaves(compiled):
     compiled passes with the leaves on 2^10-amplitude tiles), every branch's
     sampled amplitudes against its own full sweep and against the oracle
     (four branches); the sibling leaves also in one call
-    (sv_sampler_run_branches), bit-exact against the single calls."""
+    (sv_sampler_run_branches, sv_sampler_run_subtree), bit-exact against the
+    single calls."""
     _gpu()
     rows, cols, depth, seed = 5, 6, 16, 0x5EED0004
     n = rows * cols
@@ -1244,10 +1245,17 @@ def test_branch_stage_tree_sampled_leaves(compiled):
     prefix = (1 << ceff) - 1 - sum(1 << b for b in last_bits)  # every earlier bit set: the walk's last group
     brs = [prefix | sum(((v >> i) & 1) << b for i, b in enumerate(last_bits)) for v in range(1 << len(last_bits))]
     many = torch.empty(len(brs) * m, dtype=torch.complex64, device=DEV)
+    rows = torch.empty(len(brs) * m, dtype=torch.complex64, device=DEV)
     qsv.sv_sampler_run_branches(smp, parent, work, many, brs)
+    # the same siblings as one grid with a row per branch
+    qsv.sv_sampler_run_subtree(smp, parent, work, rows, prefix, sum(1 << b for b in last_bits))
     for i, br in enumerate(brs):
         qsv.sv_sampler_run(smp, parent, work, out, branch=br)
         assert torch.equal(many[i * m:(i + 1) * m], out), br
+        assert torch.equal(rows[i * m:(i + 1) * m], out), br
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.sv_sampler_run_subtree(smp, parent, work, rows, 1, 1)
+    assert e.value.status == 1
     assert len(stages) == len(ranges)
 
 
