@@ -132,6 +132,7 @@ struct Gen {
     std::ostringstream o;
     int m[64];            // pending rotation i^m of each register
     int h[64];            // pending factor 2^{-h/2} of each register
+    int w[64];            // pending factor e^{i pi/4} (1) or none (0) of each register
     bool sdirty[8];       // slot s carries the run-time sign sg<s>
     bool e_dirty = false; // e or the zero flag may differ from (0, alive)
     bool dp;              // complex128 state (validation instantiation)
@@ -139,7 +140,7 @@ struct Gen {
     std::string CT, RT, MK, CM, XS, QT, ZERO;
     Gen(const PassProg &p, int r, int t, bool double_precision = false)
         : P(p), R(r), T(t), N(1 << r), L(r + t), dp(double_precision) {
-        for (int j = 0; j < 64; ++j) m[j] = h[j] = 0;
+        for (int j = 0; j < 64; ++j) m[j] = h[j] = w[j] = 0;
         for (int s = 0; s < 8; ++s) sdirty[s] = false;
         CT = dp ? "double2" : "float2";
         RT = dp ? "double" : "float";
@@ -198,6 +199,13 @@ struct Gen {
     bool declared_sg[8] = {false, false, false, false, false, false, false, false};
 
     void butterfly(uint32_t code, int S) {
+        // a pending e^{i pi/4} common to both inputs of a pair stays pending
+        // on both outputs; on one input only it is applied first
+        for (int j = 0; j < N; ++j) {
+            if (j & (1 << S)) continue;
+            const int k = j | (1 << S);
+            if (w[j] != w[k]) omega_reg(w[j] ? j : k);
+        }
         // coefficient of Y relative to X per distinct h difference
         std::map<int, std::string> coef;
         for (int j = 0; j < N; ++j) {
@@ -234,23 +242,37 @@ struct Gen {
               << ";v[" << k << "]=" << sum(a1, b1, cf) << ";}\n";
             m[k] = m[j];
             h[k] = h[j];
+            w[k] = w[j];
         }
         sdirty[S] = false;  // absorbed
     }
     void rot_reg(int j, int k) { m[j] = (m[j] + k / 2) & 3; }
-    void omega_reg(int j) {  // multiply the stored value by (1 + i); w = (1 + i)/sqrt2
+    // apply the pending e^{i pi/4} = (1 + i)/sqrt2 of register j: the stored
+    // value times (1 + i), the 1/sqrt2 joins its power of two
+    void omega_reg(int j) {
         o << "v[" << j << "]=" << MK << "(v[" << j << "].x-v[" << j << "].y,v[" << j << "].x+v[" << j
           << "].y);\n";
         h[j] += 1;
+        w[j] = 0;
     }
+    // e^{i pi k/4}: the multiple of i/2 rotates, an odd k toggles the pending
+    // e^{i pi/4} (two of them are i), so T gates cost nothing until a
+    // butterfly pairs the register with one that lacks the factor
     void phase_reg(int j, int k) {
         k &= 7;
         rot_reg(j, k & 6);
-        if (k & 1) omega_reg(j);
+        if (k & 1) {
+            if (w[j]) {
+                w[j] = 0;
+                m[j] = (m[j] + 1) & 3;
+            } else {
+                w[j] = 1;
+            }
+        }
     }
     void zero_reg(int j) {
         o << "v[" << j << "]=" << MK << "(" << ZERO << "," << ZERO << ");\n";
-        m[j] = h[j] = 0;
+        m[j] = h[j] = w[j] = 0;
     }
 
     void op_phase(uint32_t loc, int k) {
@@ -357,9 +379,15 @@ struct Gen {
             // register j0 in the partial form
             const int j0 = partial ? (j & ~move_mask) : -1;
             const int dm = partial ? m[j] - m[j0] : m[j], dh = partial ? h[j] - h[j0] : h[j];
+            const int dw = partial ? w[j] - w[j0] : w[j];
             const double mag = std::pow(2.0, -0.5 * dh);
             double kr = sr * mag, ki = si * mag;
             for (int q = 0; q < (dm & 3); ++q) { double t2 = -ki; ki = kr; kr = t2; }
+            if (dw != 0) {  // times e^{+-i pi/4}
+                const double c = std::sqrt(0.5), r2 = kr, i2 = ki;
+                kr = c * (dw > 0 ? r2 - i2 : r2 + i2);
+                ki = c * (dw > 0 ? r2 + i2 : i2 - r2);
+            }
             const std::string sj = sign_of(j & dmask);
             if (!e_dirty) {
                 const bool real = (ki == 0.0), imag = (kr == 0.0);
@@ -392,11 +420,11 @@ struct Gen {
             }
         }
         if (partial) {
-            for (int j = 0; j < N; ++j) { m[j] = m[j & ~move_mask]; h[j] = h[j & ~move_mask]; }
+            for (int j = 0; j < N; ++j) { m[j] = m[j & ~move_mask]; h[j] = h[j & ~move_mask]; w[j] = w[j & ~move_mask]; }
             for (int s = 0; s < R; ++s) sdirty[s] = false;
             return;
         }
-        for (int j = 0; j < N; ++j) m[j] = h[j] = 0;
+        for (int j = 0; j < N; ++j) m[j] = h[j] = w[j] = 0;
         for (int s = 0; s < R; ++s) sdirty[s] = false;
         if (e_dirty) o << "e = 0u; alive = 1u;\n";
         e_dirty = false;
@@ -406,15 +434,17 @@ struct Gen {
     // materialize depend on staying register slots only; move them with
     // their slots.
     void rename_factors(const int *perm) {
-        int mo[64], ho[64];
+        int mo[64], ho[64], wo[64];
         std::copy(m, m + N, mo);
         std::copy(h, h + N, ho);
+        std::copy(w, w + N, wo);
         for (int jn = 0; jn < N; ++jn) {
             int jo = 0;  // old register index of the staying bits of jn
             for (int sn = 0; sn < R; ++sn)
                 if (((jn >> sn) & 1) && perm[sn] < R) jo |= 1 << perm[sn];
             m[jn] = mo[jo];
             h[jn] = ho[jo];
+            w[jn] = wo[jo];
         }
     }
 
