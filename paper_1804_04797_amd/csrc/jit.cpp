@@ -656,19 +656,79 @@ struct Gen {
         return r;
     }
     // Load this thread's 2^R amplitudes of the tile at `basev` into `dst`.
+    // Projections (OP_PROJ) that the program applies before its first
+    // exchange and, on a register slot, before any non-diagonal op on that
+    // slot: until then nothing mixes the amplitudes they zero with the
+    // others, so those amplitudes need not be loaded (zeros give the same
+    // result).  Each entry: locator, surviving bit value (expression).
+    std::vector<std::pair<uint32_t, std::string>> early_projections() const {
+        std::vector<std::pair<uint32_t, std::string>> out;
+        bool nd[kMaxSlots] = {};
+        for (int pc = 0; pc < P.n_ops; ++pc) {
+            const uint64_t op = P.ops[pc];
+            const uint32_t code = uint32_t(op & 0xff), a = uint32_t((op >> 8) & 0xff);
+            const uint32_t b = uint32_t((op >> 16) & 0xff), c = uint32_t((op >> 24) & 0xff);
+            if (code == OP_XCHG) break;
+            if (code == OP_H || code == OP_SX || code == OP_SY || code == OP_SXDG || code == OP_SYDG) {
+                if (a < uint32_t(kMaxSlots)) nd[a] = true;
+                continue;
+            }
+            if (code != OP_PROJ || (is_reg(a) && nd[a])) continue;
+            out.push_back({a, c ? "unsigned((branch >> " + std::to_string(b) + ") & 1ull)" : std::to_string(b) + "u"});
+        }
+        return out;
+    }
     void emit_load(const std::string &dst, const std::string &basev, const std::vector<int> &tld) {
+        // loads of amplitudes that an early projection zeroes are skipped:
+        // a per-thread condition (thread and tile-index bits) and, per load,
+        // the register bits
+        const auto proj = early_projections();
+        std::string ok;
+        std::vector<std::pair<int, std::string>> regp;  // (register slot, surviving value)
+        for (const auto &pr : proj) {
+            const uint32_t loc = pr.first;
+            if (is_reg(loc)) {
+                regp.push_back({int(loc), pr.second});
+            } else {
+                const std::string bit = is_glob(loc)
+                    ? "unsigned(((" + basev + ") >> " + std::to_string(loc & 0x7f) + ") & 1ull)"
+                    : "((t >> " + std::to_string(loc - R) + ") & 1u)";
+                ok += " && (" + bit + " == " + pr.second + ")";
+            }
+        }
+        const int lid = ok.empty() ? -1 : uid++;  // no new names otherwise
+        if (!ok.empty()) o << "const bool ldok" << lid << " = true" << ok << ";\n";
+        // condition of a load covering the registers of `mask` bits equal to those of j
+        auto cond = [&](int j, int s0) -> std::string {
+            std::string c = ok.empty() ? "" : "ldok" + std::to_string(lid);
+            for (const auto &rp : regp) {
+                if (rp.first < s0) continue;
+                c += std::string(c.empty() ? "" : " && ") + "(" + (((j >> rp.first) & 1) ? "1u" : "0u") + " == " +
+                     rp.second + ")";
+            }
+            return c;
+        };
         if (dp) {
             o << "{const v2d* src = (const v2d*)(srcp + (" << basev << " | " << scatter_expr("t", tld, true)
               << "));\n";
-            for (int j = 0; j < N; ++j)
+            for (int j = 0; j < N; ++j) {
+                const std::string c = cond(j, 0);
+                if (!c.empty()) o << "if (" << c << ") ";
                 o << "{const v2d w = __builtin_nontemporal_load(src + " << hex64(reg_offset(j, P.ld_phys, 0))
                   << ");" << dst << "[" << j << "]=D2(w.x,w.y);}\n";
+                if (!c.empty()) o << "else {" << dst << "[" << j << "]=D2(0.0,0.0);}\n";
+            }
         } else {
             o << "{const v4f* src = (const v4f*)(srcp + (" << basev << " | " << scatter_expr("t", tld, true)
               << "));\n";
-            for (int j = 0; j < N; j += 2)
+            for (int j = 0; j < N; j += 2) {
+                const std::string c = cond(j, 1);  // a load covers both values of slot 0
+                if (!c.empty()) o << "if (" << c << ") ";
                 o << "{const v4f w = __builtin_nontemporal_load(src + " << hex64(reg_offset(j, P.ld_phys, 1) / 2)
                   << ");" << dst << "[" << j << "]=F2(w.x,w.y);" << dst << "[" << j + 1 << "]=F2(w.z,w.w);}\n";
+                if (!c.empty())
+                    o << "else {" << dst << "[" << j << "]=F2(0.f,0.f);" << dst << "[" << j + 1 << "]=F2(0.f,0.f);}\n";
+            }
         }
         o << "}\n";
     }
