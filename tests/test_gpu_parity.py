@@ -957,6 +957,44 @@ def test_split_7x7_branches_full_size():
         _check_full(bst, ref, 21)
 
 
+def test_split_7x7_stage_tree_full_size():
+    """The 28-qubit half of the full-size 49-qubit split through the tree over
+    branch stages as the benchmark runs it: stage 0 from |+>, one level-1
+    stage pass from it (loads of projected amplitudes skipped), and the
+    merged leaf stage sampled on 2^10-amplitude tiles for all 128 siblings
+    in one launch.  Branches 0 and 1337 against stored oracle amplitudes."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("7x7-d16")
+    ha, hb, ceff, folded = qsv.circuit_split(c, workloads.column_cut_mask(7, 7, 3))
+    levels = qsv.circuit_branch_levels(ha)
+    assert len(levels) == 3
+    jit = dict(jit=1)
+    leaf_opts = dict(reg_qubits=4, thread_qubits=6, low_qubits=1, plain=0, jit=1)
+    root = qsv.circuit_branch_stage(ha, 0, 1)
+    lvl1 = qsv.circuit_branch_stage(ha, 1, 2)
+    leaf = qsv.circuit_branch_stage(ha, 2, -1)
+    assert qsv.sv_plan_info(lvl1, 0, -1)["n_passes"] == 1
+    assert qsv.sv_plan_info(leaf, 0, -1, leaf_opts)["n_passes"] == 1
+    s0 = torch.empty(1 << 28, dtype=torch.complex64, device=DEV)
+    s1 = torch.empty_like(s0)
+    work = torch.empty_like(s0)
+    qsv.sv_simulate(s0, root, init_kind=qsv.INIT_PLUS, layer_begin=1, opts=jit)
+    leaf_mask = levels[1] | levels[2]
+    leaf_bits = [b for b in range(64) if (leaf_mask >> b) & 1]
+    for br in (0, 1337):
+        xs, ref = _golden_branch("7x7-d16", br)
+        m = xs.size
+        smp = qsv.sv_sampler_create(leaf, xs, layer_begin=0, opts=leaf_opts)
+        prefix = br & levels[0]
+        qsv.sv_apply_fused_from(s0, s1, lvl1, branch=prefix, opts=jit)
+        out = torch.empty((1 << len(leaf_bits)) * m, dtype=torch.complex64, device=DEV)
+        qsv.sv_sampler_run_subtree(smp, s1, work, out, prefix, leaf_mask)
+        y = sum(((br >> b) & 1) << i for i, b in enumerate(leaf_bits))  # row of br
+        got = out[y * m:(y + 1) * m].cpu().numpy()
+        d = np.max(np.abs(got - ref))
+        assert d <= TOL and d * 2 ** 14 <= TOL_SCALED, (br, d)
+
+
 # --- three-part partition: branch sweeps, block combines, part C -------------
 
 def _partition_run(c, rows, cols, present, r0, max_move=2):
