@@ -87,7 +87,7 @@ typedef struct qsv_batch qsv_batch;      /* opaque */
  *                  per workgroup; 2 = the same kernels as persistent workgroups
  *                  that prefetch their next tile into registers while they
  *                  compute the current one; 3 = per pass: pass p persistent iff
- *                  bit p of pass_forms is set (p < 21); -1 = always use the
+ *                  bit p of pass_forms is set (p < 20); -1 = always use the
  *                  generic pass kernel; 0 = 1 for states of 2^24 amplitudes or
  *                  more, else -1 (the environment variable QSV_JIT=0 makes 0
  *                  mean -1 everywhere; QSV_JIT_DUMP=<file> writes the last
@@ -339,6 +339,18 @@ qsv_status sv_apply_dense(void *amps, const qsv_circuit *c, uint64_t branch, int
  *   workgroups per branch (the leaves of a branch tree at once); otherwise
  *   one run per branch.  prefix & mask must be 0 (QSV_EINVAL); k <= 15
  *   (QSV_ERANGE).
+ * sv_sampler_create_tiles: a sampler whose last pass computes the tiles that
+ *   hold the given indices and stores each of them whole: sv_sampler_run
+ *   then writes (U src) at every index of those tiles (a superset of the
+ *   given ones) into out_dev, a device complex64[2^n] that is neither src nor
+ *   work, and leaves the rest of out_dev untouched.  For the inner levels of
+ *   a branch tree whose leaves read only part of their parent.  Needs the
+ *   compiled pass kernels (QSV_EUNSUPPORTED otherwise); run_branches and
+ *   run_subtree refuse it (QSV_EINVAL).
+ * sv_sampler_inputs: for a sampler whose sweep is one compiled pass, the
+ *   indices of src its run reads (the amplitudes of the tiles it computes):
+ *   *count = their number, the first min(cap, *count) written to out (host
+ *   uint64).  QSV_EUNSUPPORTED when the run reads the whole state.
  */
 typedef struct qsv_sampler qsv_sampler;  /* opaque */
 qsv_status sv_sampler_create(const qsv_circuit *c, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
@@ -349,6 +361,10 @@ qsv_status sv_sampler_run_branches(qsv_sampler *s, const void *src, void *work, 
                                    size_t count, void *out_dev, void *stream);
 qsv_status sv_sampler_run_subtree(qsv_sampler *s, const void *src, void *work, uint64_t prefix, uint64_t mask,
                                   void *out_dev, void *stream);
+qsv_status sv_sampler_create_tiles(const qsv_circuit *c, int layer_begin, int layer_end,
+                                   const qsv_fuse_opts *opts, const uint64_t *indices, size_t m,
+                                   qsv_sampler **out);
+qsv_status sv_sampler_inputs(const qsv_sampler *s, uint64_t *out, size_t cap, size_t *count);
 void sv_sampler_destroy(qsv_sampler *s);
 
 /*

@@ -489,6 +489,8 @@ struct qsv_sampler {
     qsv_fuse_opts opts{};
     uint64_t m = 0, ntiles = 0;
     bool compiled = false;     // sampling pass kernels; else sweep + gather
+    bool tiles = false;        // the listed tiles are stored whole into a state
+    std::vector<uint64_t> h_tiles;  // tile indices of the last pass, host copy
     TileShape sh{};
     int jm = 0;
     std::shared_ptr<Plan> plan;
@@ -502,8 +504,8 @@ struct qsv_sampler {
 
 extern "C" {
 
-qsv_status sv_sampler_create(const qsv_circuit *c, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
-                             const uint64_t *bitstrings, size_t m, qsv_sampler **out) {
+static qsv_status sampler_create(const qsv_circuit *c, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
+                                 const uint64_t *bitstrings, size_t m, bool tiles, qsv_sampler **out) {
     if (!c || !out || (m && !bitstrings)) return fail(QSV_EINVAL, "sv_sampler_create: null argument");
     if (m == 0 || m > (size_t(1) << 32)) return fail(QSV_ERANGE, "sv_sampler_create: m out of range");
     if (layer_begin < 0) return fail(QSV_EINVAL, "sv_sampler_create: layer_begin < 0");
@@ -530,6 +532,9 @@ qsv_status sv_sampler_create(const qsv_circuit *c, int layer_begin, int layer_en
             return st;
         S->compiled = !S->plan->passes.empty();
     }
+    if (tiles && !S->compiled)
+        return fail(QSV_EUNSUPPORTED, "sv_sampler_create_tiles: needs compiled pass kernels (opts jit >= 1)");
+    S->tiles = tiles;
     if (S->compiled) {
         // entries sorted by the tile of the last pass that holds them
         const PassProg &L = S->plan->passes.back().prog;
@@ -552,6 +557,7 @@ qsv_status sv_sampler_create(const qsv_circuit *c, int layer_begin, int layer_en
         }
         start.push_back(uint32_t(m));
         S->ntiles = tiles.size();
+        S->h_tiles = tiles;
         const size_t off_t = 64, off_s = off_t + 8 * tiles.size(), off_x = (off_s + 4 * start.size() + 7) / 8 * 8,
                      off_l = off_x + 8 * m, bytes = off_l + 4 * m;
         if ((e = hipMalloc(&S->d_mem, bytes)) != hipSuccess) return hip_fail(e, "sv_sampler_create");
@@ -567,13 +573,46 @@ qsv_status sv_sampler_create(const qsv_circuit *c, int layer_begin, int layer_en
         if ((e = hipMemcpy(S->d_mem, h.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess)
             return hip_fail(e, "sv_sampler_create");
         std::lock_guard<std::mutex> g(S->plan->jit_mu);
-        if ((st = jit_prepare(*S->plan, kJitPlain | kJitSample | (S->jm & ~3))) != QSV_OK) return st;
+        if ((st = jit_prepare(*S->plan, kJitPlain | kJitSample | (S->tiles ? kJitTiles : 0) | (S->jm & ~3))) != QSV_OK)
+            return st;
     } else {
         if ((e = hipMalloc(&S->d_xs, 8 * m)) != hipSuccess) return hip_fail(e, "sv_sampler_create");
         if ((e = hipMemcpy(S->d_xs, bitstrings, 8 * m, hipMemcpyHostToDevice)) != hipSuccess)
             return hip_fail(e, "sv_sampler_create");
     }
     *out = S.release();
+    return QSV_OK;
+}
+
+qsv_status sv_sampler_create(const qsv_circuit *c, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
+                             const uint64_t *bitstrings, size_t m, qsv_sampler **out) {
+    return sampler_create(c, layer_begin, layer_end, opts, bitstrings, m, false, out);
+}
+
+qsv_status sv_sampler_create_tiles(const qsv_circuit *c, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
+                                   const uint64_t *indices, size_t m, qsv_sampler **out) {
+    return sampler_create(c, layer_begin, layer_end, opts, indices, m, true, out);
+}
+
+qsv_status sv_sampler_inputs(const qsv_sampler *S, uint64_t *out, size_t cap, size_t *count) {
+    if (!S || !count || (cap && !out)) return fail(QSV_EINVAL, "sv_sampler_inputs: null argument");
+    if (!S->compiled || S->plan->passes.size() != 1)
+        return fail(QSV_EUNSUPPORTED, "sv_sampler_inputs: the sweep has more than one pass (it reads the whole state)");
+    const PassProg &P = S->plan->passes[0].prog;
+    const int L = S->plan->R + S->plan->T;
+    const size_t per = size_t(1) << L;
+    *count = S->h_tiles.size() * per;
+    size_t k = 0;
+    for (uint64_t tile : S->h_tiles) {
+        uint64_t base = 0;
+        for (int i = 0; i < P.n_glob; ++i) base |= ((tile >> i) & 1ull) << P.glob_bits[i];
+        for (size_t l = 0; l < per && k < cap; ++l, ++k) {
+            uint64_t x = base;
+            for (int sl = 0; sl < L; ++sl)
+                if ((l >> sl) & 1) x |= 1ull << P.ld_phys[sl];
+            out[k] = x;
+        }
+    }
     return QSV_OK;
 }
 
@@ -600,7 +639,9 @@ qsv_status sv_sampler_run(qsv_sampler *S, const void *src, void *work, uint64_t 
     if ((st = get_fused_plan(c, S->lb, S->le, S->sh, oop_mode(c, eo, S->jm), false, plan, &scratch)) != QSV_OK)
         return st;
     if (plan != S->plan) return fail(QSV_EINTERNAL, "sv_sampler_run: the circuit's plan changed");
-    const int variant = kJitPlain | kJitSample | (S->jm & ~3);
+    if (S->tiles && (out_dev == src || (plan->passes.size() > 1 && out_dev == work)))
+        return fail(QSV_EINVAL, "sv_sampler_run: the tile state must be neither src nor work");
+    const int variant = kJitPlain | kJitSample | (S->tiles ? kJitTiles : 0) | (S->jm & ~3);
     return jit_launch(*plan, variant, work, scratch, branch, 0, nullptr, s, nullptr, src, nullptr,
                       static_cast<const SampleTab *>(S->d_mem), S->ntiles, out_dev);
 }
@@ -608,6 +649,7 @@ qsv_status sv_sampler_run(qsv_sampler *S, const void *src, void *work, uint64_t 
 qsv_status sv_sampler_run_subtree(qsv_sampler *S, const void *src, void *work, uint64_t prefix, uint64_t mask,
                                   void *out_dev, void *stream) {
     if (!S || !out_dev) return fail(QSV_EINVAL, "sv_sampler_run_subtree: null argument");
+    if (S->tiles) return fail(QSV_EINVAL, "sv_sampler_run_subtree: a tile sampler writes one state per run");
     if (prefix & mask) return fail(QSV_EINVAL, "sv_sampler_run_subtree: prefix and mask share bits");
     const int k = __builtin_popcountll(mask);
     if (k > 15) return fail(QSV_ERANGE, "sv_sampler_run_subtree: more than 15 branch bits");
@@ -651,6 +693,7 @@ qsv_status sv_sampler_run_subtree(qsv_sampler *S, const void *src, void *work, u
 qsv_status sv_sampler_run_branches(qsv_sampler *S, const void *src, void *work, const uint64_t *branches,
                                    size_t count, void *out_dev, void *stream) {
     if (!S || !out_dev || (count && !branches)) return fail(QSV_EINVAL, "sv_sampler_run_branches: null argument");
+    if (S->tiles) return fail(QSV_EINVAL, "sv_sampler_run_branches: a tile sampler writes one state per run");
     // every call below validates the same arguments; the first one reports
     for (size_t i = 0; i < count; ++i) {
         void *out = static_cast<char *>(out_dev) + i * S->m * sizeof(float2);

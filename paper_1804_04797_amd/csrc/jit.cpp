@@ -870,9 +870,10 @@ struct Gen {
     // set while it computes the current one.
     std::string emit(const std::string &name, bool &uses_lds, int init_kind = -1, bool norm = false,
                      int n = 0, bool batched = false, bool loop = false, bool dot = false,
-                     bool sample = false) {
+                     bool sample = false, bool tiles = false) {
         if (sample) loop = false;  // one workgroup per listed tile
-        sample_rows = sample && init_kind < 0;
+        tiles = tiles && sample;
+        sample_rows = sample && !tiles && init_kind < 0;
         uses_lds = false;
         persistent = loop;
         for (int pc = 0; pc < P.n_ops; ++pc) {
@@ -911,6 +912,10 @@ struct Gen {
             o << "const SampleTabJ* tab = (const SampleTabJ*)a;\n";
             o << "const unsigned long long tile = tab->tiles[blockIdx.x];\n";
             o << "const unsigned long long base = " << scatter_expr("tile", glob, true) << ";\n";
+            if (tiles) {  // the listed tiles go whole into the state at `part`
+                o << "a = (" << CT << "*)part;\n";
+                o << "const unsigned long long bst = " << scatter_expr("tile", globst, true) << ";\n";
+            }
             o << CT << " v[" << N << "];\n";
             if (init_kind >= 0) emit_init(init_kind, n, tld);
             else emit_load("v", "base", tld);
@@ -947,7 +952,7 @@ struct Gen {
         }
         o << "unsigned e = 0u, alive = 1u;\n(void)e; (void)alive;\n";
         emit_ops();
-        if (sample) {
+        if (sample && !tiles) {
             emit_sample();
         } else if (dot) {
             emit_dot(loop, tst);
@@ -1023,8 +1028,10 @@ qsv_status compile_source(const std::string &src, std::vector<char> &code, std::
 // variant is named for what it does, so traces tell the kinds apart.
 std::string pass_name(const Plan &plan, int variant, size_t p) {
     const bool last = p + 1 == plan.passes.size() && !(variant & kJitBatched);
-    const char *kind = (last && (variant & kJitDot)) ? "qsv_dot_" : (last && (variant & kJitSample)) ? "qsv_sample_"
-                                                                                                    : "qsv_pass_";
+    const char *kind = (last && (variant & kJitDot))      ? "qsv_dot_"
+                       : (last && (variant & kJitTiles))  ? "qsv_tiles_"
+                       : (last && (variant & kJitSample)) ? "qsv_sample_"
+                                                          : "qsv_pass_";
     return kind + std::to_string(p);
 }
 
@@ -1033,6 +1040,7 @@ std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int var
     const bool norm = (variant & 8) != 0;
     const bool dot = (variant & kJitDot) != 0;
     const bool sample = (variant & kJitSample) != 0;
+    const bool tiles = (variant & kJitTiles) != 0;
     const bool dp = (variant & kJitDouble) != 0;
     const bool batched = (variant & kJitBatched) != 0;
     std::string src = kPrelude;
@@ -1043,7 +1051,7 @@ std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int var
         const bool last = p + 1 == plan.passes.size();
         src += g.emit(pass_name(plan, variant, p), uses_lds, p == 0 ? init_kind : -1,
                       norm && !batched && last, plan.n, batched, loop, dot && !batched && last,
-                      sample && !batched && last);
+                      sample && !batched && last, tiles);
         if (lds_bytes) lds_bytes->push_back(uses_lds ? size_t(g.lds_elems) * (dp ? 16 : 8) : 0);
     }
     return src;

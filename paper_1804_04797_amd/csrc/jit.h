@@ -19,8 +19,9 @@ constexpr int kJitNorm = 8;
 constexpr int kJitDouble = 16;  // complex128 state (validation instantiation)
 constexpr int kJitBatched = 32; // state and branch per blockIdx.y from a batch entry table
 constexpr int kJitLoop = 64;    // persistent workgroups, next tile prefetched into registers
-constexpr int kJitPerPass = 128; // pass p persistent iff bit (8 + p) of the variant (p < 21)
-constexpr int kJitPassBits = 21;
+constexpr int kJitPerPass = 128; // pass p persistent iff bit (8 + p) of the variant (p < 20)
+constexpr int kJitPassBits = 20;
+constexpr int kJitTiles = 1 << 28;  // with kJitSample: the listed tiles are stored whole instead
 constexpr int kJitSample = 1 << 29; // the last pass runs only listed tiles and writes listed amplitudes
 constexpr int kJitDot = 1 << 30; // the last pass stores nothing: FP64 <result|other> partials per tile
 inline bool jit_pass_loop(int variant, size_t p) {
@@ -37,6 +38,8 @@ qsv_status jit_prepare(Plan &plan, int variant);
 // kJitDot variants: the last pass reads dot_other at its store addresses and
 // writes the FP64 partials of <result|other> to part (re of every tile, then
 // im of every tile) instead of storing the result.
+// kJitSample | kJitTiles: the last pass runs the listed tiles and stores each
+// of them whole into sample_out (a state) instead of writing amplitudes.
 // kJitSample variants: the last pass runs sample_tiles workgroups over the
 // tile list of the device table sample_tab and writes the listed amplitudes
 // to sample_out (complex64) instead of storing the state.  With sample_rows

@@ -35,6 +35,7 @@ EXPORTS = ["circuit_create", "circuit_destroy", "circuit_info", "circuit_gates",
            "circuit_partition_offsets", "circuit_partition_parts", "circuit_partition_destroy",
            "sv_partition_workspace_bytes", "sv_partition_simulate", "sv_apply_fused_from",
            "sv_simulate_dot", "sv_sampler_create", "sv_sampler_run", "sv_sampler_destroy", "sv_sampler_run_branches", "sv_sampler_run_subtree",
+           "sv_sampler_create_tiles", "sv_sampler_inputs",
            "circuit_branch_levels", "circuit_branch_stage",
            "qsv_last_error", "qsv_version"]
 
@@ -86,6 +87,8 @@ def lib():
         "sv_sampler_destroy": (None, [vp]),
         "sv_sampler_run_branches": (st, [vp, vp, vp, vp, sz, vp, vp]),
         "sv_sampler_run_subtree": (st, [vp, vp, vp, u64, u64, vp, vp]),
+        "sv_sampler_create_tiles": (st, [vp, i32, i32, vp, vp, sz, P(vp)]),
+        "sv_sampler_inputs": (st, [vp, vp, sz, P(sz)]),
         "sv_simulate": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, vp, sz, vp, i32, vp]),
         "sv_simulate_c128": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, sz, vp, vp]),
         "sv_amplitudes": (st, [vp, i32, vp, sz, vp, i32, vp]),
@@ -540,6 +543,23 @@ def sv_sampler_create(c, bitstrings, layer_begin=0, layer_end=-1, opts=None) -> 
     _check(lib().sv_sampler_create(c, layer_begin, layer_end, _opts(opts), _ptr(xs), xs.size,
                                    ctypes.byref(out)))
     return Sampler(out.value, c, xs.size)
+
+
+def sv_sampler_create_tiles(c, indices, layer_begin=0, layer_end=-1, opts=None) -> Sampler:
+    xs = np.ascontiguousarray(np.asarray(indices, dtype=np.uint64))
+    out = ctypes.c_void_p()
+    _check(lib().sv_sampler_create_tiles(c, layer_begin, layer_end, _opts(opts), _ptr(xs), xs.size,
+                                         ctypes.byref(out)))
+    return Sampler(out.value, c, xs.size)
+
+
+def sv_sampler_inputs(sampler) -> np.ndarray:
+    """Indices of src that a one-pass sampler reads (see qsv.h)."""
+    cnt = ctypes.c_size_t()
+    _check(lib().sv_sampler_inputs(sampler, None, 0, ctypes.byref(cnt)))
+    out = np.empty(cnt.value, np.uint64)
+    _check(lib().sv_sampler_inputs(sampler, _ptr(out), out.size, ctypes.byref(cnt)))
+    return out
 
 
 def sv_sampler_run(sampler, src, work, out, branch=0, stream=None):

@@ -959,10 +959,11 @@ def test_split_7x7_branches_full_size():
 
 def test_split_7x7_stage_tree_full_size():
     """The 28-qubit half of the full-size 49-qubit split through the tree over
-    branch stages as the benchmark runs it: stage 0 from |+>, one level-1
-    stage pass from it (loads of projected amplitudes skipped), and the
-    merged leaf stage sampled on 2^10-amplitude tiles for all 128 siblings
-    in one launch.  Branches 0 and 1337 against stored oracle amplitudes."""
+    branch stages as the benchmark runs it: stage 0 from |+>, the level-1
+    stage only at the tiles its leaves read (tile sampler; loads of projected
+    amplitudes skipped), and the merged leaf stage sampled on 2^10-amplitude
+    tiles for all 128 siblings in one launch.  Branches 0 and 1337 against
+    stored oracle amplitudes."""
     _gpu()
     spec, c, lat = _lattice_circuit("7x7-d16")
     ha, hb, ceff, folded = qsv.circuit_split(c, workloads.column_cut_mask(7, 7, 3))
@@ -981,12 +982,21 @@ def test_split_7x7_stage_tree_full_size():
     qsv.sv_simulate(s0, root, init_kind=qsv.INIT_PLUS, layer_begin=1, opts=jit)
     leaf_mask = levels[1] | levels[2]
     leaf_bits = [b for b in range(64) if (leaf_mask >> b) & 1]
+    full = torch.empty_like(s0)
     for br in (0, 1337):
         xs, ref = _golden_branch("7x7-d16", br)
         m = xs.size
         smp = qsv.sv_sampler_create(leaf, xs, layer_begin=0, opts=leaf_opts)
         prefix = br & levels[0]
-        qsv.sv_apply_fused_from(s0, s1, lvl1, branch=prefix, opts=jit)
+        # the level-1 state only at the tiles the leaves read (tile sampler),
+        # bit-identical there to the whole level-1 sweep
+        need = qsv.sv_sampler_inputs(smp)
+        assert need.size < (1 << 28) // 16
+        tsmp = qsv.sv_sampler_create_tiles(lvl1, need, layer_begin=0, opts=jit)
+        qsv.sv_sampler_run(tsmp, s0, work, s1, branch=prefix)
+        qsv.sv_apply_fused_from(s0, full, lvl1, branch=prefix, opts=jit)
+        ni = torch.from_numpy(need.view(np.int64)).to(DEV)
+        assert torch.equal(s1[ni], full[ni])
         out = torch.empty((1 << len(leaf_bits)) * m, dtype=torch.complex64, device=DEV)
         qsv.sv_sampler_run_subtree(smp, s1, work, out, prefix, leaf_mask)
         y = sum(((br >> b) & 1) << i for i, b in enumerate(leaf_bits))  # row of br
@@ -1219,6 +1229,54 @@ def test_branch_stage_tree(depth, col, oop, merge):
         seen.append(br)
     _stage_tree(ha, ranges, bufs, leaf, opts)
     assert sorted(seen) == list(range(1 << ceff))
+
+
+@pytest.mark.parametrize("rows,cols,depth,lb,oop", [(4, 6, 12, 6, 0), (4, 6, 12, 9, 1), (5, 5, 14, 8, 1),
+                                                     (4, 6, 12, 12, 0), (5, 5, 14, 13, 1)])
+def test_tile_sampler_matches_full_sweep(rows, cols, depth, lb, oop):
+    """A tile sampler writes the sweep's result at every requested index
+    (bit-identical to the full sweep) and otherwise either leaves the target
+    untouched or writes the sweep's own values.  For one-pass sweeps,
+    sv_sampler_inputs covers what a run reads: a source that holds NaN
+    everywhere else gives the same sampled amplitudes."""
+    _gpu()
+    n = rows * cols
+    c = qsv.circuit_create(rows, cols, None, depth, 19)
+    opts = dict(jit=1, out_of_place=1 if oop else 0)
+    src = torch.empty(1 << n, dtype=torch.complex64, device=DEV)
+    qsv.sv_simulate(src, c, init_kind=qsv.INIT_PLUS, layer_begin=1, layer_end=lb, opts=opts)
+    full = torch.empty_like(src)
+    qsv.sv_apply_fused_from(src, full, c, layer_begin=lb, opts=opts)
+    xs = workloads.bitstrings(n, 300, 7)
+    tsmp = qsv.sv_sampler_create_tiles(c, xs, layer_begin=lb, opts=opts)
+    work = torch.empty_like(src)
+    out = torch.full_like(src, complex(7.0, -7.0))
+    qsv.sv_sampler_run(tsmp, src, work, out, branch=0)
+    xi = torch.from_numpy(xs.view(np.int64)).to(DEV)
+    assert torch.equal(out[xi], full[xi])
+    sentinel = out == complex(7.0, -7.0)
+    assert torch.equal(out[~sentinel], full[~sentinel])
+    assert int((~sentinel).sum()) < (1 << n)  # only some tiles were computed
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.sv_sampler_run(tsmp, src, work, src, branch=0)  # the target must not be src
+    assert e.value.status == 1
+    if qsv.sv_plan_info(c, lb, -1, opts)["n_passes"] == 1:
+        smp = qsv.sv_sampler_create(c, xs, layer_begin=lb, opts=opts)
+        need = qsv.sv_sampler_inputs(smp)
+        assert 0 < need.size < (1 << n) and np.unique(need).size == need.size
+        o1 = torch.empty(xs.size, dtype=torch.complex64, device=DEV)
+        o2 = torch.empty_like(o1)
+        qsv.sv_sampler_run(smp, src, work, o1)
+        dirty = torch.full_like(src, complex(float("nan"), float("nan")))
+        ni = torch.from_numpy(need.view(np.int64)).to(DEV)
+        dirty[ni] = src[ni]
+        qsv.sv_sampler_run(smp, dirty, work, o2)
+        assert torch.equal(o1, o2)
+        assert torch.equal(o1, full[xi])
+    else:
+        with pytest.raises(qsv.QsvError) as e:
+            qsv.sv_sampler_inputs(qsv.sv_sampler_create(c, xs, layer_begin=lb, opts=opts))
+        assert e.value.status == 5
 
 
 @pytest.mark.parametrize("compiled", [0, 1])
