@@ -97,7 +97,18 @@ qsv_status build_tables(qsv_batch *b, int lb) {
             // states of the HBM-streaming class get their own compiled
             // kernels with the single-state default tile shape
             TileShape sh{b->R, b->T, b->c};
-            if (big_state(b, c->n)) sh = default_shape(c->n);
+            if (big_state(b, c->n)) {
+                sh = default_shape(c->n);
+                // the autotuned shape of this circuit (sv_tune / sv_tune_set), if any
+                qsv_fuse_opts t;
+                if (tuned_opts(c, lb, -1, &t) && t.reg_qubits > 0 && t.thread_qubits > 0 &&
+                    fused_shape_supported(t.reg_qubits, t.thread_qubits) &&
+                    t.reg_qubits + t.thread_qubits <= c->n) {
+                    sh.R = t.reg_qubits;
+                    sh.T = t.thread_qubits;
+                    sh.c = t.low_qubits > 0 ? t.low_qubits : std::min(5, sh.T + 1);
+                }
+            }
             PlanKey key{lb, -1, sh.R, sh.T, sh.c, false};
             std::shared_ptr<Plan> p;
             {

@@ -36,7 +36,7 @@ EXPORTS = ["circuit_create", "circuit_destroy", "circuit_info", "circuit_gates",
            "sv_partition_workspace_bytes", "sv_partition_simulate", "sv_apply_fused_from",
            "sv_simulate_dot", "sv_sampler_create", "sv_sampler_run", "sv_sampler_destroy", "sv_sampler_run_branches", "sv_sampler_run_subtree",
            "sv_sampler_create_tiles", "sv_sampler_inputs",
-           "circuit_branch_levels", "circuit_branch_stage",
+           "circuit_branch_levels", "circuit_branch_stage", "sv_tune_set",
            "qsv_last_error", "qsv_version"]
 
 
@@ -103,6 +103,7 @@ def lib():
         "qsv_release_device_buffers": (st, []),
         "circuit_inverse": (st, [vp, P(vp)]),
         "circuit_branch_levels": (st, [vp, P(i32), vp, sz]),
+        "sv_tune_set": (st, [vp, i32, i32, vp]),
         "circuit_branch_stage": (st, [vp, i32, i32, P(vp)]),
         "sv_inner_product": (st, [vp, vp, i32, vp, vp]),
         "sv_branch_combine_full": (st, [vp, vp, sz, i32, i32, u64, vp, vp, sz, vp, vp]),
@@ -371,6 +372,10 @@ def circuit_inverse(c) -> Circuit:
     out = ctypes.c_void_p()
     _check(lib().circuit_inverse(c, ctypes.byref(out)))
     return Circuit(out.value)
+
+
+def sv_tune_set(c, opts, layer_begin=0, layer_end=-1):
+    _check(lib().sv_tune_set(c, layer_begin, layer_end, _opts(opts)))
 
 
 def circuit_branch_levels(c) -> list:

@@ -580,3 +580,18 @@ def test_branch_stages_without_branches_and_bad_ranges():
         with pytest.raises(qsv.QsvError) as e:
             qsv.circuit_branch_stage(ha, lb, le)
         assert e.value.status == 1
+
+
+def test_tune_set_applies_to_plans():
+    """sv_tune_set makes later calls without options plan with the given
+    shape; it is keyed by circuit content and layer range; null arguments are
+    refused."""
+    c = qsv.circuit_create(5, 6, None, 20, 0x7E57)  # a circuit no other test tunes
+    o = dict(reg_qubits=5, thread_qubits=9, low_qubits=5, plain=0, jit=1)
+    want = qsv.sv_plan_info(c, 1, -1, o)["resident"]
+    qsv.sv_tune_set(c, o, layer_begin=1)
+    assert qsv.sv_plan_info(c, 1, -1)["resident"] == want
+    same = qsv.circuit_create(5, 6, None, 20, 0x7E57)  # same content
+    assert qsv.sv_plan_info(same, 1, -1)["resident"] == want
+    assert qsv.lib().sv_tune_set(None, 0, -1, None) == 1
+

@@ -607,6 +607,33 @@ def test_batch_size_classes():
         _check_full(st, ref, n)
 
 
+@pytest.mark.parametrize("shape", [(5, 9, 5), (4, 8, 4), (6, 8, 4)])
+def test_batch_tuned_shape_for_large_states(shape):
+    """States of the HBM-streaming class take the tile shape tuned for their
+    circuit (here set with sv_tune_set, as a size-class autotune does):
+    every state against the oracle, and the plan the batch uses has that
+    shape's pass count."""
+    _gpu()
+    items = []
+    for i, (n, d) in enumerate([(23, 8), (14, 9), (24, 7)]):
+        rows, cols, pres = workloads.lattice_for_qubits(n)
+        seed = 0x7A5E + i
+        items.append((qsv.circuit_create(rows, cols, pres, d, seed),
+                      OC.random_circuit(OC.Lattice.for_qubits(n), d, seed), n))
+    o = dict(reg_qubits=shape[0], thread_qubits=shape[1], low_qubits=shape[2], plain=0, jit=1)
+    for c, _, n in items:
+        if n >= 23:
+            qsv.sv_tune_set(c, o, layer_begin=1)
+            assert qsv.sv_plan_info(c, 1, -1)["n_passes"] == qsv.sv_plan_info(c, 1, -1, o)["n_passes"]
+    b = qsv.sv_batch_create([c for c, _, _ in items])
+    states = [torch.empty(1 << n, dtype=torch.complex64, device=DEV) for _, _, n in items]
+    qsv.sv_batch_run(b, states, init_plus=True)
+    torch.cuda.synchronize()
+    for st, (_, gates, n) in zip(states, items):
+        ref = sim.run(np.full(1 << n, 2.0 ** (-n / 2), np.complex128), n, [g for g in gates if g[3] >= 1])
+        _check_full(st, ref, n)
+
+
 @pytest.mark.parametrize("jit", [0, 1])
 @pytest.mark.parametrize("init_plus", [False, True])
 def test_batch_uneven_circuits(init_plus, jit):
