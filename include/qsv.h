@@ -462,7 +462,7 @@ qsv_status sv_tune(void *amps_scratch, const qsv_circuit *c, int layer_begin, in
  * sv_tune_set - remember opts as the tuned options of c and the layer range,
  * as if sv_tune had picked them (host only).  A batch tunes one circuit per
  * size class with sv_tune and hands the choice to the others of the class;
- * sv_batch_create gives states of 2^23 amplitudes or more the tile shape
+ * sv_batch_create gives states of 2^21 amplitudes or more the tile shape
  * tuned for their circuit (the default shape otherwise).
  */
 qsv_status sv_tune_set(const qsv_circuit *c, int layer_begin, int layer_end, const qsv_fuse_opts *opts);

@@ -76,11 +76,12 @@ void drop_graph(qsv_batch *b) {
     b->exec = nullptr;
 }
 
-// Size classes: states of 2^23 amplitudes or more stream from HBM and are
+// Size classes: states of 2^21 amplitudes or more stream from HBM (or the
+// last-level cache) and are
 // swept by compiled kernels of their own plan (unless jit = -1); smaller ones
 // share the batch's tile shape and the generic kernel (or compiled kernels per
 // plan shared by >= 8 entries).
-constexpr int kBigState = 23;
+constexpr int kBigState = 21;
 bool big_state(const qsv_batch *b, int n) { return b->jit_mode >= 0 && n >= kBigState; }
 
 // Plans and device tables for layers [lb, end) of every entry.
