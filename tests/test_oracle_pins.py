@@ -228,6 +228,55 @@ def test_gate_identities():
         assert np.allclose(u.conj().T @ u, np.eye(2), atol=1e-15)
 
 
+# X^1/2 and Y^1/2 (Section 2, the gate set of the random circuits) are the
+# principal square roots: X and Y have eigenvalues +1 and -1, and the
+# principal root maps them to +1 and +i.  The matrices below are built from
+# numpy's eigendecomposition of X and Y, independently of the oracle's
+# literal constants; the adjoints SXDG/SYDG are their conjugate transposes.
+# Both the oracle's matrices and its simulator path are compared, the latter
+# column by column from |0> and |1> = H Z H |0>.
+_PAULI = {"SX": np.array([[0, 1], [1, 0]], np.complex128),
+          "SY": np.array([[0, -1j], [1j, 0]], np.complex128)}
+
+
+def _principal_root(p):
+    lam, vec = np.linalg.eigh(p)
+    root = np.array([1.0 if l > 0 else 1j for l in lam.real])
+    return vec @ np.diag(root) @ vec.conj().T
+
+
+def _root_deviation():
+    worst = 0.0
+    for nm, p in _PAULI.items():
+        want = _principal_root(p)
+        assert np.allclose(want @ want, p, atol=1e-14)
+        for name, w in ((nm, want), (nm + "DG", want.conj().T)):
+            got = np.array(C.gate_matrix(name), np.complex128)
+            worst = max(worst, float(np.max(np.abs(got - w))))
+            for col, prep in ((0, []), (1, [("H", 0, -1, 0), ("Z", 0, -1, 0), ("H", 0, -1, 0)])):
+                psi = sim.simulate(prep + [(name, 0, -1, 0)], 1)
+                worst = max(worst, float(np.max(np.abs(psi - w[:, col]))))
+    return worst
+
+
+def test_sqrt_gates_are_principal_roots():
+    assert _root_deviation() < 1e-14
+    # eigenvalues {1, +i}: the adjoint roots have {1, -i} and are the wrong choice
+    for nm in ("SX", "SY"):
+        ev = sorted(np.linalg.eigvals(np.array(C.gate_matrix(nm), np.complex128)), key=lambda z: z.imag)
+        assert np.allclose(ev, [1, 1j], atol=1e-14)
+
+
+@pytest.mark.parametrize("swap", [("SX", "SXDG"), ("SY", "SYDG")])
+def test_sqrt_root_pin_detects_adjoint_swap(monkeypatch, swap):
+    # A planted mistake in the oracle (a root replaced by its adjoint, which
+    # also squares to the Pauli matrix and is unitary) must fail the pin.
+    table = {swap[0]: swap[1], swap[1]: swap[0]}
+    mats = {nm: C.gate_matrix(nm) for nm in ("H", "T", "TDG", "Z", "P0", "P1", "SX", "SY", "SXDG", "SYDG")}
+    monkeypatch.setattr(C, "gate_matrix", lambda name: mats[table.get(name, name)])
+    assert _root_deviation() > 0.5
+
+
 @pytest.mark.parametrize("n", [1, 7, 16])
 def test_layer0_uniform(n):
     psi = sim.simulate([("H", q, -1, 0) for q in range(n)], n)
