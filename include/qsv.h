@@ -93,14 +93,14 @@ typedef struct qsv_batch qsv_batch;      /* opaque */
  *                  mean -1 everywhere; QSV_JIT_DUMP=<file> writes the last
  *                  generated source there, a debugging aid)
  *   out_of_place   compiled kernels only.  1 = every pass reads one buffer and
- *                  writes the other (the caller's state and a second state
- *                  buffer the library allocates once per device and keeps), so
+ *                  writes the other (the caller's state and the second state
+ *                  buffer in the call's workspace, see sv_workspace_bytes), so
  *                  that each pass can write the state with the next pass's
  *                  qubits at the lowest address bits; the result is always in
- *                  the caller's buffer.  -1 = in place.  0 = out of place for
- *                  2^24 amplitudes or more when the second buffer fits.  Calls
- *                  that overlap on one device share the second buffer: run
- *                  them with -1.
+ *                  the caller's buffer; QSV_EINVAL if the workspace cannot hold
+ *                  the second buffer.  -1 = in place.  0 = out of place for
+ *                  2^24 amplitudes or more when the workspace holds the second
+ *                  buffer, else in place.
  *   pass_forms     see jit = 3.
  */
 typedef struct {
@@ -211,6 +211,22 @@ enum { QSV_INIT_ZERO = 0, QSV_INIT_PLUS = 1, QSV_INIT_BASIS = 2 };
 qsv_status sv_init(void *amps, int n_qubits, int kind, uint64_t basis, void *stream);
 
 /*
+ * sv_workspace_bytes - size of the caller-owned workspace that the sweep
+ * calls below (sv_apply_fused, sv_apply_fused_from, sv_simulate,
+ * sv_simulate_dot, sv_simulate_c128, the sampler runs and sv_tune) use for
+ * layers [layer_begin, layer_end) of c with these options (NULL = the tuned
+ * or default ones).  It holds the second state buffer of out-of-place passes
+ * (8 * 2^n bytes, when the options choose them) and the FP64 partial sums of
+ * the norm and inner-product reductions (16 bytes per tile of the smallest
+ * tile the tuner considers, at least 1 MiB), so a workspace sized before
+ * sv_tune also fits the tuned shape.  Host only.  The library keeps no
+ * pointer to a workspace past the call that receives it; two calls in flight
+ * at once need two workspaces.
+ */
+qsv_status sv_workspace_bytes(const qsv_circuit *c, int layer_begin, int layer_end,
+                              const qsv_fuse_opts *opts, size_t *bytes);
+
+/*
  * sv_apply_fused - apply the gates of layers [layer_begin, layer_end) of the
  * circuit to amps in place (device complex64[2^n], n = the circuit's qubit
  * count).  layer_end < 0 means "to the end".  branch selects P_l / Z^l of the
@@ -224,10 +240,14 @@ qsv_status sv_init(void *amps, int n_qubits, int kind, uint64_t basis, void *str
  * Plans are built on the host on first use and cached in the circuit.
  * Asynchronous on stream; the state is exact (up to FP32 rounding) after the
  * last pass of the call, so calls over consecutive layer ranges compose.
+ * workspace: caller-owned device memory of ws_bytes bytes (see
+ * sv_workspace_bytes) or NULL; without room for the second state buffer the
+ * passes run in place.  No device memory is allocated or freed by the call
+ * (the first call of a plan compiles and loads its kernels).
  */
 qsv_status sv_apply_fused(void *amps, const qsv_circuit *c, uint64_t branch,
                           int layer_begin, int layer_end, const qsv_fuse_opts *opts,
-                          void *stream);
+                          void *workspace, size_t ws_bytes, void *stream);
 
 /*
  * sv_simulate - the whole sweep of one circuit in one call: initial state,
@@ -238,11 +258,16 @@ qsv_status sv_apply_fused(void *amps, const qsv_circuit *c, uint64_t branch,
  * back, and the last pass accumulates the FP64 norm of the tiles it stores,
  * saving two full-state sweeps.  norm_out_dev (device double[1]) may be NULL;
  * with m = 0 nothing is gathered.  opts->plain selects the unfused path.
+ * The init kinds are those of sv_init (Section 2: the opening Hadamard
+ * layer makes |+>^n from |0>).  workspace / ws_bytes as for
+ * sv_apply_fused; the norm needs it (its partial sums live there:
+ * QSV_EINVAL without a workspace of sv_workspace_bytes bytes).
  */
 qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int init_kind,
                        uint64_t basis, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
                        double *norm_out_dev, const uint64_t *bitstrings_dev, size_t m,
-                       void *amps_out_dev, int out_c128, void *stream);
+                       void *amps_out_dev, int out_c128, void *workspace, size_t ws_bytes,
+                       void *stream);
 
 /*
  * sv_simulate_dot - <U |init> | other> in FP64 without storing U |init>:
@@ -255,24 +280,28 @@ qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int in
  * forward half.  amps: work buffer for the passes before the last
  * (complex64[2^n], contents unspecified afterwards); other: device
  * complex64[2^n], not written; out_dev: device double[2] = (re, im).  With
- * the generic kernel the result is stored to amps and sv_inner_product
- * follows.  Asynchronous on stream.
+ * the generic kernel the result is stored to amps and the inner product
+ * follows.  workspace (required: the FP64 partial sums live there) and
+ * ws_bytes as for sv_simulate.  Asynchronous on stream.
  */
 qsv_status sv_simulate_dot(void *amps, const qsv_circuit *c, uint64_t branch, int init_kind,
                            uint64_t basis, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
-                           const void *other, double *out_dev, void *stream);
+                           const void *other, double *out_dev, void *workspace, size_t ws_bytes,
+                           void *stream);
 
 /*
  * sv_simulate_c128 - the same sweep on a complex128 state (device
  * complex128[2^n], 16 bytes per amplitude): the compiled pass kernels
  * instantiated in FP64.  A precision reference for the complex64 path, not a
- * fast path; tile shape fixed at 4 register x 8 thread qubits.  Output
- * amplitudes are complex128[m]; norm_out_dev may be NULL.  Needs 12 <= n <= 34.
+ * fast path; tile shape fixed at 4 register x 8 thread qubits, in place.
+ * Output amplitudes are complex128[m]; norm_out_dev may be NULL (else the
+ * norm's partial sums go to workspace, as for sv_simulate).  Needs
+ * 12 <= n <= 34.
  */
 qsv_status sv_simulate_c128(void *amps, const qsv_circuit *c, uint64_t branch, int init_kind,
                             uint64_t basis, int layer_begin, int layer_end, double *norm_out_dev,
                             const uint64_t *bitstrings_dev, size_t m, void *amps_out_dev,
-                            void *stream);
+                            void *workspace, size_t ws_bytes, void *stream);
 
 /*
  * sv_apply_fused_from - dst = U(layers [layer_begin, layer_end), branch) src
@@ -283,10 +312,12 @@ qsv_status sv_simulate_c128(void *amps, const qsv_circuit *c, uint64_t branch, i
  * layer is computed once and each child continues from it.  src, dst:
  * device complex64[2^n], 16-byte aligned, must not overlap (src == dst runs
  * in place).  With the generic kernel (jit = -1) or the per-gate path, src
- * is copied to dst first.  Asynchronous on stream.
+ * is copied to dst first.  workspace / ws_bytes as for sv_apply_fused.
+ * Asynchronous on stream.
  */
 qsv_status sv_apply_fused_from(const void *src, void *dst, const qsv_circuit *c, uint64_t branch,
-                               int layer_begin, int layer_end, const qsv_fuse_opts *opts, void *stream);
+                               int layer_begin, int layer_end, const qsv_fuse_opts *opts,
+                               void *workspace, size_t ws_bytes, void *stream);
 
 /*
  * sv_apply_plain - the unfused comparator: one full-state (or, for diagonal
@@ -326,8 +357,10 @@ qsv_status sv_apply_dense(void *amps, const qsv_circuit *c, uint64_t branch, int
  *   src: device complex64[2^n], not written; work: another device
  *   complex64[2^n] for the passes before the last (contents unspecified
  *   afterwards).  With the generic kernel the sweep is stored to work and
- *   gathered.  Asynchronous on stream; calls that overlap on one device
- *   share the library's second state buffer.
+ *   gathered.  The sampler's plan is fixed when it is created: when it runs
+ *   out of place (the options choose it, see sv_workspace_bytes) every run
+ *   needs a workspace that holds the second state buffer (QSV_EINVAL
+ *   otherwise).  Asynchronous on stream.
  * sv_sampler_run_branches: sv_sampler_run for count branches of the same
  *   src, one after the other on the stream (the sibling leaves of a branch
  *   tree): branches = host uint64[count], out_dev = device
@@ -356,11 +389,12 @@ typedef struct qsv_sampler qsv_sampler;  /* opaque */
 qsv_status sv_sampler_create(const qsv_circuit *c, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
                              const uint64_t *bitstrings, size_t m, qsv_sampler **out);
 qsv_status sv_sampler_run(qsv_sampler *s, const void *src, void *work, uint64_t branch, void *out_dev,
-                          void *stream);
+                          void *workspace, size_t ws_bytes, void *stream);
 qsv_status sv_sampler_run_branches(qsv_sampler *s, const void *src, void *work, const uint64_t *branches,
-                                   size_t count, void *out_dev, void *stream);
+                                   size_t count, void *out_dev, void *workspace, size_t ws_bytes,
+                                   void *stream);
 qsv_status sv_sampler_run_subtree(qsv_sampler *s, const void *src, void *work, uint64_t prefix, uint64_t mask,
-                                  void *out_dev, void *stream);
+                                  void *out_dev, void *workspace, size_t ws_bytes, void *stream);
 qsv_status sv_sampler_create_tiles(const qsv_circuit *c, int layer_begin, int layer_end,
                                    const qsv_fuse_opts *opts, const uint64_t *indices, size_t m,
                                    qsv_sampler **out);
@@ -378,9 +412,22 @@ qsv_status sv_amplitudes(const void *amps, int n_qubits, const uint64_t *bitstri
                          size_t m, void *out_dev, int out_c128, void *stream);
 
 /*
+ * sv_stream_copy - dst = src for `bytes` bytes of device memory (a multiple
+ * of 16; both buffers 16-byte aligned and disjoint) with the access pattern
+ * of the fused passes: 16-byte nontemporal loads and stores, several in
+ * flight per thread.  The HBM rate of a pass without arithmetic, the
+ * ceiling the sweep's rate is compared with (one read and one write per
+ * amplitude, like one pass).  Asynchronous on stream.
+ */
+qsv_status sv_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+
+/*
  * sv_norm_fp64 - sum of |alpha_i|^2 over the state with every product and
- * partial sum in FP64 and a fixed-order pairwise tree (deterministic).
- * out_dev: device double[1].
+ * partial sum in FP64 and a fixed-order pairwise tree (deterministic): the
+ * norm check of the sweep (a unitary circuit keeps it at 1).  out_dev:
+ * device double[1].  The partial sums go to a 1 MiB buffer that the library
+ * allocates for each device and stream on its first such call (freed by
+ * qsv_release_device_buffers); calls on different streams never share one.
  */
 qsv_status sv_norm_fp64(const void *amps, int n_qubits, double *out_dev, void *stream);
 
@@ -408,8 +455,13 @@ qsv_status sv_branch_combine(const void *a_tab, const void *b_tab, size_t n_bran
 /*
  * sv_branch_combine_full - the complete state of a cut circuit (Fig. 2,
  * eq. (1), eqs. (6)-(7)): out[x] = s(x) * sum_b A_b[x_A] B_b[x_B] for all
- * 2^(n_a + n_b) indices x, a complex GEMM on FP32 matrix cores (FP32
- * accumulation).  a_states: complex64 [n_branches][2^n_a] (branch-major),
+ * 2^(n_a + n_b) indices x, a complex GEMM on matrix cores.  flags = 0: the
+ * complex64 inputs are widened to FP64 and every product and sum is FP64
+ * (v_mfma_f64_16x16x4f64), the result rounded once to a complex64 out_state;
+ * QSV_COMBINE_OUT_C128: out_state is complex128 (no rounding);
+ * QSV_COMBINE_FP32: FP32 products and accumulation on FP32 matrix cores
+ * (twice the rate, FP32 rounding in the sums).  a_states: complex64
+ * [n_branches][2^n_a] (branch-major),
  * local qubit i of side A = i-th set bit of side_a_mask; b_states likewise
  * for the other n_b qubits (as circuit_split numbers them).  folded_a /
  * folded_b: the folded pairs of circuit_split (global qubit numbers, side A
@@ -417,20 +469,36 @@ qsv_status sv_branch_combine(const void *a_tab, const void *b_tab, size_t n_bran
  * natural order.  Limits: 7 <= n_a, 7 <= n_b <= 22, n_a + n_b <= 34, at most
  * 64 folded pairs.  All buffers are caller-owned device memory.
  */
+enum { QSV_COMBINE_OUT_C128 = 1, QSV_COMBINE_FP32 = 2 };
 qsv_status sv_branch_combine_full(const void *a_states, const void *b_states, size_t n_branches,
                                   int n_a, int n_b, uint64_t side_a_mask, const int32_t *folded_a,
-                                  const int32_t *folded_b, size_t n_folded, void *out_state,
+                                  const int32_t *folded_b, size_t n_folded, void *out_state, int flags,
                                   void *stream);
 
 /*
  * Batched execution: many states (branches of split halves, or independent
- * circuits of uneven size) swept by ONE persistent kernel launch, replayed
- * from a captured hipGraph.
+ * circuits of uneven size) swept together, replayed from a captured hipGraph
+ * (Section 3: Stage 1 runs many independent sub-circuit sweeps; Fig. 2: the
+ * branches of a cut circuit).
+ *
+ * Size classes.  States of at most 2^14 amplitudes run on a tile that holds
+ * the whole state (the whole circuit in one workgroup, in registers and LDS);
+ * states below 2^21 amplitudes on the batch's tile shape; both with the
+ * generic pass kernel, one launch per tile shape and pass round.  States of
+ * 2^21 amplitudes or more run compiled kernels of their own plan on the tile
+ * shape tuned for their class (sv_tune / sv_tune_set).  A persistent form
+ * (one launch per tile shape whose workgroups take work items (pass round,
+ * entry, tile) in order from a device counter, per-entry counters of
+ * completed tiles ordering each entry's passes) is switched off in this
+ * version: QSV_BATCH_PERSISTENT=1 makes sv_batch_create return
+ * QSV_EUNSUPPORTED.
  *
  * sv_batch_create: count entries; entry i runs circuit circs[i] with branch
  * index branch_ids[i] (NULL = all 0) on its own state.  Plans per circuit
- * are built (and tuned) here.  The circuits must stay alive until
- * sv_batch_destroy.
+ * are built here.  opts may force one tile shape for every generic entry
+ * ((5,9), (5,8), (5,7), (4,8) or (4,7)) and the compiled-kernel mode (jit).
+ * The circuits must stay alive until sv_batch_destroy.  States need >= 11
+ * qubits.
  * sv_batch_run: amps_dev[i] is entry i's device state (complex64[2^n_i]),
  * already initialised by the caller (or pass init_plus = 1 to have the
  * launch start every state from |+>^n itself).  After the sweep, when
@@ -438,26 +506,44 @@ qsv_status sv_branch_combine_full(const void *a_states, const void *b_states, si
  * local numbering of entry i) are written to amp_table_dev[i*m + k] (device
  * complex64).  The first call captures a graph for these pointers; later
  * calls with the same pointers replay it.  Asynchronous on stream.
+ * sv_batch_status: synchronises stream and reports QSV_EINTERNAL if a wait of
+ * a persistent launch gave up since the last status call (its bounded spin
+ * ran out, or sv_batch_abort was called): the results of that run are then
+ * unspecified.  Clears the abort request.
+ * sv_batch_abort: asks the waits of the batch's launches in flight to give up
+ * (host only; a pinned flag they poll), so every launch drains promptly.
  */
 qsv_status sv_batch_create(const qsv_circuit *const *circs, const uint64_t *branch_ids,
                            size_t count, const qsv_fuse_opts *opts, qsv_batch **out);
 qsv_status sv_batch_run(qsv_batch *b, void *const *amps_dev, int init_plus,
                         const uint64_t *bitstrings_dev, size_t m, void *amp_table_dev,
                         void *stream);
+qsv_status sv_batch_status(qsv_batch *b, void *stream);
+qsv_status sv_batch_abort(qsv_batch *b);
 void sv_batch_destroy(qsv_batch *b);
 
 /*
  * sv_tune - autotune the fused sweep of layers [layer_begin, layer_end) of c.
  * Candidate tile shapes (register qubits, thread qubits, always-resident low
  * qubits) are planned; those within one pass of the fewest passes are timed
- * on the device with sv_apply_fused on amps_scratch (device complex64[2^n],
- * contents destroyed) and the fastest is written to *out (and its median time
- * in ms to *best_ms, may be NULL).  The choice is remembered for this circuit
- * content and layer range: later sv_apply_fused / sv_simulate calls with
- * opts == NULL use it.  Synchronises the stream.
+ * on the device on amps_scratch (device complex64[2^n], contents destroyed)
+ * with the workspace given (out-of-place forms are considered only when it
+ * holds a second state buffer; see sv_workspace_bytes) and the fastest is
+ * written to *out (and its median time in ms to *best_ms, may be NULL).
+ * States above 2^30 amplitudes are timed on the first 2^30 amplitudes' worth
+ * of tiles of every pass.  The choice is remembered for this circuit content
+ * and layer range: later calls with opts == NULL use it.  This is the
+ * scheduling preprocessing of Section 2.4 done by measurement.  Synchronises
+ * the stream.  With the environment variable QSV_TUNE_CACHE=<file> the
+ * choice is also appended to that file (keyed by a hash of the qubit count,
+ * layer range, gate list and device) and a later process takes it from
+ * there without timing; QSV_JIT_CACHE=<directory> likewise keeps the
+ * compiled pass kernels' code objects (keyed by a hash of their source and
+ * compiler options) so a later process loads them instead of compiling.
  */
 qsv_status sv_tune(void *amps_scratch, const qsv_circuit *c, int layer_begin, int layer_end,
-                   qsv_fuse_opts *out, double *best_ms, void *stream);
+                   void *workspace, size_t ws_bytes, qsv_fuse_opts *out, double *best_ms,
+                   void *stream);
 /*
  * sv_tune_set - remember opts as the tuned options of c and the layer range,
  * as if sv_tune had picked them (host only).  A batch tunes one circuit per
@@ -488,6 +574,21 @@ qsv_status sv_plan_info(const qsv_circuit *c, int layer_begin, int layer_end,
  */
 qsv_status sv_debug_emulate(void *amps_host, const qsv_circuit *c, uint64_t branch,
                             int layer_begin, int layer_end, const qsv_fuse_opts *opts);
+
+/*
+ * sv_debug_batch_schedule - host emulation of the work-item schedule of a
+ * persistent batch launch (a CPU check of its ordering rule; no product entry
+ * point calls it): count entries of n_qubits[i] qubits and passes[i] passes on
+ * tiles of 2^tile_qubits amplitudes, `workers` virtual workgroups taking the
+ * items in order, completions in a seeded random order.  QSV_OK if every
+ * (entry, pass, tile) runs exactly once, none starts before every tile of its
+ * entry's earlier passes has completed, and nothing stalls; QSV_EINTERNAL
+ * otherwise.  *items_out (may be NULL) = the launch's work items.
+ * planted_early_start != 0 lets an item start one completed tile early (a
+ * planted mistake that the check must catch).
+ */
+qsv_status sv_debug_batch_schedule(const int *n_qubits, const int *passes, size_t count, int tile_qubits,
+                                   int workers, uint64_t seed, int planted_early_start, uint64_t *items_out);
 
 /*
  * sv_debug_emulate_dense - apply the dense blocks of sv_apply_dense on the
@@ -575,8 +676,9 @@ void circuit_partition_destroy(qsv_partition *p);
  *      into workspace: one batch (sv_batch_*) for the parts of 11 or more
  *      qubits, one sv_simulate call per branch for a smaller part;
  *   2. psi_in = s(x) sum_e phi_{e,u(x)}[x_A] xi_{e,w(x)}[x_B] (e = shared
- *      branch bits, u / w = the selector qubits' values) as complex GEMMs on
- *      FP32 matrix cores, one per value of the selector qubits;
+ *      branch bits, u / w = the selector qubits' values) as complex GEMMs
+ *      with FP64 products and sums on matrix cores, one per value of the
+ *      selector qubits, rounded once to complex64;
  *   3. the gates of part C with sv_apply_fused on out_state.
  * workspace: device memory of sv_partition_workspace_bytes bytes (A's branch
  * states, then B's), caller-owned; the partition keeps the batch it built for
@@ -593,11 +695,9 @@ qsv_status sv_partition_simulate(qsv_partition *p, void *workspace, size_t ws_by
 
 /*
  * qsv_release_device_buffers - free the device memory the library keeps on
- * the current device between calls: the second state buffer of out-of-place
- * sweeps (8 * 2^n bytes, allocated at the first such sweep) and the FP64
- * partial sums of the norm.  Synchronises the device first.  Later calls
- * allocate again as needed.  For callers that need the memory back (e.g.
- * before allocating a larger state).
+ * the current device between calls: the FP64 partial-sum buffers of
+ * sv_norm_fp64 and sv_inner_product (1 MiB per stream that called them).
+ * Synchronises the device first.  Later calls allocate again as needed.
  */
 qsv_status qsv_release_device_buffers(void);
 

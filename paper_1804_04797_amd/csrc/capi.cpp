@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 
@@ -29,8 +30,10 @@ qsv_status hip_fail(hipError_t e, const char *where) {
     return fail(QSV_EHIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+}  // namespace
+
 // gfx950 check, cached per device ordinal.
-qsv_status check_device() {
+qsv_status check_gfx950() {
     static std::mutex mu;
     static int state[64] = {0};  // 0 unknown, 1 ok, 2 unsupported
     int dev = 0;
@@ -48,35 +51,34 @@ qsv_status check_device() {
     return QSV_OK;
 }
 
-// FP64 partial-sum buffer of the norm reductions, one per device, grown on
-// demand and kept for the life of the process.
-std::mutex g_part_mu;
-double *g_part[64] = {nullptr};
-size_t g_part_cap[64] = {0};
+namespace {
 
-qsv_status norm_partials(size_t count, double **out) {
-    std::mutex &mu = g_part_mu;
-    double **buf = g_part;
-    size_t *cap = g_part_cap;
+qsv_status check_device() { return check_gfx950(); }
+
+// FP64 partial sums of the standalone reductions (sv_norm_fp64,
+// sv_inner_product): one fixed buffer of 2 * 65536 doubles per device and
+// stream, allocated by the first such call on that stream and never regrown,
+// so calls on different streams never share one and nothing is freed while
+// queued work may read it.  qsv_release_device_buffers frees them.
+constexpr size_t kStreamPartials = 2 * 65536;
+std::mutex g_part_mu;
+std::map<std::pair<int, hipStream_t>, double *> g_part;
+
+qsv_status stream_partials(hipStream_t s, double **out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    if (dev < 0 || dev >= 64) return fail(QSV_EUNSUPPORTED, "device ordinal out of range");
-    std::lock_guard<std::mutex> g(mu);
-    if (cap[dev] < count) {
-        size_t want = std::max<size_t>(count, 65536);
-        double *p = nullptr;
-        e = hipMalloc(reinterpret_cast<void **>(&p), want * sizeof(double));
-        if (e != hipSuccess) return fail(QSV_ENOMEM, "norm partials: hipMalloc failed");
-        if (buf[dev]) {
-            // the old buffer may still be read by queued work: synchronise first
-            hipDeviceSynchronize();
-            hipFree(buf[dev]);
+    std::lock_guard<std::mutex> g(g_part_mu);
+    double *&buf = g_part[{dev, s}];
+    if (!buf) {
+        e = hipMalloc(reinterpret_cast<void **>(&buf), kStreamPartials * sizeof(double));
+        if (e != hipSuccess) {
+            buf = nullptr;
+            (void)hipGetLastError();
+            return fail(QSV_ENOMEM, "partial sums: hipMalloc failed");
         }
-        buf[dev] = p;
-        cap[dev] = want;
     }
-    *out = buf[dev];
+    *out = buf;
     return QSV_OK;
 }
 
@@ -88,41 +90,24 @@ qsv_status check_state(const void *amps, int n) {
     return QSV_OK;
 }
 
-// Second state buffer of out-of-place sweeps, one per device, grown on
-// demand and kept until the process ends.  Calls that overlap on one device
-// share it, so they must not both run out of place.
-std::mutex g_scratch_mu;
-void *g_scratch[64] = {nullptr};
-size_t g_scratch_cap[64] = {0};
+// Caller-owned workspace of a sweep call (sv_workspace_bytes): when the
+// plan runs out of place, the second state buffer (8 * 2^n bytes) at offset
+// 0 and the FP64 partial sums of the norm or inner-product epilogue after
+// it; otherwise the partial sums at offset 0.
+struct Workspace {
+    char *p = nullptr;
+    size_t bytes = 0;
+};
 
-qsv_status state_scratch(size_t bytes, void **out) {
-    std::mutex &mu = g_scratch_mu;
-    void **buf = g_scratch;
-    size_t *cap = g_scratch_cap;
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    if (dev < 0 || dev >= 64) return fail(QSV_EUNSUPPORTED, "device ordinal out of range");
-    std::lock_guard<std::mutex> g(mu);
-    if (cap[dev] < bytes) {
-        if (buf[dev]) {
-            // queued work may still use the old buffer
-            hipDeviceSynchronize();
-            hipFree(buf[dev]);
-            buf[dev] = nullptr;
-            cap[dev] = 0;
-        }
-        void *p = nullptr;
-        e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(QSV_ENOMEM, "out-of-place sweep: second state buffer does not fit");
-        }
-        buf[dev] = p;
-        cap[dev] = bytes;
-    }
-    *out = buf[dev];
-    return QSV_OK;
+size_t state_bytes(int n) { return sizeof(float) * 2 * (size_t(1) << n); }
+
+// Partial-sum region: two doubles per tile of the smallest tile the tuner
+// considers (2^11 amplitudes), at least 2 * 65536 for the generic kernels'
+// reductions, so that a workspace sized before tuning still fits.
+size_t partial_bytes(int n, int L) {
+    const int l = std::min(L > 0 ? L : 11, 11);
+    const size_t tiles = n > l ? size_t(1) << (n - l) : 1;
+    return 2 * sizeof(double) * std::max<size_t>(tiles, 65536);
 }
 
 // opts as given, else the autotuned options of this circuit and layer range
@@ -182,15 +167,35 @@ qsv_status select_plan(const qsv_circuit *c, int lb, int le, TileShape sh, int o
     return get_plan(c, lb, le, sh, plan);
 }
 
+// Plan, second buffer and partial sums of a fused call.  part_need: bytes
+// of FP64 partial sums the call writes (0 = none).  An out-of-place plan
+// runs only when the workspace holds the second buffer and the partials;
+// otherwise a forced one (oop > 1) fails and an automatic one runs in place.
 qsv_status get_fused_plan(const qsv_circuit *c, int lb, int le, TileShape sh, int oop,
-                          bool reads_state, std::shared_ptr<Plan> &plan, void **scratch) {
+                          bool reads_state, const Workspace &ws, size_t part_need,
+                          std::shared_ptr<Plan> &plan, void **scratch, double **part) {
     *scratch = nullptr;
+    if (part) *part = nullptr;
     qsv_status st = select_plan(c, lb, le, sh, oop, reads_state, plan);
-    if (st != QSV_OK || !plan->oop) return st;
-    st = state_scratch(sizeof(float) * 2 * (size_t(1) << c->n), scratch);
-    if (st == QSV_OK || oop > 1) return st;
-    sh.oop = false;
-    return get_plan(c, lb, le, sh, plan);
+    if (st != QSV_OK) return st;
+    if (plan->oop) {
+        const size_t sb = state_bytes(c->n);
+        if (ws.p && ws.bytes >= sb + part_need) {
+            *scratch = ws.p;
+            if (part && part_need) *part = reinterpret_cast<double *>(ws.p + sb);
+            return QSV_OK;
+        }
+        if (oop > 1)
+            return fail(QSV_EINVAL, "out-of-place sweep: the workspace is smaller than sv_workspace_bytes");
+        sh.oop = false;
+        if ((st = get_plan(c, lb, le, sh, plan)) != QSV_OK) return st;
+    }
+    if (part_need) {
+        if (!ws.p || ws.bytes < part_need)
+            return fail(QSV_EINVAL, "the FP64 reduction needs a workspace of sv_workspace_bytes bytes");
+        if (part) *part = reinterpret_cast<double *>(ws.p);
+    }
+    return QSV_OK;
 }
 
 qsv_status get_plan(const qsv_circuit *cc, int lb, int le, TileShape sh,
@@ -244,7 +249,8 @@ void gate_matrix_f32(uint8_t kind, float m[8]) {
 // Per-pass times of the sweep as sv_simulate runs it from |+>^n (the
 // autotuner's choice of kernel form per pass).
 qsv_status time_sweep_passes(const qsv_circuit *c, int lb, int le, const qsv_fuse_opts *opts,
-                             void *amps, hipStream_t s, std::vector<float> &ms) {
+                             void *amps, void *workspace, size_t ws_bytes, hipStream_t s,
+                             uint64_t max_tiles, std::vector<float> &ms) {
     TileShape sh;
     qsv_status st = resolve_shape(c, opts, sh, lb, le);
     if (st != QSV_OK) return st;
@@ -252,7 +258,9 @@ qsv_status time_sweep_passes(const qsv_circuit *c, int lb, int le, const qsv_fus
     if (sh.R == 0 || !jm) return fail(QSV_EUNSUPPORTED, "pass timing needs compiled pass kernels");
     std::shared_ptr<Plan> plan;
     void *scratch = nullptr;
-    if ((st = get_fused_plan(c, lb, le, sh, oop_mode(c, opts, jm), false, plan, &scratch)) != QSV_OK)
+    const Workspace ws{static_cast<char *>(workspace), ws_bytes};
+    if ((st = get_fused_plan(c, lb, le, sh, oop_mode(c, opts, jm), false, ws, 0, plan, &scratch, nullptr)) !=
+        QSV_OK)
         return st;
     if (plan->passes.empty()) return fail(QSV_EUNSUPPORTED, "empty layer range");
     const int variant = kJitInit | QSV_INIT_PLUS | (jm & ~3);
@@ -260,7 +268,8 @@ qsv_status time_sweep_passes(const qsv_circuit *c, int lb, int le, const qsv_fus
         std::lock_guard<std::mutex> g(plan->jit_mu);
         if ((st = jit_prepare(*plan, variant)) != QSV_OK) return st;
     }
-    return jit_launch(*plan, variant, amps, scratch, 0, 0, nullptr, s, &ms);
+    return jit_launch(*plan, variant, amps, scratch, 0, 0, nullptr, s, &ms, nullptr, nullptr, nullptr, 0,
+                      nullptr, 1, 0, max_tiles);
 }
 
 }  // namespace qsv
@@ -278,16 +287,15 @@ qsv_status qsv_release_device_buffers(void) {
     e = hipDeviceSynchronize();  // queued sweeps may still use them
     if (e != hipSuccess) return hip_fail(e, "qsv_release_device_buffers");
     {
-        std::lock_guard<std::mutex> g(g_scratch_mu);
-        if (g_scratch[dev]) hipFree(g_scratch[dev]);
-        g_scratch[dev] = nullptr;
-        g_scratch_cap[dev] = 0;
-    }
-    {
         std::lock_guard<std::mutex> g(g_part_mu);
-        if (g_part[dev]) hipFree(g_part[dev]);
-        g_part[dev] = nullptr;
-        g_part_cap[dev] = 0;
+        for (auto it = g_part.begin(); it != g_part.end();) {
+            if (it->first.first == dev) {
+                if (it->second) hipFree(it->second);
+                it = g_part.erase(it);
+            } else {
+                ++it;
+            }
+        }
     }
     return QSV_OK;
 }
@@ -398,7 +406,8 @@ qsv_status sv_apply_plain(void *amps, const qsv_circuit *c, uint64_t branch, int
 }
 
 qsv_status sv_apply_fused(void *amps, const qsv_circuit *c, uint64_t branch, int layer_begin,
-                          int layer_end, const qsv_fuse_opts *opts, void *stream) {
+                          int layer_end, const qsv_fuse_opts *opts, void *workspace, size_t ws_bytes,
+                          void *stream) {
     if (!c) return fail(QSV_EINVAL, "sv_apply_fused: null circuit");
     qsv_status st = check_state(amps, c->n);
     if (st != QSV_OK) return st;
@@ -414,8 +423,9 @@ qsv_status sv_apply_fused(void *amps, const qsv_circuit *c, uint64_t branch, int
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (const int jm = jit_mode(c, opts)) {
         void *scratch = nullptr;
-        if ((st = get_fused_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jm), true, plan,
-                                 &scratch)) != QSV_OK)
+        const Workspace ws{static_cast<char *>(workspace), ws_bytes};
+        if ((st = get_fused_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jm), true, ws, 0, plan,
+                                 &scratch, nullptr)) != QSV_OK)
             return st;
         if (plan->passes.empty()) return QSV_OK;  // no gates in the range
         const int variant = kJitPlain | (jm & ~3);
@@ -434,12 +444,14 @@ qsv_status sv_apply_fused(void *amps, const qsv_circuit *c, uint64_t branch, int
 }
 
 qsv_status sv_apply_fused_from(const void *src, void *dst, const qsv_circuit *c, uint64_t branch,
-                               int layer_begin, int layer_end, const qsv_fuse_opts *opts, void *stream) {
+                               int layer_begin, int layer_end, const qsv_fuse_opts *opts, void *workspace,
+                               size_t ws_bytes, void *stream) {
     if (!c) return fail(QSV_EINVAL, "sv_apply_fused_from: null circuit");
     qsv_status st = check_state(src, c->n);
     if (st != QSV_OK) return st;
     if ((st = check_state(dst, c->n)) != QSV_OK) return st;
-    if (src == dst) return sv_apply_fused(dst, c, branch, layer_begin, layer_end, opts, stream);
+    if (src == dst)
+        return sv_apply_fused(dst, c, branch, layer_begin, layer_end, opts, workspace, ws_bytes, stream);
     const size_t bytes = sizeof(float) * 2 * (size_t(1) << c->n);
     const char *a = static_cast<const char *>(src), *b = static_cast<const char *>(dst);
     if (a < b + bytes && b < a + bytes) return fail(QSV_EINVAL, "sv_apply_fused_from: src and dst overlap");
@@ -460,8 +472,9 @@ qsv_status sv_apply_fused_from(const void *src, void *dst, const qsv_circuit *c,
         // any pass count ends in dst and src is never written
         std::shared_ptr<Plan> plan;
         void *scratch = nullptr;
-        if ((st = get_fused_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jm), false, plan,
-                                 &scratch)) != QSV_OK)
+        const Workspace ws{static_cast<char *>(workspace), ws_bytes};
+        if ((st = get_fused_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jm), false, ws, 0, plan,
+                                 &scratch, nullptr)) != QSV_OK)
             return st;
         if (plan->passes.empty()) {  // no gates in the range: dst = src
             hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
@@ -477,7 +490,7 @@ qsv_status sv_apply_fused_from(const void *src, void *dst, const qsv_circuit *c,
     // generic kernel or per-gate path: copy, then sweep dst in place
     hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "sv_apply_fused_from: copy");
-    return sv_apply_fused(dst, c, branch, layer_begin, layer_end, opts, stream);
+    return sv_apply_fused(dst, c, branch, layer_begin, layer_end, opts, workspace, ws_bytes, stream);
 }
 
 }  // extern "C"
@@ -526,9 +539,9 @@ static qsv_status sampler_create(const qsv_circuit *c, int layer_begin, int laye
     S->jm = fused ? jit_mode(c, eo) : 0;
     hipError_t e;
     if (S->jm) {
-        void *scratch = nullptr;
-        if ((st = get_fused_plan(c, layer_begin, layer_end, S->sh, oop_mode(c, eo, S->jm), false, S->plan,
-                                 &scratch)) != QSV_OK)
+        // the plan the runs use when their workspace holds a second state
+        // buffer; runs without one plan in place and need their own sampler
+        if ((st = select_plan(c, layer_begin, layer_end, S->sh, oop_mode(c, eo, S->jm), false, S->plan)) != QSV_OK)
             return st;
         S->compiled = !S->plan->passes.empty();
     }
@@ -616,8 +629,19 @@ qsv_status sv_sampler_inputs(const qsv_sampler *S, uint64_t *out, size_t cap, si
     return QSV_OK;
 }
 
+// The second state buffer of a sampler run: the sampler's plan is fixed at
+// creation, so an out-of-place plan needs it in every run's workspace.
+static qsv_status sampler_scratch(const qsv_sampler *S, void *workspace, size_t ws_bytes, void **scratch) {
+    *scratch = nullptr;
+    if (!S->plan || !S->plan->oop) return QSV_OK;
+    if (!workspace || ws_bytes < state_bytes(S->c->n))
+        return fail(QSV_EINVAL, "sampler run: the out-of-place plan needs a workspace of sv_workspace_bytes bytes");
+    *scratch = workspace;
+    return QSV_OK;
+}
+
 qsv_status sv_sampler_run(qsv_sampler *S, const void *src, void *work, uint64_t branch, void *out_dev,
-                          void *stream) {
+                          void *workspace, size_t ws_bytes, void *stream) {
     if (!S || !out_dev) return fail(QSV_EINVAL, "sv_sampler_run: null argument");
     const qsv_circuit *c = S->c;
     qsv_status st = check_state(src, c->n);
@@ -628,17 +652,15 @@ qsv_status sv_sampler_run(qsv_sampler *S, const void *src, void *work, uint64_t 
     hipStream_t s = static_cast<hipStream_t>(stream);
     const qsv_fuse_opts *opts = S->has_opts ? &S->opts : nullptr;
     if (!S->compiled) {
-        if ((st = sv_apply_fused_from(src, work, c, branch, S->lb, S->le, opts, stream)) != QSV_OK) return st;
+        if ((st = sv_apply_fused_from(src, work, c, branch, S->lb, S->le, opts, workspace, ws_bytes, stream)) !=
+            QSV_OK)
+            return st;
         hipError_t e = launch_gather(static_cast<const float2 *>(work), c->n, S->d_xs, S->m, out_dev, 0, s);
         return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_sampler_run");
     }
-    qsv_fuse_opts tuned;
-    const qsv_fuse_opts *eo = effective_opts(c, opts, S->lb, S->le, &tuned);
-    std::shared_ptr<Plan> plan;
-    void *scratch = nullptr;  // fetched per run: the second buffer may have been regrown
-    if ((st = get_fused_plan(c, S->lb, S->le, S->sh, oop_mode(c, eo, S->jm), false, plan, &scratch)) != QSV_OK)
-        return st;
-    if (plan != S->plan) return fail(QSV_EINTERNAL, "sv_sampler_run: the circuit's plan changed");
+    const std::shared_ptr<Plan> &plan = S->plan;
+    void *scratch = nullptr;
+    if ((st = sampler_scratch(S, workspace, ws_bytes, &scratch)) != QSV_OK) return st;
     if (S->tiles && (out_dev == src || (plan->passes.size() > 1 && out_dev == work)))
         return fail(QSV_EINVAL, "sv_sampler_run: the tile state must be neither src nor work");
     const int variant = kJitPlain | kJitSample | (S->tiles ? kJitTiles : 0) | (S->jm & ~3);
@@ -647,7 +669,7 @@ qsv_status sv_sampler_run(qsv_sampler *S, const void *src, void *work, uint64_t 
 }
 
 qsv_status sv_sampler_run_subtree(qsv_sampler *S, const void *src, void *work, uint64_t prefix, uint64_t mask,
-                                  void *out_dev, void *stream) {
+                                  void *out_dev, void *workspace, size_t ws_bytes, void *stream) {
     if (!S || !out_dev) return fail(QSV_EINVAL, "sv_sampler_run_subtree: null argument");
     if (S->tiles) return fail(QSV_EINVAL, "sv_sampler_run_subtree: a tile sampler writes one state per run");
     if (prefix & mask) return fail(QSV_EINVAL, "sv_sampler_run_subtree: prefix and mask share bits");
@@ -660,16 +682,9 @@ qsv_status sv_sampler_run_subtree(qsv_sampler *S, const void *src, void *work, u
     if (src == work) return fail(QSV_EINVAL, "sv_sampler_run_subtree: work must not be src");
     if ((st = check_device()) != QSV_OK) return st;
     const size_t rows = size_t(1) << k;
-    std::shared_ptr<Plan> plan;
+    const std::shared_ptr<Plan> &plan = S->plan;
     void *scratch = nullptr;
-    if (S->compiled) {
-        const qsv_fuse_opts *opts = S->has_opts ? &S->opts : nullptr;
-        qsv_fuse_opts tuned;
-        const qsv_fuse_opts *eo = effective_opts(c, opts, S->lb, S->le, &tuned);
-        if ((st = get_fused_plan(c, S->lb, S->le, S->sh, oop_mode(c, eo, S->jm), false, plan, &scratch)) != QSV_OK)
-            return st;
-        if (plan != S->plan) return fail(QSV_EINTERNAL, "sv_sampler_run_subtree: the circuit's plan changed");
-    }
+    if (S->compiled && (st = sampler_scratch(S, workspace, ws_bytes, &scratch)) != QSV_OK) return st;
     if (!S->compiled || plan->passes.size() != 1) {
         // earlier passes are per branch: one run per row
         for (size_t y = 0; y < rows; ++y) {
@@ -681,7 +696,7 @@ qsv_status sv_sampler_run_subtree(qsv_sampler *S, const void *src, void *work, u
                 msk ^= low;
             }
             void *out = static_cast<char *>(out_dev) + y * S->m * sizeof(float2);
-            if ((st = sv_sampler_run(S, src, work, br, out, stream)) != QSV_OK) return st;
+            if ((st = sv_sampler_run(S, src, work, br, out, workspace, ws_bytes, stream)) != QSV_OK) return st;
         }
         return QSV_OK;
     }
@@ -691,13 +706,13 @@ qsv_status sv_sampler_run_subtree(qsv_sampler *S, const void *src, void *work, u
 }
 
 qsv_status sv_sampler_run_branches(qsv_sampler *S, const void *src, void *work, const uint64_t *branches,
-                                   size_t count, void *out_dev, void *stream) {
+                                   size_t count, void *out_dev, void *workspace, size_t ws_bytes, void *stream) {
     if (!S || !out_dev || (count && !branches)) return fail(QSV_EINVAL, "sv_sampler_run_branches: null argument");
     if (S->tiles) return fail(QSV_EINVAL, "sv_sampler_run_branches: a tile sampler writes one state per run");
     // every call below validates the same arguments; the first one reports
     for (size_t i = 0; i < count; ++i) {
         void *out = static_cast<char *>(out_dev) + i * S->m * sizeof(float2);
-        qsv_status st = sv_sampler_run(S, src, work, branches[i], out, stream);
+        qsv_status st = sv_sampler_run(S, src, work, branches[i], out, workspace, ws_bytes, stream);
         if (st != QSV_OK) return st;
     }
     return QSV_OK;
@@ -716,13 +731,25 @@ qsv_status sv_amplitudes(const void *amps, int n_qubits, const uint64_t *bitstri
     return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_amplitudes");
 }
 
+qsv_status sv_stream_copy(const void *src, void *dst, size_t bytes, void *stream) {
+    if (!src || !dst) return fail(QSV_EINVAL, "sv_stream_copy: null buffer");
+    if (bytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16)
+        return fail(QSV_EINVAL, "sv_stream_copy: buffers and size must be multiples of 16 bytes");
+    const char *a = static_cast<const char *>(src), *b = static_cast<const char *>(dst);
+    if (a < b + bytes && b < a + bytes) return fail(QSV_EINVAL, "sv_stream_copy: buffers overlap");
+    qsv_status st = check_device();
+    if (st != QSV_OK) return st;
+    hipError_t e = launch_stream_copy(src, dst, bytes, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_stream_copy");
+}
+
 qsv_status sv_norm_fp64(const void *amps, int n_qubits, double *out_dev, void *stream) {
     qsv_status st = check_state(amps, n_qubits);
     if (st != QSV_OK) return st;
     if (!out_dev) return fail(QSV_EINVAL, "sv_norm_fp64: null output");
     if ((st = check_device()) != QSV_OK) return st;
     double *part = nullptr;
-    if ((st = norm_partials(65536, &part)) != QSV_OK) return st;
+    if ((st = stream_partials(static_cast<hipStream_t>(stream), &part)) != QSV_OK) return st;
     hipError_t e = launch_norm(static_cast<const float2 *>(amps), n_qubits, out_dev, part,
                                static_cast<hipStream_t>(stream));
     return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_norm_fp64");
@@ -735,7 +762,7 @@ qsv_status sv_inner_product(const void *a, const void *b, int n_qubits, double *
     if (!out_dev) return fail(QSV_EINVAL, "sv_inner_product: null output");
     if ((st = check_device()) != QSV_OK) return st;
     double *part = nullptr;
-    if ((st = norm_partials(2 * 65536, &part)) != QSV_OK) return st;
+    if ((st = stream_partials(static_cast<hipStream_t>(stream), &part)) != QSV_OK) return st;
     hipError_t e = launch_dot(static_cast<const float2 *>(a), static_cast<const float2 *>(b), n_qubits,
                               out_dev, part, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_inner_product");
@@ -743,8 +770,10 @@ qsv_status sv_inner_product(const void *a, const void *b, int n_qubits, double *
 
 qsv_status sv_branch_combine_full(const void *a_states, const void *b_states, size_t n_branches,
                                   int n_a, int n_b, uint64_t side_a_mask, const int32_t *folded_a,
-                                  const int32_t *folded_b, size_t n_folded, void *out_state,
+                                  const int32_t *folded_b, size_t n_folded, void *out_state, int flags,
                                   void *stream) {
+    if (flags & ~(QSV_COMBINE_OUT_C128 | QSV_COMBINE_FP32))
+        return fail(QSV_EINVAL, "sv_branch_combine_full: unknown flag");
     if (!a_states || !b_states || !out_state) return fail(QSV_EINVAL, "sv_branch_combine_full: null buffer");
     if (n_folded && (!folded_a || !folded_b))
         return fail(QSV_EINVAL, "sv_branch_combine_full: null folded pairs");
@@ -784,8 +813,8 @@ qsv_status sv_branch_combine_full(const void *a_states, const void *b_states, si
     qsv_status st = check_device();
     if (st != QSV_OK) return st;
     hipError_t e = launch_combine_gemm(static_cast<const float2 *>(a_states), static_cast<const float2 *>(b_states),
-                                       n_branches, P, static_cast<float2 *>(out_state),
-                                       static_cast<hipStream_t>(stream));
+                                       n_branches, P, out_state, !(flags & QSV_COMBINE_FP32),
+                                       (flags & QSV_COMBINE_OUT_C128) != 0, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_branch_combine_full");
 }
 
@@ -795,7 +824,13 @@ qsv_status sv_partition_workspace_bytes(const qsv_partition *p, size_t *bytes) {
     partition_layout(p, L);
     const int ea = L.na + L.eb + L.kb, eb = L.nb + L.eb + L.ka;
     if (ea > 40 || eb > 40) return fail(QSV_ERANGE, "sv_partition_workspace_bytes: parts too large");
-    *bytes = sizeof(float) * 2 * ((size_t(1) << ea) + (size_t(1) << eb));
+    // branch states of A and B, then the workspace of part C's sweep
+    size_t c_ws = 0;
+    if (L.c_gates) {
+        qsv_status st = sv_workspace_bytes(partition_part(p, 2), 0, -1, nullptr, &c_ws);
+        if (st != QSV_OK) return st;
+    }
+    *bytes = sizeof(float) * 2 * ((size_t(1) << ea) + (size_t(1) << eb)) + c_ws;
     return QSV_OK;
 }
 
@@ -843,7 +878,7 @@ qsv_status sv_partition_simulate(qsv_partition *p, void *workspace, size_t ws_by
                 circs.push_back(partition_part(p, side));
                 ids.push_back(i);
             } else if ((st = sv_simulate(w + (i << nq), partition_part(p, side), i, QSV_INIT_PLUS, 0, 1, -1,
-                                         nullptr, nullptr, nullptr, 0, nullptr, 0, stream)) != QSV_OK) {
+                                         nullptr, nullptr, nullptr, 0, nullptr, 0, nullptr, 0, stream)) != QSV_OK) {
                 return st;
             }
         }
@@ -881,12 +916,15 @@ qsv_status sv_partition_simulate(qsv_partition *p, void *workspace, size_t ws_by
             // A's branch (e, u = vb), B's branch (e, w = va)
             P.a_off = ((vb << L.eb) << L.na) + P.row_base;
             P.b_off = ((va << L.eb) << L.nb) + P.col_base;
-            hipError_t e = launch_combine_gemm(wa, wb, ne, P, static_cast<float2 *>(out_state), s);
+            hipError_t e = launch_combine_gemm(wa, wb, ne, P, out_state, true, false, s);
             if (e != hipSuccess) return hip_fail(e, "sv_partition_simulate: combine");
         }
-    // 3. part C on the complete state
+    // 3. part C on the complete state (its sweep workspace follows the
+    // branch states)
     if (L.c_gates == 0) return QSV_OK;
-    return sv_apply_fused(out_state, partition_part(p, 2), 0, 0, -1, nullptr, stream);
+    const size_t used = sizeof(float) * 2 * ((nbr_a << L.na) + (nbr_b << L.nb));
+    return sv_apply_fused(out_state, partition_part(p, 2), 0, 0, -1, nullptr, static_cast<char *>(workspace) + used,
+                          ws_bytes - used, stream);
 }
 
 qsv_status sv_branch_combine(const void *a_tab, const void *b_tab, size_t n_branches, size_t m,
@@ -906,7 +944,7 @@ qsv_status sv_branch_combine(const void *a_tab, const void *b_tab, size_t n_bran
 qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int init_kind,
                        uint64_t basis, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
                        double *norm_out_dev, const uint64_t *bitstrings_dev, size_t m,
-                       void *amps_out_dev, int out_c128, void *stream) {
+                       void *amps_out_dev, int out_c128, void *workspace, size_t ws_bytes, void *stream) {
     if (!c) return fail(QSV_EINVAL, "sv_simulate: null circuit");
     qsv_status st = check_state(amps, c->n);
     if (st != QSV_OK) return st;
@@ -920,6 +958,7 @@ qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int in
     if (m && (!bitstrings_dev || !amps_out_dev)) return fail(QSV_EINVAL, "sv_simulate: null gather buffer");
     if ((st = check_device()) != QSV_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const Workspace ws{static_cast<char *>(workspace), ws_bytes};
     TileShape sh;
     bool fused = !(opts && opts->plain);
     if (fused) {
@@ -929,14 +968,16 @@ qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int in
     std::shared_ptr<Plan> plan;
     const int jm = fused ? jit_mode(c, opts) : 0;
     void *scratch = nullptr;
+    double *part = nullptr;
     if (jm) {
-        if ((st = get_fused_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jm), false, plan,
-                                 &scratch)) != QSV_OK)
+        const uint64_t tiles = 1ull << (c->n - sh.R - sh.T);
+        const size_t need = norm_out_dev ? tiles * sizeof(double) : 0;
+        if ((st = get_fused_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jm), false, ws, need, plan,
+                                 &scratch, &part)) != QSV_OK)
             return st;
     } else if (fused && (st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) {
         return st;
     }
-    bool done_norm = false;
     if (jm && !plan->passes.empty()) {
         // initial state generated by the first pass, norm by the last
         const int variant = kJitInit | init_kind | (norm_out_dev ? kJitNorm : 0) | (jm & ~3);
@@ -944,24 +985,28 @@ qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int in
             std::lock_guard<std::mutex> g(plan->jit_mu);
             if ((st = jit_prepare(*plan, variant)) != QSV_OK) return st;
         }
-        double *part = nullptr;
         const uint64_t tiles = 1ull << (c->n - sh.R - sh.T);
-        if (norm_out_dev && (st = norm_partials(tiles, &part)) != QSV_OK) return st;
         if ((st = jit_launch(*plan, variant, amps, scratch, branch, basis, part, s)) != QSV_OK) return st;
         if (norm_out_dev) {
             hipError_t e = launch_sum_partials(part, tiles, norm_out_dev, s);
             if (e != hipSuccess) return hip_fail(e, "sv_simulate");
-            done_norm = true;
         }
     } else {
+        // generic kernel or per-gate path: init, sweep in place, then the
+        // norm's own reduction with its partial sums in the workspace
+        const size_t need = norm_out_dev ? norm_partial_count(c->n) * sizeof(double) : 0;
+        if (need && (!ws.p || ws.bytes < need))
+            return fail(QSV_EINVAL, "sv_simulate: the FP64 norm needs a workspace of sv_workspace_bytes bytes");
         hipError_t e = launch_init(static_cast<float2 *>(amps), c->n, init_kind, basis, s);
         if (e != hipSuccess) return hip_fail(e, "sv_simulate");
-        st = fused ? sv_apply_fused(amps, c, branch, layer_begin, layer_end, opts, stream)
+        st = fused ? sv_apply_fused(amps, c, branch, layer_begin, layer_end, opts, nullptr, 0, stream)
                    : sv_apply_plain(amps, c, branch, layer_begin, layer_end, stream);
         if (st != QSV_OK) return st;
-    }
-    if (norm_out_dev && !done_norm) {
-        if ((st = sv_norm_fp64(amps, c->n, norm_out_dev, stream)) != QSV_OK) return st;
+        if (norm_out_dev) {
+            e = launch_norm(static_cast<const float2 *>(amps), c->n, norm_out_dev, reinterpret_cast<double *>(ws.p),
+                            s);
+            if (e != hipSuccess) return hip_fail(e, "sv_simulate: norm");
+        }
     }
     if (m) {
         hipError_t e = launch_gather(static_cast<const float2 *>(amps), c->n, bitstrings_dev, m,
@@ -973,7 +1018,7 @@ qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int in
 
 qsv_status sv_simulate_dot(void *amps, const qsv_circuit *c, uint64_t branch, int init_kind,
                            uint64_t basis, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
-                           const void *other, double *out_dev, void *stream) {
+                           const void *other, double *out_dev, void *workspace, size_t ws_bytes, void *stream) {
     if (!c) return fail(QSV_EINVAL, "sv_simulate_dot: null circuit");
     qsv_status st = check_state(amps, c->n);
     if (st != QSV_OK) return st;
@@ -989,6 +1034,7 @@ qsv_status sv_simulate_dot(void *amps, const qsv_circuit *c, uint64_t branch, in
     opts = effective_opts(c, opts, layer_begin, layer_end, &tuned);
     if ((st = check_device()) != QSV_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const Workspace ws{static_cast<char *>(workspace), ws_bytes};
     TileShape sh;
     bool fused = !(opts && opts->plain);
     if (fused) {
@@ -998,15 +1044,23 @@ qsv_status sv_simulate_dot(void *amps, const qsv_circuit *c, uint64_t branch, in
     const int jm = fused ? jit_mode(c, opts) : 0;
     std::shared_ptr<Plan> plan;
     void *scratch = nullptr;
-    if (jm && (st = get_fused_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jm), false, plan,
-                                   &scratch)) != QSV_OK)
+    double *part = nullptr;
+    const uint64_t tiles = fused ? 1ull << (c->n - sh.R - sh.T) : 0;
+    if (jm && (st = get_fused_plan(c, layer_begin, layer_end, sh, oop_mode(c, opts, jm), false, ws,
+                                   2 * tiles * sizeof(double), plan, &scratch, &part)) != QSV_OK)
         return st;
     if (!jm || plan->passes.empty()) {
-        // the sweep into amps, then the inner product (two kernels)
+        // the sweep into amps, then the inner product (two kernels, the
+        // reduction's partial sums in the workspace)
+        const size_t need = 2 * 65536 * sizeof(double);
+        if (!ws.p || ws.bytes < need)
+            return fail(QSV_EINVAL, "sv_simulate_dot: needs a workspace of sv_workspace_bytes bytes");
         if ((st = sv_simulate(amps, c, branch, init_kind, basis, layer_begin, layer_end, opts, nullptr, nullptr,
-                              0, nullptr, 0, stream)) != QSV_OK)
+                              0, nullptr, 0, nullptr, 0, stream)) != QSV_OK)
             return st;
-        return sv_inner_product(amps, other, c->n, out_dev, stream);
+        hipError_t e = launch_dot(static_cast<const float2 *>(amps), static_cast<const float2 *>(other), c->n,
+                                  out_dev, reinterpret_cast<double *>(ws.p), s);
+        return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_simulate_dot");
     }
     // initial state from the first pass; the last pass stores nothing and
     // writes the FP64 partials of <result|other>
@@ -1015,9 +1069,6 @@ qsv_status sv_simulate_dot(void *amps, const qsv_circuit *c, uint64_t branch, in
         std::lock_guard<std::mutex> g(plan->jit_mu);
         if ((st = jit_prepare(*plan, variant)) != QSV_OK) return st;
     }
-    const uint64_t tiles = 1ull << (c->n - sh.R - sh.T);
-    double *part = nullptr;
-    if ((st = norm_partials(2 * tiles, &part)) != QSV_OK) return st;
     if ((st = jit_launch(*plan, variant, amps, scratch, branch, basis, part, s, nullptr, nullptr, other)) != QSV_OK)
         return st;
     hipError_t e = launch_sum_partials(part, tiles, out_dev, s);
@@ -1028,7 +1079,7 @@ qsv_status sv_simulate_dot(void *amps, const qsv_circuit *c, uint64_t branch, in
 qsv_status sv_simulate_c128(void *amps, const qsv_circuit *c, uint64_t branch, int init_kind,
                             uint64_t basis, int layer_begin, int layer_end, double *norm_out_dev,
                             const uint64_t *bitstrings_dev, size_t m, void *amps_out_dev,
-                            void *stream) {
+                            void *workspace, size_t ws_bytes, void *stream) {
     if (!c || !amps) return fail(QSV_EINVAL, "sv_simulate_c128: null argument");
     if (reinterpret_cast<uintptr_t>(amps) % 16) return fail(QSV_EINVAL, "sv_simulate_c128: misaligned state");
     if (c->n < 12 || c->n > kMaxQubits) return fail(QSV_EUNSUPPORTED, "sv_simulate_c128: needs 12 <= n <= 34");
@@ -1038,9 +1089,12 @@ qsv_status sv_simulate_c128(void *amps, const qsv_circuit *c, uint64_t branch, i
     if (init_kind == QSV_INIT_ZERO) basis = 0;
     if (layer_begin < 0) return fail(QSV_EINVAL, "sv_simulate_c128: layer_begin < 0");
     if (m && (!bitstrings_dev || !amps_out_dev)) return fail(QSV_EINVAL, "sv_simulate_c128: null gather buffer");
+    const TileShape sh{4, 8, 4};
+    const uint64_t tiles = 1ull << (c->n - sh.R - sh.T);
+    if (norm_out_dev && (!workspace || ws_bytes < tiles * sizeof(double)))
+        return fail(QSV_EINVAL, "sv_simulate_c128: the FP64 norm needs a workspace of sv_workspace_bytes bytes");
     qsv_status st = check_device();
     if (st != QSV_OK) return st;
-    const TileShape sh{4, 8, 4};
     std::shared_ptr<Plan> plan;
     if ((st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) return st;
     if (plan->passes.empty()) return fail(QSV_EUNSUPPORTED, "sv_simulate_c128: empty layer range");
@@ -1050,9 +1104,7 @@ qsv_status sv_simulate_c128(void *amps, const qsv_circuit *c, uint64_t branch, i
         if ((st = jit_prepare(*plan, variant)) != QSV_OK) return st;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    double *part = nullptr;
-    const uint64_t tiles = 1ull << (c->n - sh.R - sh.T);
-    if (norm_out_dev && (st = norm_partials(tiles, &part)) != QSV_OK) return st;
+    double *part = norm_out_dev ? static_cast<double *>(workspace) : nullptr;
     if ((st = jit_launch(*plan, variant, amps, nullptr, branch, basis, part, s)) != QSV_OK) return st;
     if (norm_out_dev) {
         hipError_t e = launch_sum_partials(part, tiles, norm_out_dev, s);
@@ -1062,6 +1114,24 @@ qsv_status sv_simulate_c128(void *amps, const qsv_circuit *c, uint64_t branch, i
         hipError_t e = launch_gather_c128(amps, c->n, bitstrings_dev, m, amps_out_dev, s);
         if (e != hipSuccess) return hip_fail(e, "sv_simulate_c128");
     }
+    return QSV_OK;
+}
+
+qsv_status sv_workspace_bytes(const qsv_circuit *c, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
+                              size_t *bytes) {
+    if (!c || !bytes) return fail(QSV_EINVAL, "sv_workspace_bytes: null argument");
+    if (layer_begin < 0) return fail(QSV_EINVAL, "sv_workspace_bytes: layer_begin < 0");
+    qsv_fuse_opts tuned;
+    opts = effective_opts(c, opts, layer_begin, layer_end, &tuned);
+    TileShape sh{0, 0, 0};
+    const bool fused = !(opts && opts->plain);
+    if (fused) {
+        qsv_status st = resolve_shape(c, opts, sh, layer_begin, layer_end);
+        if (st != QSV_OK) return st;
+    }
+    const int jm = (fused && sh.R) ? jit_mode(c, opts) : 0;
+    *bytes = partial_bytes(c->n, sh.R + sh.T);
+    if (jm && oop_mode(c, opts, jm)) *bytes += state_bytes(c->n);
     return QSV_OK;
 }
 

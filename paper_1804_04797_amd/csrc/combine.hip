@@ -9,9 +9,14 @@
 // runs as two real GEMMs over an interleaved K index k = 2b + part:
 //   Mr = sum_k A1[k] B1[k],  A1 = (Ar, -Ai),  B1 = (Br, Bi)
 //   Mi = sum_k A2[k] B1[k],  A2 = (Ai,  Ar)
-// on v_mfma_f32_16x16x4f32 with FP32 accumulation.  A workgroup owns a
-// 128 x 128 output tile; each of its four waves a 64 x 64 quadrant (4 x 4
-// MFMA blocks for each of Mr, Mi).  Branch chunks of 16 are staged in LDS as
+// The default form sums the branch products in FP64: the FP32 inputs are
+// widened and multiplied on v_mfma_f64_16x16x4f64, so every product is exact
+// and every partial sum is an FP64 sum; the result is rounded once, to the
+// complex64 state or not at all for a complex128 output.  The FP32 form
+// (v_mfma_f32_16x16x4f32, FP32 accumulation) runs at twice the matrix-core
+// rate and is selected explicitly.  A workgroup owns a 128 x 128 output tile;
+// each of its four waves a 64 x 64 quadrant (4 x 4 MFMA blocks for each of
+// Mr, Mi).  Branch chunks of 16 are staged in LDS as
 // k-major planes; the next chunk's global loads are issued before the current
 // chunk's MFMA work so that they overlap it.  The epilogue applies s(x) and
 // scatters the tile to the state's natural index order through per-tile
@@ -22,6 +27,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -29,27 +35,33 @@ namespace qsv {
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = 128;  // output rows (x_A) and columns (x_B) per workgroup
 constexpr int kBr = 16;     // branches per LDS chunk
 constexpr int kK = 2 * kBr; // interleaved K per chunk
 
-__global__ void __launch_bounds__(256, 2)
+// F64: FP64 products and sums (accumulators of 256 registers per lane: one
+// workgroup per CU); otherwise FP32 (two workgroups per CU).  out_c128: the
+// output state is complex128.
+template <bool F64>
+__global__ void __launch_bounds__(256, F64 ? 1 : 2)
 k_combine_gemm(const float2 *__restrict__ A, const float2 *__restrict__ B, uint64_t nbr,
-               const CombineArgs P, float2 *__restrict__ out) {
+               const CombineArgs P, void *__restrict__ out, int out_c128) {
+    using Acc = typename std::conditional<F64, v4d, v4f>::type;
     __shared__ __attribute__((aligned(16))) float a1[kK][kTile];  // also the epilogue's 64-bit tables
     __shared__ float a2[kK][kTile], b1[kK][kTile];
     const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
     const uint64_t i0 = uint64_t(blockIdx.x) * kTile, j0 = uint64_t(blockIdx.y) * kTile;
     const uint32_t wr = w & 1u, wc = w >> 1;  // quadrant of this wave
     const uint32_t lr = lane & 15u, lk = lane >> 4;
-    v4f accr[4][4], acci[4][4];
+    Acc accr[4][4], acci[4][4];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            accr[m][c] = v4f{0, 0, 0, 0};
-            acci[m][c] = v4f{0, 0, 0, 0};
+            accr[m][c] = Acc{0, 0, 0, 0};
+            acci[m][c] = Acc{0, 0, 0, 0};
         }
     // staging: thread t always loads in-tile row tr of branches tb, tb + 2, ...
     // of a chunk, so one pointer per side and a uniform stride address them
@@ -97,16 +109,34 @@ k_combine_gemm(const float2 *__restrict__ A, const float2 *__restrict__ B, uint6
                 fa2[m] = a2[ks + lk][wr * 64 + m * 16 + lr];
                 fb[m] = b1[ks + lk][wc * 64 + m * 16 + lr];
             }
+            if constexpr (F64) {
+                double da1[4], da2[4], db[4];
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    accr[m][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa1[m], fb[c], accr[m][c], 0, 0, 0);
-                    acci[m][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa2[m], fb[c], acci[m][c], 0, 0, 0);
+                for (int m = 0; m < 4; ++m) {
+                    da1[m] = double(fa1[m]);
+                    da2[m] = double(fa2[m]);
+                    db[m] = double(fb[m]);
                 }
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        accr[m][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(da1[m], db[c], accr[m][c], 0, 0, 0);
+                        acci[m][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(da2[m], db[c], acci[m][c], 0, 0, 0);
+                    }
+            } else {
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        accr[m][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa1[m], fb[c], accr[m][c], 0, 0, 0);
+                        acci[m][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa2[m], fb[c], acci[m][c], 0, 0, 0);
+                    }
+            }
         }
     }
-    // epilogue: block (m, c) element r of this lane is row 4*lk + r, column lr.
+    // epilogue: block (m, c) element r of this lane is row 4*lk + r (FP32
+    // accumulators) or row 4*r + lk (FP64 accumulators), column lr.
     // The output bits of the tile's 128 rows and 128 columns and the sign mask
     // of each row are tabulated once in the (now free) LDS staging area.
     __syncthreads();  // last chunk's fragments are read
@@ -141,14 +171,17 @@ k_combine_gemm(const float2 *__restrict__ A, const float2 *__restrict__ B, uint6
     for (int m = 0; m < 4; ++m) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const uint32_t il = wr * 64 + m * 16 + 4 * lk + r;
+            const uint32_t il = wr * 64 + m * 16 + (F64 ? 4 * r + lk : 4 * lk + r);
             const uint64_t xa = rowx[il], fm = rowf[il] & j0b;
             const uint32_t fl = uint32_t(rowf[il]) & 127u;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const uint32_t jl = wc * 64 + c * 16 + lr;
-                const float sgn = ((__popcll(fm) + __popc(fl & jl)) & 1) ? -1.f : 1.f;
-                out[xa | xb[c]] = make_float2(sgn * accr[m][c][r], sgn * acci[m][c][r]);
+                const bool neg = ((__popcll(fm) + __popc(fl & jl)) & 1) != 0;
+                double vr = double(accr[m][c][r]), vi = double(acci[m][c][r]);
+                if (neg) { vr = -vr; vi = -vi; }
+                if (out_c128) static_cast<double2 *>(out)[xa | xb[c]] = make_double2(vr, vi);
+                else static_cast<float2 *>(out)[xa | xb[c]] = make_float2(float(vr), float(vi));
             }
         }
     }
@@ -169,7 +202,7 @@ static int low_run(const uint8_t *pos, int n) {
 // the sign is symmetric), so the sides are exchanged when side A holds the
 // longer run of low output bits.
 hipError_t launch_combine_gemm(const float2 *A, const float2 *B, uint64_t nbr, const CombineArgs &P,
-                               float2 *out, hipStream_t s) {
+                               void *out, bool fp64, bool out_c128, hipStream_t s) {
     CombineArgs Q = P;
     const float2 *X = A, *Y = B;
     if (low_run(P.pos_a, P.na) > low_run(P.pos_b, P.nb) && P.na_blk <= 22) {
@@ -186,7 +219,8 @@ hipError_t launch_combine_gemm(const float2 *A, const float2 *B, uint64_t nbr, c
         std::memcpy(Q.fold_b, P.fold_a, sizeof(Q.fold_b));
     }
     const dim3 grid(unsigned(1ull << (Q.na_blk - 7)), unsigned(1ull << (Q.nb_blk - 7)));
-    hipLaunchKernelGGL(k_combine_gemm, grid, dim3(256), 0, s, X, Y, nbr, Q, out);
+    if (fp64) hipLaunchKernelGGL(k_combine_gemm<true>, grid, dim3(256), 0, s, X, Y, nbr, Q, out, out_c128 ? 1 : 0);
+    else hipLaunchKernelGGL(k_combine_gemm<false>, grid, dim3(256), 0, s, X, Y, nbr, Q, out, out_c128 ? 1 : 0);
     return hipGetLastError();
 }
 

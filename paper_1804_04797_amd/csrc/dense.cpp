@@ -241,7 +241,7 @@ namespace {
 qsv_status dense_prepare(const qsv_circuit *c, int lb, int le, int k, uint64_t branch,
                          std::shared_ptr<DensePlan> &out) {
     if (!c) return fail(QSV_EINVAL, "dense: null circuit");
-    if (k != 4 && k != 5 && k != 6) return fail(QSV_EUNSUPPORTED, "dense: k must be 4, 5 or 6");
+    if (k < 4 || k > 7) return fail(QSV_EUNSUPPORTED, "dense: k must be 4..7");
     if (c->n < k + 6) return fail(QSV_EUNSUPPORTED, "dense: needs n >= k + 6");
     qsv_circuit *cc = const_cast<qsv_circuit *>(c);
     std::lock_guard<std::mutex> g(cc->mu);

@@ -991,6 +991,57 @@ std::string program_key(const Plan &plan, int variant) {
 }
 double g_total_compile_s = 0;
 
+// 64-bit FNV-1a hash (Fowler, Noll, Vo) of a byte string.
+uint64_t fnv1a(const void *p, size_t n, uint64_t h = 0xcbf29ce484222325ull) {
+    const unsigned char *b = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+// On-disk cache of compiled code objects (QSV_JIT_CACHE=<directory>): a
+// code object is stored under the hash of its source text and the compiler
+// options, so a later process loads it instead of compiling it again.
+std::string cache_path(const std::string &src, const char *const *opts, size_t nopt) {
+    const char *dir = std::getenv("QSV_JIT_CACHE");
+    if (!dir || !dir[0]) return std::string();
+    uint64_t h = fnv1a(src.data(), src.size());
+    for (size_t i = 0; i < nopt; ++i) h = fnv1a(opts[i], std::strlen(opts[i]), h);
+    char name[64];
+    std::snprintf(name, sizeof name, "/qsv_%016llx.co", (unsigned long long)h);
+    return std::string(dir) + name;
+}
+
+bool read_file(const std::string &path, std::vector<char> &out) {
+    FILE *f = std::fopen(path.c_str(), "rb");
+    if (!f) return false;
+    std::fseek(f, 0, SEEK_END);
+    const long n = std::ftell(f);
+    std::fseek(f, 0, SEEK_SET);
+    bool ok = n > 0;
+    if (ok) {
+        out.resize(size_t(n));
+        ok = std::fread(out.data(), 1, size_t(n), f) == size_t(n);
+    }
+    std::fclose(f);
+    return ok;
+}
+
+void write_file_atomically(const std::string &path, const std::vector<char> &data) {
+    char suffix[32];
+    std::snprintf(suffix, sizeof suffix, ".tmp%llx",
+                  (unsigned long long)std::hash<std::thread::id>()(std::this_thread::get_id()));
+    const std::string tmp = path + suffix;
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return;
+    const bool ok = std::fwrite(data.data(), 1, data.size(), f) == data.size();
+    std::fclose(f);
+    if (ok) std::rename(tmp.c_str(), path.c_str());
+    else std::remove(tmp.c_str());
+}
+
 qsv_status compile_source(const std::string &src, std::vector<char> &code, std::string &log) {
     if (const char *dump = std::getenv("QSV_JIT_DUMP")) {  // debugging aid: keep the source
         if (FILE *f = std::fopen(dump, "w")) {
@@ -998,14 +1049,17 @@ qsv_status compile_source(const std::string &src, std::vector<char> &code, std::
             std::fclose(f);
         }
     }
+    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17",
+                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                          "-mllvm", "-simplifycfg-sink-common=false"};
+    const size_t nopt = sizeof(opts) / sizeof(opts[0]);
+    const std::string cached = cache_path(src, opts, nopt);
+    if (!cached.empty() && read_file(cached, code)) return QSV_OK;
     hiprtcProgram prog;
     if (hiprtcCreateProgram(&prog, src.c_str(), "qsv_pass.hip", 0, nullptr, nullptr) !=
         HIPRTC_SUCCESS)
         return fail(QSV_EINTERNAL, "hiprtcCreateProgram failed");
-    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17",
-                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                          "-mllvm", "-simplifycfg-sink-common=false"};
-    hiprtcResult r = hiprtcCompileProgram(prog, int(sizeof(opts) / sizeof(opts[0])), opts);
+    hiprtcResult r = hiprtcCompileProgram(prog, int(nopt), opts);
     size_t ls = 0;
     hiprtcGetProgramLogSize(prog, &ls);
     log.assign(ls, '\0');
@@ -1019,6 +1073,7 @@ qsv_status compile_source(const std::string &src, std::vector<char> &code, std::
     code.resize(cs);
     hiprtcGetCode(prog, code.data());
     hiprtcDestroyProgram(&prog);
+    if (!cached.empty()) write_file_atomically(cached, code);
     return QSV_OK;
 }
 
@@ -1073,6 +1128,9 @@ qsv_status jit_compile_only(const Plan &plan, size_t *code_bytes, double *second
     st = compile_source(jit_source(plan, &lds, kJitInit | 2 | kJitDot | kJitLoop), code, log);
     if (st != QSV_OK) return st;
     st = compile_source(jit_source(plan, &lds, kJitSample), code, log);  // sampling last pass
+    if (st != QSV_OK) return st;
+    // the batched form (entry table per grid row), from |+> as batches run it
+    st = compile_source(jit_source(plan, &lds, kJitBatched | kJitInit | 1), code, log);
     if (st != QSV_OK) return st;
     std::string src = jit_source(plan, &lds, kJitInit | 1 | kJitNorm);
     st = compile_source(src, code, log);
@@ -1148,12 +1206,14 @@ qsv_status jit_prepare(Plan &plan, int variant) {
 qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, uint64_t branch,
                       uint64_t basis, double *part, hipStream_t s, std::vector<float> *pass_ms,
                       const void *src0, const void *dot_other, const SampleTab *sample_tab,
-                      uint64_t sample_tiles, void *sample_out, uint64_t sample_rows, uint64_t sample_stride) {
+                      uint64_t sample_tiles, void *sample_out, uint64_t sample_rows, uint64_t sample_stride,
+                      uint64_t max_tiles) {
     auto vit = plan.jit_variants.find(variant);
     if (vit == plan.jit_variants.end()) return fail(QSV_EINTERNAL, "jit variant not prepared");
     const CacheEntry &e = *static_cast<const CacheEntry *>(vit->second.get());
     const int L = plan.R + plan.T;
-    const uint64_t tiles = 1ull << (plan.n - L);
+    const uint64_t all_tiles = 1ull << (plan.n - L);
+    const uint64_t tiles = (max_tiles && max_tiles < all_tiles) ? max_tiles : all_tiles;
     const uint64_t chunk = 1ull << 30;
     const size_t np = plan.passes.size();
     if (plan.oop && (!scratch || (!(variant & kJitInit) && !src0 && np % 2)))

@@ -47,6 +47,7 @@ qsv_status jit_prepare(Plan &plan, int variant);
 // `branch` with the bits of y deposited on the set bits of `basis`, and
 // writes at sample_out + y * sample_stride (the earlier passes, if any, run
 // for `branch` only, so callers use rows with one-pass plans).
+// max_tiles > 0: each pass runs only its first max_tiles tiles (timing).
 struct SampleTab {  // device layout read by the sampling pass
     const uint64_t *tiles;   // tile index of workgroup b
     const uint32_t *start;   // entries of workgroup b: [start[b], start[b + 1])
@@ -58,7 +59,7 @@ qsv_status jit_launch(const Plan &plan, int variant, void *amps, void *scratch, 
                       std::vector<float> *pass_ms = nullptr, const void *src0 = nullptr,
                       const void *dot_other = nullptr, const SampleTab *sample_tab = nullptr,
                       uint64_t sample_tiles = 0, void *sample_out = nullptr, uint64_t sample_rows = 1,
-                      uint64_t sample_stride = 0);
+                      uint64_t sample_stride = 0, uint64_t max_tiles = 0);
 // Launch all passes over `count` batch entries (BatchEntry table on the device).
 qsv_status jit_launch_batched(const Plan &plan, int variant, const void *ents, unsigned count,
                               hipStream_t s);

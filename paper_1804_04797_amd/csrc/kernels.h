@@ -13,6 +13,15 @@ hipError_t launch_fused(float2 *amps, int n, int R, int T, const PassProg &p, ui
 hipError_t launch_fused_batch(int R, int T, const BatchSeg *segs, int nseg, const BatchEntry *ents,
                               const PassProg *progs, int round, uint64_t blocks, int init_plus,
                               hipStream_t s);
+// One persistent launch over every work item of a tile shape's rounds (see
+// BatchRound).  resident != NULL: only report the workgroups the device holds
+// at once (no launch).  abort: pinned host flag the waits poll; wait_us:
+// longest wait of one work item before it gives up.
+hipError_t launch_fused_persistent(int R, int T, const BatchRound *rounds, int nrounds, const BatchSeg *segs,
+                                   uint64_t total, const BatchEntry *ents, const PassProg *progs, int init_plus,
+                                   uint32_t *done, unsigned long long *next, uint32_t *err, const uint32_t *abort,
+                                   uint32_t wait_us, unsigned grid, hipStream_t s, unsigned *resident);
+hipError_t launch_zero_u32(uint32_t *p, uint64_t count, hipStream_t s);
 hipError_t launch_gather_batch(const BatchEntry *ents, uint64_t count, const uint64_t *xs,
                                uint64_t m, float2 *out, hipStream_t s);
 hipError_t launch_dense(float2 *amps, int n, int k, const int *qubits, const float *mat_t,
@@ -27,6 +36,8 @@ hipError_t launch_gather(const float2 *amps, int n, const uint64_t *xs, uint64_t
 hipError_t launch_gather_c128(const void *amps, int n, const uint64_t *xs, uint64_t m, void *out,
                               hipStream_t s);
 hipError_t launch_norm(const float2 *amps, int n, double *out, double *partials, hipStream_t s);
+// partial sums launch_norm writes for a state of 2^n amplitudes (at most 65536)
+size_t norm_partial_count(int n);
 // <a|b> in FP64 into out[0] (re), out[1] (im); partials: 2 * 65536 doubles
 hipError_t launch_dot(const float2 *a, const float2 *b, int n, double *out, double *partials,
                       hipStream_t s);
@@ -44,9 +55,13 @@ struct CombineArgs {
     uint8_t pos_a[64], pos_b[64];
     uint8_t fold_a[64], fold_b[64];
 };
+// fp64: FP64 products and sums (else FP32 accumulation); out_c128: out is
+// complex128 (else complex64)
 hipError_t launch_combine_gemm(const float2 *A, const float2 *B, uint64_t nbr, const CombineArgs &P,
-                               float2 *out, hipStream_t s);
+                               void *out, bool fp64, bool out_c128, hipStream_t s);
 hipError_t launch_sum_partials(const double *part, uint64_t count, double *out, hipStream_t s);
+// dst = src, bytes a multiple of 16, both 16-byte aligned
+hipError_t launch_stream_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s);
 hipError_t launch_branch_combine(const float2 *A, const float2 *B, uint64_t nb, uint64_t m,
                                  const int8_t *sign, double2 *out, hipStream_t s);
 

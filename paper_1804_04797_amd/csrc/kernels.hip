@@ -6,6 +6,7 @@
 // (2^34 amplitudes exceed 32 bits).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 
@@ -343,6 +344,72 @@ k_fused_batch(const BatchSeg *__restrict__ segs, int nseg, const BatchEntry *__r
                      en.init_val, lds);
 }
 
+// Persistent form of a batch's generic tile passes: one launch for every
+// pass round of every entry of one tile shape.  Workgroups take work items
+// (round, entry, tile) in order from *next (batch_decode); an item of round
+// r > 0 first waits until done[entry] reaches r * tiles(entry), i.e. until
+// every tile of the entry's earlier passes is stored.  The device has one L2
+// per XCD, so the counters are updated and polled with system-scope atomics
+// (performed past the XCD caches), a tile's stores are written back
+// (system-scope release fence of every wave) before its entry's counter is
+// raised, and the waiting workgroup invalidates its caches (acquire fence)
+// once the counter has reached its target, before any wave loads.  Every
+// wait is bounded in time: after wait_ticks ticks of the constant-rate
+// device clock, or when the host sets *abort (pinned host memory, polled
+// every 256 tries), the workgroup records the failure in *err and goes on,
+// so the launch always drains within a bounded time.
+template <int R, int T>
+__global__ void __launch_bounds__(1 << T)
+k_fused_persistent(const BatchRound *__restrict__ rounds, int nrounds, const BatchSeg *__restrict__ segs,
+                   uint64_t total, const BatchEntry *__restrict__ ents, const PassProg *__restrict__ progs,
+                   int init_plus, uint32_t *done, unsigned long long *next, uint32_t *err,
+                   const volatile uint32_t *abort, uint64_t wait_ticks) {
+    extern __shared__ float2 lds[];
+    __shared__ unsigned long long item_s;
+    constexpr int L = R + T;
+    for (;;) {
+        if (threadIdx.x == 0)
+            item_s = __hip_atomic_fetch_add(next, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __syncthreads();
+        const uint64_t item = item_s;
+        __syncthreads();  // every wave has the item before it is overwritten
+        if (item >= total) break;
+        int r = 0;
+        uint32_t e = 0;
+        uint64_t tile = 0;
+        batch_decode(rounds, nrounds, segs, item, &r, &e, &tile);
+        const BatchEntry en = ents[e];
+        if (r > 0) {
+            if (threadIdx.x == 0) {
+                const uint32_t need = uint32_t(r) << (en.n - L);
+                const uint64_t t0 = wall_clock64();
+                for (uint32_t k = 1;
+                     __hip_atomic_load(done + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) < need; ++k) {
+                    if (wall_clock64() - t0 > wait_ticks || ((k & 255u) == 0 && *abort)) {
+                        __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            __syncthreads();
+            __atomic_thread_fence(__ATOMIC_ACQUIRE);  // system scope: drop stale cached lines
+        }
+        fused_tile<R, T>(reinterpret_cast<float2 *>(en.amps), progs[en.prog0 + r], en.branch, tile,
+                         (init_plus && r == 0) ? 1 : 0, en.init_val, lds);
+        __threadfence_system();  // this wave's stores are written back
+        __syncthreads();         // ... for every wave of the tile
+        if (threadIdx.x == 0) __hip_atomic_fetch_add(done + e, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// Clears the counters of a persistent batch launch (a kernel, not a memset:
+// it is replayed inside the batch's graph).
+__global__ void __launch_bounds__(256) k_zero_u32(uint32_t *__restrict__ p, uint64_t count) {
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0u;
+}
+
 // Gather for every entry of a batch: out[e*m + k] = amps_e[xs[e*m + k]].
 __global__ void __launch_bounds__(256)
 k_gather_batch(const BatchEntry *__restrict__ ents, uint64_t count, const uint64_t *__restrict__ xs,
@@ -370,6 +437,8 @@ struct DenseArgs {
     uint8_t glob_bits[48];     // tile index bit i -> physical bit
     uint8_t phys[16];          // tile local bit i -> physical bit
     uint8_t sub[16];           // position of local bit i within the row or column index
+    uint8_t sub_row[8];        // row index bit b -> tile local bit
+    uint8_t sub_col[8];        // column index bit b -> tile local bit
     uint16_t rowmask;          // local bits that belong to the row index
     int32_t n_glob;
 };
@@ -468,6 +537,142 @@ k_dense(float2 *__restrict__ amps, const float *__restrict__ mat_t, const DenseA
     }
 }
 
+// Dense block for k = 6, 7: Y = M X with the 2^k x 2^k matrix M held in
+// registers.  Wave w of a workgroup owns output rows [16 w, 16 w + 16) (its
+// strip of Mr and Mi, 2^k / 2 registers per lane, loaded once) and computes
+// them for a tile of 64 columns: Yr = Mr Xr - Mi Xi and Yi = Mr Xi + Mi Xr on
+// v_mfma_f32_16x16x4f32 (FP32 accumulation), the X tile staged in LDS as
+// separate re/im planes with a row stride of 80 floats (the 4 rows one
+// MFMA operand read covers fall on distinct bank groups).  Persistent
+// workgroups walk the tiles; the next tile's 16-byte global loads are issued
+// into registers before the current tile's matrix-core work, and each wave
+// stores its outputs straight from the accumulators.  pair_cols: column
+// index bit 0 is physical bit 0, so a 16-byte access holds columns 2c and
+// 2c + 1 (otherwise 8-byte accesses).
+template <int K>
+__global__ void __launch_bounds__(64 * (1 << K) / 16)
+k_dense_strip(float2 *__restrict__ amps, const float *__restrict__ mat_t, const DenseArgs A, int pair_cols) {
+    constexpr int DIM = 1 << K;
+    constexpr int WAVES = DIM / 16;
+    constexpr int NT = 64 * WAVES;          // threads
+    constexpr int COLS = 64;
+    constexpr int XS = 80;                   // row stride of the X planes (floats)
+    constexpr int KS = DIM / 4;              // k-steps of 4
+    constexpr int PAIRS = DIM * COLS / 2;    // column pairs of a tile
+    constexpr int PER = PAIRS / NT;          // pairs per thread (8)
+    static_assert(PER * NT == PAIRS, "tile split");
+    __shared__ float xr[DIM * XS], xi[DIM * XS];
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+    const uint32_t lr = lane & 15u, lk = lane >> 4;
+    // this wave's strip of M: A operand of k-step ks, lane (k % 4) * 16 + i
+    float mr[KS], mi[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const uint32_t k = uint32_t(ks) * 4u + lk, row = w * 16u + lr;
+        mr[ks] = mat_t[k * DIM + row];
+        mi[ks] = mat_t[DIM * DIM + k * DIM + row];
+    }
+    // physical offsets of tile-local row and column indices
+    auto row_off = [&](uint32_t row) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int b = 0; b < K; ++b)
+            if ((row >> b) & 1u) o |= 1ull << A.phys[A.sub_row[b]];
+        return o;
+    };
+    auto col_off = [&](uint32_t col) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int b = 0; b < 6; ++b)
+            if ((col >> b) & 1u) o |= 1ull << A.phys[A.sub_col[b]];
+        return o;
+    };
+    // load assignment: pair p = it * NT + t -> row p / 32, column pair p % 32
+    uint64_t loff[PER];
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+        const uint32_t p = uint32_t(it) * NT + t, row = p >> 5, cp = p & 31u;
+        loff[it] = row_off(row) | col_off(2u * cp);
+    }
+    // store offsets: row 16 w + 4 lk + r, column 16 c + lr
+    uint64_t srow[4], scol[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) srow[r] = row_off(w * 16u + 4u * lk + uint32_t(r));
+#pragma unroll
+    for (int c = 0; c < 4; ++c) scol[c] = col_off(uint32_t(c) * 16u + lr);
+    const uint64_t c1 = col_off(1u);  // physical offset of column bit 0
+    v4f nx[PER];
+    auto fetch = [&](uint64_t tile) {
+        uint64_t base = 0;
+        for (int i = 0; i < A.n_glob; ++i) base |= ((tile >> i) & 1ull) << A.glob_bits[i];
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            if (pair_cols) {
+                nx[it] = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(amps + (base | loff[it])));
+            } else {
+                const float2 a = amps[base | loff[it]], b = amps[base | loff[it] | c1];
+                nx[it] = v4f{a.x, a.y, b.x, b.y};
+            }
+        }
+    };
+    uint64_t tile = blockIdx.x;
+    if (tile < A.tiles) fetch(tile);
+    for (; tile < A.tiles; tile += gridDim.x) {
+        uint64_t base = 0;
+        for (int i = 0; i < A.n_glob; ++i) base |= ((tile >> i) & 1ull) << A.glob_bits[i];
+        __syncthreads();  // the previous tile's LDS reads are complete
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const uint32_t p = uint32_t(it) * NT + t, row = p >> 5, cp = p & 31u;
+            *reinterpret_cast<float2 *>(&xr[row * XS + 2 * cp]) = make_float2(nx[it].x, nx[it].z);
+            *reinterpret_cast<float2 *>(&xi[row * XS + 2 * cp]) = make_float2(nx[it].y, nx[it].w);
+        }
+        __syncthreads();
+        if (tile + gridDim.x < A.tiles) fetch(tile + gridDim.x);  // in flight during the MFMA work
+        v4f arr[4], aii[4], ai[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) { arr[c] = v4f{0, 0, 0, 0}; aii[c] = arr[c]; ai[c] = arr[c]; }
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const uint32_t krow = uint32_t(ks) * 4u + lk;
+            float br[4], bi[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                br[c] = xr[krow * XS + uint32_t(c) * 16u + lr];
+                bi[c] = xi[krow * XS + uint32_t(c) * 16u + lr];
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                arr[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(mr[ks], br[c], arr[c], 0, 0, 0);
+                aii[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(mi[ks], bi[c], aii[c], 0, 0, 0);
+                ai[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(mr[ks], bi[c], ai[c], 0, 0, 0);
+                ai[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(mi[ks], br[c], ai[c], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                amps[base | srow[r] | scol[c]] = make_float2(arr[c][r] - aii[c][r], ai[c][r]);
+    }
+}
+
+template <int K>
+hipError_t launch_dense_strip_t(float2 *amps, const float *mat_t, const DenseArgs &A, int pair_cols,
+                                hipStream_t s) {
+    constexpr int NT = 64 * (1 << K) / 16;
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(&k_dense_strip<K>), NT, 0);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const uint64_t resident = uint64_t(std::max(1, per_cu)) * uint64_t(std::max(1, cus));
+    const uint64_t grid = A.tiles < resident ? A.tiles : resident;
+    hipLaunchKernelGGL((k_dense_strip<K>), dim3(unsigned(grid)), dim3(NT), 0, s, amps, mat_t, A, pair_cols);
+    return hipGetLastError();
+}
+
 template <int K>
 hipError_t launch_dense_t(float2 *amps, int n, const int *qubits, const float *mat_t,
                           hipStream_t s) {
@@ -502,9 +707,19 @@ hipError_t launch_dense_t(float2 *amps, int n, const int *qubits, const float *m
     A.n_glob = g;
     A.tiles = 1ull << (n - K - 6);
     (void)ri;
-    const uint64_t grid = A.tiles < 1024 ? A.tiles : 1024;
-    hipLaunchKernelGGL((k_dense<K>), dim3(unsigned(grid)), dim3(256), 0, s, amps, mat_t, A);
-    return hipGetLastError();
+    for (int l = 0; l < K + 6; ++l) {
+        if ((A.rowmask >> l) & 1u) A.sub_row[A.sub[l]] = uint8_t(l);
+        else A.sub_col[A.sub[l]] = uint8_t(l);
+    }
+    if constexpr (K >= 6) {
+        // column bit 0 is physical bit 0 when qubit 0 is outside the block
+        const int pair_cols = (qmask & 1ull) ? 0 : 1;
+        return launch_dense_strip_t<K>(amps, mat_t, A, pair_cols, s);
+    } else {
+        const uint64_t grid = A.tiles < 1024 ? A.tiles : 1024;
+        hipLaunchKernelGGL((k_dense<K>), dim3(unsigned(grid)), dim3(256), 0, s, amps, mat_t, A);
+        return hipGetLastError();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -759,6 +974,28 @@ k_branch_combine(const float2 *__restrict__ A, const float2 *__restrict__ B, uin
     }
 }
 
+// Streaming copy with the sweep's access pattern (16-byte nontemporal loads
+// and stores, 8 in flight per thread): the HBM rate a pass that does no
+// arithmetic would reach, the ceiling the fused passes are compared with.
+__global__ void __launch_bounds__(256)
+k_stream_copy(const v4f *__restrict__ src, v4f *__restrict__ dst, uint64_t count) {
+    constexpr int U = 8;
+    const uint64_t stride = uint64_t(gridDim.x) * 256u * U;
+    for (uint64_t base = uint64_t(blockIdx.x) * 256u * U + threadIdx.x; base < count; base += stride) {
+        v4f w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = base + uint64_t(u) * 256u;
+            if (i < count) w[u] = __builtin_nontemporal_load(src + i);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = base + uint64_t(u) * 256u;
+            if (i < count) __builtin_nontemporal_store(w[u], dst + i);
+        }
+    }
+}
+
 unsigned grid_for(uint64_t work, unsigned per_block = 256, unsigned cap = 1u << 20) {
     uint64_t g = (work + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -809,7 +1046,68 @@ hipError_t launch_fused_batch_t(const BatchSeg *segs, int nseg, const BatchEntry
     return hipGetLastError();
 }
 
+template <int R, int T>
+hipError_t launch_fused_persistent_t(const BatchRound *rounds, int nrounds, const BatchSeg *segs, uint64_t total,
+                                     const BatchEntry *ents, const PassProg *progs, int init_plus, uint32_t *done,
+                                     unsigned long long *next, uint32_t *err, const uint32_t *abort,
+                                     uint32_t wait_us, unsigned grid, hipStream_t s, unsigned *resident) {
+    constexpr int L = R + T;
+    const size_t lds = (size_t(1) << L) * sizeof(float2) + (size_t(1) << T) * sizeof(float2);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fused_persistent<R, T>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    if (resident) {  // workgroups the device holds at once
+        int per_cu = 0, dev = 0, cus = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(&k_fused_persistent<R, T>), 1 << T, lds);
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        *resident = unsigned(std::max(1, per_cu) * std::max(1, cus));
+        return hipSuccess;
+    }
+    if (total == 0 || grid == 0) return hipSuccess;
+    int dev = 0, khz = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess) return e;
+    const uint64_t wait_ticks = uint64_t(wait_us) * uint64_t(khz > 0 ? khz : 100000) / 1000u;
+    hipLaunchKernelGGL((k_fused_persistent<R, T>), dim3(grid), dim3(1 << T), lds, s, rounds, nrounds, segs, total,
+                       ents, progs, init_plus, done, next, err, reinterpret_cast<const volatile uint32_t *>(abort),
+                       wait_ticks);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_fused_persistent(int R, int T, const BatchRound *rounds, int nrounds, const BatchSeg *segs,
+                                   uint64_t total, const BatchEntry *ents, const PassProg *progs, int init_plus,
+                                   uint32_t *done, unsigned long long *next, uint32_t *err, const uint32_t *abort,
+                                   uint32_t wait_us, unsigned grid, hipStream_t s, unsigned *resident) {
+#define QSV_PERSIST(RR, TT)                                                                                     \
+    case RR * 16 + TT:                                                                                          \
+        return launch_fused_persistent_t<RR, TT>(rounds, nrounds, segs, total, ents, progs, init_plus, done, next, \
+                                                 err, abort, wait_us, grid, s, resident);
+    switch (R * 16 + T) {
+        QSV_PERSIST(5, 9)
+        QSV_PERSIST(5, 8)
+        QSV_PERSIST(4, 8)
+        QSV_PERSIST(5, 7)
+        QSV_PERSIST(4, 7)
+    default: return hipErrorInvalidValue;
+    }
+#undef QSV_PERSIST
+}
+
+hipError_t launch_zero_u32(uint32_t *p, uint64_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(count, 256, 1024)), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
 
 hipError_t launch_fused_batch(int R, int T, const BatchSeg *segs, int nseg, const BatchEntry *ents,
                               const PassProg *progs, int round, uint64_t blocks, int init_plus,
@@ -819,6 +1117,7 @@ hipError_t launch_fused_batch(int R, int T, const BatchSeg *segs, int nseg, cons
     case 4 * 16 + 8: return launch_fused_batch_t<4, 8>(segs, nseg, ents, progs, round, blocks, init_plus, s);
     case 5 * 16 + 7: return launch_fused_batch_t<5, 7>(segs, nseg, ents, progs, round, blocks, init_plus, s);
     case 4 * 16 + 7: return launch_fused_batch_t<4, 7>(segs, nseg, ents, progs, round, blocks, init_plus, s);
+    case 5 * 16 + 9: return launch_fused_batch_t<5, 9>(segs, nseg, ents, progs, round, blocks, init_plus, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -837,6 +1136,7 @@ hipError_t launch_dense(float2 *amps, int n, int k, const int *qubits, const flo
     case 4: return launch_dense_t<4>(amps, n, qubits, mat_t, s);
     case 5: return launch_dense_t<5>(amps, n, qubits, mat_t, s);
     case 6: return launch_dense_t<6>(amps, n, qubits, mat_t, s);
+    case 7: return launch_dense_t<7>(amps, n, qubits, mat_t, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -926,16 +1226,22 @@ hipError_t launch_gather_c128(const void *amps, int n, const uint64_t *xs, uint6
     return hipGetLastError();
 }
 
+size_t norm_partial_count(int n) {
+    if (n < 14) return 0;
+    // log2(blocks) so that each block has 1024 quads, at most 65536 blocks
+    const int lb = n - 1 - 10 > 16 ? 16 : n - 1 - 10;
+    return size_t(1) << lb;
+}
+
 hipError_t launch_norm(const float2 *amps, int n, double *out, double *partials, hipStream_t s) {
     const uint64_t dim = 1ull << n;
     if (n < 14) {
         hipLaunchKernelGGL(k_norm_small, dim3(1), dim3(256), 0, s, amps, dim, out);
         return hipGetLastError();
     }
-    // at most 65536 blocks; each block a contiguous chunk of >= 2^13 quads
-    int lb = n - 1 - 10;           // log2(blocks) so that each block has 1024 quads
-    if (lb > 16) lb = 16;
-    const unsigned blocks = 1u << lb;
+    // at most 65536 blocks; each block a contiguous chunk of >= 1024 quads
+    const unsigned blocks = unsigned(norm_partial_count(n));
+    const int lb = __builtin_ctz(blocks);
     const uint64_t qpb = (dim / 2) >> lb;
     hipLaunchKernelGGL(k_norm_partial, dim3(blocks), dim3(256), 0, s,
                        reinterpret_cast<const float4 *>(amps), qpb, partials);
@@ -959,6 +1265,18 @@ hipError_t launch_dot(const float2 *a, const float2 *b, int n, double *out, doub
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, partials, uint64_t(blocks), out);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, partials + blocks, uint64_t(blocks),
                        out + 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s) {
+    const uint64_t count = bytes / 16;
+    if (count == 0) return hipSuccess;
+    // 8 workgroups of 256 threads per CU on 256 CUs, each thread 8 x 16 B in flight
+    const uint64_t per_block = 256u * 8u;
+    uint64_t grid = (count + per_block - 1) / per_block;
+    if (grid > 2048) grid = 2048;
+    hipLaunchKernelGGL(k_stream_copy, dim3(unsigned(grid)), dim3(256), 0, s, static_cast<const v4f *>(src),
+                       static_cast<v4f *>(dst), count);
     return hipGetLastError();
 }
 

@@ -597,17 +597,21 @@ qsv_status build_plan_weighted(const qsv_circuit &c, int lb, int le, TileShape s
         for (size_t i = 0; i < tq.size(); ++i) P.glob_st[i] = uint8_t(nphys[tq[i]]);
 
         total_phase = (total_phase + phase) & 7;
-        // Intermediate passes apply the exact power of two of the removed
-        // 2^{-m/2}; an odd half power is carried to the pass that applies the
-        // last gates, which also applies the accumulated phase, so at most
-        // one inexact factor is rounded per call.
+        // The removed factors 2^{-1/2} are applied by the pass that applies
+        // the last gates, together with the accumulated phase, so at most one
+        // inexact factor is rounded per call.  Until then the state between
+        // passes is the true state times 2^{carry_half/2} (true amplitudes
+        // have modulus <= 1): powers of two scale FP32 values exactly, so
+        // deferring them changes no rounding and saves each intermediate
+        // pass a multiply of every amplitude.  Only when the deferred growth
+        // would pass 2^60 does an intermediate pass apply its even part.
         carry_half += m_nd;
         const bool last_gates = (n_done == NG) && !final_scaled;
-        double mag;
+        double mag = 1.0;
         if (last_gates) {
             mag = std::pow(2.0, -0.5 * carry_half);
             carry_half = 0;
-        } else {
+        } else if (carry_half > 120) {
             mag = std::ldexp(1.0, -(carry_half / 2));
             carry_half &= 1;
         }

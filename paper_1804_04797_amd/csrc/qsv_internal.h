@@ -18,7 +18,7 @@ namespace qsv {
 constexpr int kMaxQubits = 34;   // 2^34 complex64 = 128 GiB per state
 constexpr int kBatchMinQubits = 11;  // smallest state of a batch (tile 2^(4+7))
 constexpr int kMaxSlots = 16;    // register + thread slots of one tile
-constexpr int kMaxOps = 192;     // op words per pass program (kernel argument)
+constexpr int kMaxOps = 384;     // op words per pass program (kernel argument)
 
 // Opcodes of a pass program.  Each op is one 64-bit word; XCHG is followed by
 // one extra word holding the slot permutation.
@@ -71,10 +71,49 @@ struct BatchEntry {
     uint32_t pad;
 };
 struct BatchSeg {
-    uint64_t start;     // first block of the segment in its round's launch
+    uint64_t start;     // first block (work item) of the segment within its round
     uint32_t entry;
     uint32_t pad;
 };
+
+// Persistent batch launch (one per tile shape of the generic kernel): work
+// items are ordered by pass round, then by entry, then by tile; a workgroup
+// takes the next item from a device counter.  Item i of round r is tile
+// (i - item_start - seg.start) of entry seg.entry, for the round's last
+// segment with start <= i - item_start.  An item of round r > 0 waits until
+// its entry has completed r * tiles(entry) items (every tile of its earlier
+// passes); it only ever waits on items taken before it, which are held by
+// running workgroups, so the launch cannot deadlock.
+struct BatchRound {
+    uint64_t item_start;  // first item of the round
+    uint32_t seg_off;     // its segments in the segment table
+    uint32_t nseg;
+};
+
+#if defined(__HIP__)
+#define QSV_HD __host__ __device__
+#else
+#define QSV_HD
+#endif
+// Work item -> (round, entry, tile); items < total items of the launch.
+QSV_HD inline void batch_decode(const BatchRound *rounds, int nrounds, const BatchSeg *segs, uint64_t item,
+                                int *round, uint32_t *entry, uint64_t *tile) {
+    int lo = 0, hi = nrounds - 1;
+    while (lo < hi) {  // last round with item_start <= item
+        const int mid = (lo + hi + 1) >> 1;
+        if (rounds[mid].item_start <= item) lo = mid; else hi = mid - 1;
+    }
+    const uint64_t local = item - rounds[lo].item_start;
+    const BatchSeg *sg = segs + rounds[lo].seg_off;
+    int a = 0, b = int(rounds[lo].nseg) - 1;
+    while (a < b) {  // last segment with start <= local
+        const int mid = (a + b + 1) >> 1;
+        if (sg[mid].start <= local) a = mid; else b = mid - 1;
+    }
+    *round = lo;
+    *entry = sg[a].entry;
+    *tile = local - sg[a].start;
+}
 
 struct Pass {
     PassProg prog;
@@ -134,8 +173,9 @@ struct qsv_circuit {
 
 namespace qsv {
 
-// error reporting (capi.cpp)
+// error reporting and the device check (capi.cpp)
 qsv_status fail(qsv_status s, const std::string &msg);
+qsv_status check_gfx950();  // QSV_EUNSUPPORTED unless the current device is gfx950
 
 // circuit.cpp
 bool gate_is_diagonal(uint8_t kind);
@@ -167,8 +207,11 @@ qsv_batch **partition_batch(qsv_partition *p, void ***ws);
 // tune.cpp: the shape sv_tune picked for this circuit and layer range, if any
 bool tuned_opts(const qsv_circuit *c, int lb, int le, qsv_fuse_opts *out);
 // capi.cpp: per-pass times of the compiled sweep from |+>^n (for the tuner)
+// max_tiles > 0: every pass runs only its first max_tiles tiles (timing
+// on a sample of a large state; the result is not the sweep's)
 qsv_status time_sweep_passes(const qsv_circuit *c, int lb, int le, const qsv_fuse_opts *opts,
-                             void *amps, hipStream_t s, std::vector<float> &ms);
+                             void *amps, void *workspace, size_t ws_bytes, hipStream_t s,
+                             uint64_t max_tiles, std::vector<float> &ms);
 
 // dense.cpp
 qsv_status build_dense_plan(const qsv_circuit &c, int lb, int le, int k, uint64_t branch,

@@ -6,12 +6,16 @@
 // fewer workgroups per CU.  The tuner plans the circuit for each candidate
 // shape, drops candidates whose pass count is not within one of the best,
 // times the rest on the device (the sweep as sv_simulate runs it, on the
-// caller's scratch state), then the persistent kernel form of the fastest
-// three, and remembers the fastest options per circuit content.  Calls with
-// opts == NULL use them.
+// caller's scratch state and workspace; above 2^30 amplitudes on a sample of
+// the tiles), then the persistent kernel form of the fastest three, and
+// remembers the fastest options per circuit content.  Calls with opts == NULL
+// use them.  With QSV_TUNE_CACHE=<file> the choices are also kept on disk and
+// a later process takes them from there instead of timing again.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -46,6 +50,62 @@ TuneKey key_of(const qsv_circuit *c, int lb, int le) {
     return k;
 }
 
+// Persistent tuning results (QSV_TUNE_CACHE=<file>): one line per tuned
+// circuit and layer range, "<key> R T c jit out_of_place pass_forms ms",
+// the key a 64-bit FNV-1a hash (Fowler, Noll, Vo) of the qubit count, the
+// layer range, the gate list and the device (architecture, compute units).
+uint64_t fnv1a(const void *p, size_t n, uint64_t h = 0xcbf29ce484222325ull) {
+    const unsigned char *b = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+uint64_t disk_key(const qsv_circuit *c, int lb, int le) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::memset(&prop, 0, sizeof(prop));
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipGetDeviceProperties(&prop, dev);
+    const int head[4] = {c->n, lb, le, prop.multiProcessorCount};
+    uint64_t h = fnv1a(head, sizeof(head));
+    h = fnv1a(prop.gcnArchName, std::strlen(prop.gcnArchName), h);
+    return fnv1a(c->gates.data(), c->gates.size() * sizeof(qsv_gate), h);
+}
+
+bool disk_lookup(uint64_t key, qsv_fuse_opts *out, double *ms) {
+    const char *path = std::getenv("QSV_TUNE_CACHE");
+    if (!path || !path[0]) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    unsigned long long k;
+    int R, T, cl, jit, oop;
+    unsigned forms;
+    double t;
+    while (std::fscanf(f, "%llx %d %d %d %d %d %u %lf", &k, &R, &T, &cl, &jit, &oop, &forms, &t) == 8) {
+        if (k != key) continue;
+        *out = qsv_fuse_opts{R, T, cl, 0, jit, oop, forms};
+        *ms = t;
+        found = true;  // the last line for a key wins
+    }
+    std::fclose(f);
+    return found;
+}
+
+void disk_store(uint64_t key, const qsv_fuse_opts &o, double ms) {
+    const char *path = std::getenv("QSV_TUNE_CACHE");
+    if (!path || !path[0]) return;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> g(mu);
+    if (FILE *f = std::fopen(path, "a")) {
+        std::fprintf(f, "%016llx %d %d %d %d %d %u %.6f\n", (unsigned long long)key, o.reg_qubits, o.thread_qubits,
+                     o.low_qubits, o.jit, o.out_of_place, o.pass_forms, ms);
+        std::fclose(f);
+    }
+}
+
 }  // namespace
 
 bool tuned_opts(const qsv_circuit *c, int lb, int le, qsv_fuse_opts *out) {
@@ -61,9 +121,23 @@ bool tuned_opts(const qsv_circuit *c, int lb, int le, qsv_fuse_opts *out) {
 
 using namespace qsv;
 
-extern "C" qsv_status sv_tune(void *amps_scratch, const qsv_circuit *c, int layer_begin,
-                              int layer_end, qsv_fuse_opts *out, double *best_ms, void *stream) {
+extern "C" qsv_status sv_tune(void *amps_scratch, const qsv_circuit *c, int layer_begin, int layer_end,
+                              void *workspace, size_t ws_bytes, qsv_fuse_opts *out, double *best_ms,
+                              void *stream) {
     if (!c || !out || !amps_scratch) return fail(QSV_EINVAL, "sv_tune: null argument");
+    // a result tuned in an earlier process (QSV_TUNE_CACHE)
+    const uint64_t dkey = disk_key(c, layer_begin, layer_end);
+    {
+        qsv_fuse_opts o;
+        double ms = 0;
+        if (disk_lookup(dkey, &o, &ms)) {
+            std::lock_guard<std::mutex> g(g_tmu);
+            g_tuned[key_of(c, layer_begin, layer_end)] = o;
+            *out = o;
+            if (best_ms) *best_ms = ms;
+            return QSV_OK;
+        }
+    }
     struct Cand { int R, T, c; };
     static const Cand cands[] = {{5, 8, 4}, {5, 8, 5}, {4, 8, 4}, {4, 8, 5}, {5, 9, 4}, {5, 9, 5},
                                  {6, 8, 4}, {5, 7, 4}, {4, 7, 4}};
@@ -84,17 +158,42 @@ extern "C" qsv_status sv_tune(void *amps_scratch, const qsv_circuit *c, int laye
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(QSV_EHIP, "sv_tune: event create");
+    // States above 2^30 amplitudes are timed on a sample: every pass runs
+    // its first 2^(30 - R - T) tiles only (tens of thousands of workgroups,
+    // still many per CU), which ranks the candidates as the full sweep does
+    // at a sixteenth of the cost at 34 qubits.
+    constexpr int kSampleQubits = 30;
+    auto sample_tiles = [&](const qsv_fuse_opts &o) -> uint64_t {
+        const int L = o.reg_qubits + o.thread_qubits;
+        return (c->n > kSampleQubits && L > 0) ? (1ull << (kSampleQubits - L)) : 0;
+    };
     // warm-up (plans and compiles), then the median of three timed runs of
-    // the whole sweep as sv_simulate runs it (state generated by the first pass)
+    // the whole sweep as sv_simulate runs it (state generated by the first
+    // pass); compiled sweeps are timed pass by pass (summed)
     auto time_one = [&](const qsv_fuse_opts &o, float *ms) {
+        std::vector<float> pm;
+        if (time_sweep_passes(c, layer_begin, layer_end, &o, amps_scratch, workspace, ws_bytes, s,
+                              sample_tiles(o), pm) == QSV_OK) {
+            float t[3];
+            for (int r = 0; r < 3; ++r) {
+                if (time_sweep_passes(c, layer_begin, layer_end, &o, amps_scratch, workspace, ws_bytes, s,
+                                      sample_tiles(o), pm) != QSV_OK)
+                    return false;
+                t[r] = 0.f;
+                for (float x : pm) t[r] += x;
+            }
+            std::sort(t, t + 3);
+            *ms = t[1];
+            return true;
+        }
         if (sv_simulate(amps_scratch, c, 0, QSV_INIT_PLUS, 0, layer_begin, layer_end, &o, nullptr,
-                        nullptr, 0, nullptr, 0, stream) != QSV_OK)
+                        nullptr, 0, nullptr, 0, workspace, ws_bytes, stream) != QSV_OK)
             return false;
         float t[3];
         for (int r = 0; r < 3; ++r) {
             if (hipEventRecord(e0, s) != hipSuccess ||
                 sv_simulate(amps_scratch, c, 0, QSV_INIT_PLUS, 0, layer_begin, layer_end, &o, nullptr,
-                            nullptr, 0, nullptr, 0, stream) != QSV_OK ||
+                            nullptr, 0, nullptr, 0, workspace, ws_bytes, stream) != QSV_OK ||
                 hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                 hipEventElapsedTime(&t[r], e0, e1) != hipSuccess)
                 return false;
@@ -131,8 +230,10 @@ extern "C" qsv_status sv_tune(void *amps_scratch, const qsv_circuit *c, int laye
         std::vector<std::vector<float>> t1(3), t2(3);
         bool ok = true;
         for (int r = 0; r < 3 && ok; ++r)
-            ok = time_sweep_passes(c, layer_begin, layer_end, &o1, amps_scratch, s, t1[r]) == QSV_OK &&
-                 time_sweep_passes(c, layer_begin, layer_end, &o2, amps_scratch, s, t2[r]) == QSV_OK;
+            ok = time_sweep_passes(c, layer_begin, layer_end, &o1, amps_scratch, workspace, ws_bytes, s,
+                                   sample_tiles(o1), t1[r]) == QSV_OK &&
+                 time_sweep_passes(c, layer_begin, layer_end, &o2, amps_scratch, workspace, ws_bytes, s,
+                                   sample_tiles(o2), t2[r]) == QSV_OK;
         if (ok && t1[0].size() == t2[0].size()) {
             uint32_t mask = 0;
             const size_t np = std::min<size_t>(t1[0].size(), 23);
@@ -166,6 +267,7 @@ extern "C" qsv_status sv_tune(void *amps_scratch, const qsv_circuit *c, int laye
     }
     *out = best->second;
     if (best_ms) *best_ms = best->first;
+    disk_store(dkey, best->second, best->first);
     return QSV_OK;
 }
 

@@ -37,7 +37,8 @@ EXPORTS = ["circuit_create", "circuit_destroy", "circuit_info", "circuit_gates",
            "sv_simulate_dot", "sv_sampler_create", "sv_sampler_run", "sv_sampler_destroy", "sv_sampler_run_branches", "sv_sampler_run_subtree",
            "sv_sampler_create_tiles", "sv_sampler_inputs",
            "circuit_branch_levels", "circuit_branch_stage", "sv_tune_set",
-           "qsv_last_error", "qsv_version"]
+           "qsv_last_error", "qsv_version", "sv_workspace_bytes",
+           "sv_stream_copy", "sv_batch_status", "sv_batch_abort", "sv_debug_batch_schedule"]
 
 
 class QsvError(RuntimeError):
@@ -78,25 +79,30 @@ def lib():
         "circuit_gates": (st, [vp, vp, sz, P(sz)]),
         "circuit_split": (st, [vp, u64, P(vp), P(vp), P(i32), vp, vp, sz, P(sz)]),
         "sv_init": (st, [vp, i32, i32, u64, vp]),
-        "sv_apply_fused": (st, [vp, vp, u64, i32, i32, vp, vp]),
+        "sv_apply_fused": (st, [vp, vp, u64, i32, i32, vp, vp, sz, vp]),
+        "sv_workspace_bytes": (st, [vp, i32, i32, vp, P(sz)]),
         "sv_apply_plain": (st, [vp, vp, u64, i32, i32, vp]),
-        "sv_apply_fused_from": (st, [vp, vp, vp, u64, i32, i32, vp, vp]),
-        "sv_simulate_dot": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, vp, vp]),
+        "sv_apply_fused_from": (st, [vp, vp, vp, u64, i32, i32, vp, vp, sz, vp]),
+        "sv_simulate_dot": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, vp, vp, sz, vp]),
         "sv_sampler_create": (st, [vp, i32, i32, vp, vp, sz, P(vp)]),
-        "sv_sampler_run": (st, [vp, vp, vp, u64, vp, vp]),
+        "sv_sampler_run": (st, [vp, vp, vp, u64, vp, vp, sz, vp]),
         "sv_sampler_destroy": (None, [vp]),
-        "sv_sampler_run_branches": (st, [vp, vp, vp, vp, sz, vp, vp]),
-        "sv_sampler_run_subtree": (st, [vp, vp, vp, u64, u64, vp, vp]),
+        "sv_sampler_run_branches": (st, [vp, vp, vp, vp, sz, vp, vp, sz, vp]),
+        "sv_sampler_run_subtree": (st, [vp, vp, vp, u64, u64, vp, vp, sz, vp]),
         "sv_sampler_create_tiles": (st, [vp, i32, i32, vp, vp, sz, P(vp)]),
         "sv_sampler_inputs": (st, [vp, vp, sz, P(sz)]),
-        "sv_simulate": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, vp, sz, vp, i32, vp]),
-        "sv_simulate_c128": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, sz, vp, vp]),
+        "sv_simulate": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, vp, sz, vp, i32, vp, sz, vp]),
+        "sv_simulate_c128": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, sz, vp, vp, sz, vp]),
         "sv_amplitudes": (st, [vp, i32, vp, sz, vp, i32, vp]),
         "sv_norm_fp64": (st, [vp, i32, vp, vp]),
+        "sv_stream_copy": (st, [vp, vp, sz, vp]),
         "sv_branch_combine": (st, [vp, vp, sz, sz, vp, vp, vp]),
         "sv_batch_create": (st, [vp, vp, sz, vp, P(vp)]),
         "sv_batch_run": (st, [vp, vp, i32, vp, sz, vp, vp]),
         "sv_batch_destroy": (None, [vp]),
+        "sv_batch_status": (st, [vp, vp]),
+        "sv_batch_abort": (st, [vp]),
+        "sv_debug_batch_schedule": (st, [vp, vp, sz, i32, i32, u64, i32, P(u64)]),
         "sv_plan_info": (st, [vp, i32, i32, vp, P(i32), vp, vp, sz, vp, sz]),
         "sv_debug_emulate": (st, [vp, vp, u64, i32, i32, vp]),
         "sv_debug_jit_compile": (st, [vp, i32, i32, vp, P(sz), P(ctypes.c_double)]),
@@ -106,8 +112,8 @@ def lib():
         "sv_tune_set": (st, [vp, i32, i32, vp]),
         "circuit_branch_stage": (st, [vp, i32, i32, P(vp)]),
         "sv_inner_product": (st, [vp, vp, i32, vp, vp]),
-        "sv_branch_combine_full": (st, [vp, vp, sz, i32, i32, u64, vp, vp, sz, vp, vp]),
-        "sv_tune": (st, [vp, vp, i32, i32, vp, P(ctypes.c_double), vp]),
+        "sv_branch_combine_full": (st, [vp, vp, sz, i32, i32, u64, vp, vp, sz, vp, i32, vp]),
+        "sv_tune": (st, [vp, vp, i32, i32, vp, sz, vp, P(ctypes.c_double), vp]),
         "sv_apply_dense": (st, [vp, vp, u64, i32, i32, i32, P(i32), vp]),
         "sv_debug_emulate_dense": (st, [vp, vp, u64, i32, i32, i32, P(i32)]),
         "circuit_partition_plan": (st, [vp, i32, i32, vp, i32, i32, P(vp)]),
@@ -156,6 +162,53 @@ def _stream(stream):
     except Exception:
         pass
     return None
+
+
+def _nbytes(x):
+    if hasattr(x, "numel") and hasattr(x, "element_size"):
+        return x.numel() * x.element_size()
+    if isinstance(x, np.ndarray):
+        return x.nbytes
+    raise TypeError(f"cannot size a workspace of {type(x)}")
+
+
+def _device_present():
+    import torch
+    return torch.cuda.is_available()
+
+
+def sv_workspace_bytes(c, layer_begin=0, layer_end=-1, opts=None) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().sv_workspace_bytes(c, layer_begin, layer_end, _opts(opts), ctypes.byref(b)))
+    return b.value
+
+
+def alloc_workspace(c, layer_begin=0, layer_end=-1, opts=None, device=None):
+    """A device buffer of sv_workspace_bytes bytes (torch uint8 tensor)."""
+    import torch
+    return torch.empty(sv_workspace_bytes(c, layer_begin, layer_end, opts), dtype=torch.uint8,
+                       device=device if device is not None else torch.device("cuda", torch.cuda.current_device()))
+
+
+def _ws(workspace, c, layer_begin, layer_end, opts, stream):
+    """(pointer, bytes, keep-alive) of a sweep call's workspace.  None: a
+    buffer of sv_workspace_bytes bytes from torch's allocator on the current
+    device (kept by the caller's frame for the call; torch reuses it only
+    after the work queued on the stream it was allocated for); False: none;
+    a tensor or array: its memory; a (pointer, bytes) pair: as given."""
+    if workspace is False:
+        return None, 0, None
+    if workspace is None:
+        import torch
+        if not torch.cuda.is_available():  # no device: the call fails its own checks
+            return None, 0, None
+        t = alloc_workspace(c, layer_begin, layer_end, opts)
+        if stream is not None and not isinstance(stream, int) and hasattr(stream, "cuda_stream"):
+            t.record_stream(stream)
+        return t.data_ptr(), _nbytes(t), t
+    if isinstance(workspace, tuple):
+        return workspace[0], workspace[1], None
+    return _ptr(workspace), _nbytes(workspace), workspace
 
 
 def _opts(opts):
@@ -244,44 +297,57 @@ def sv_init(amps, n_qubits, kind=INIT_ZERO, basis=0, stream=None):
     _check(lib().sv_init(_ptr(amps), n_qubits, kind, ctypes.c_uint64(basis), _stream(stream)))
 
 
-def sv_apply_fused(amps, c, branch=0, layer_begin=0, layer_end=-1, opts=None, stream=None):
+def sv_apply_fused(amps, c, branch=0, layer_begin=0, layer_end=-1, opts=None, stream=None,
+                   workspace=None):
+    wp, wb, _keep = _ws(workspace, c, layer_begin, layer_end, opts, stream)
     _check(lib().sv_apply_fused(_ptr(amps), c, ctypes.c_uint64(branch), layer_begin, layer_end,
-                                _opts(opts), _stream(stream)))
+                                _opts(opts), wp, wb, _stream(stream)))
 
 
 def sv_simulate(amps, c, branch=0, init_kind=INIT_ZERO, basis=0, layer_begin=0, layer_end=-1,
                 opts=None, norm_out=None, bitstrings=None, amps_out=None, c128=False,
-                stream=None):
+                stream=None, workspace=None):
     m = 0
     if amps_out is not None:
         m = amps_out.numel() if hasattr(amps_out, "numel") else len(amps_out)
+    wp, wb, _keep = _ws(workspace, c, layer_begin, layer_end, opts, stream)
     _check(lib().sv_simulate(_ptr(amps), c, ctypes.c_uint64(branch), init_kind,
                              ctypes.c_uint64(basis), layer_begin, layer_end, _opts(opts),
                              _ptr(norm_out), _ptr(bitstrings), m, _ptr(amps_out),
-                             1 if c128 else 0, _stream(stream)))
+                             1 if c128 else 0, wp, wb, _stream(stream)))
 
 
 def sv_simulate_c128(amps, c, branch=0, init_kind=INIT_ZERO, basis=0, layer_begin=0,
-                     layer_end=-1, norm_out=None, bitstrings=None, amps_out=None, stream=None):
+                     layer_end=-1, norm_out=None, bitstrings=None, amps_out=None, stream=None,
+                     workspace=None):
     m = 0
     if amps_out is not None:
         m = amps_out.numel() if hasattr(amps_out, "numel") else len(amps_out)
+    if workspace is None and norm_out is None:
+        workspace = False
+    if workspace is None and _device_present():  # the norm's partial sums only (in place)
+        workspace = alloc_workspace(c, layer_begin, layer_end, {"reg_qubits": 4, "thread_qubits": 8,
+                                                               "low_qubits": 4, "jit": -1})
+    wp, wb, _keep = _ws(workspace, c, layer_begin, layer_end, None, stream)
     _check(lib().sv_simulate_c128(_ptr(amps), c, ctypes.c_uint64(branch), init_kind,
                                   ctypes.c_uint64(basis), layer_begin, layer_end, _ptr(norm_out),
-                                  _ptr(bitstrings), m, _ptr(amps_out), _stream(stream)))
+                                  _ptr(bitstrings), m, _ptr(amps_out), wp, wb, _stream(stream)))
 
 
-def sv_apply_fused_from(src, dst, c, branch=0, layer_begin=0, layer_end=-1, opts=None, stream=None):
+def sv_apply_fused_from(src, dst, c, branch=0, layer_begin=0, layer_end=-1, opts=None, stream=None,
+                        workspace=None):
+    wp, wb, _keep = _ws(workspace, c, layer_begin, layer_end, opts, stream)
     _check(lib().sv_apply_fused_from(_ptr(src), _ptr(dst), c, ctypes.c_uint64(branch), layer_begin,
-                                     layer_end, _opts(opts), _stream(stream)))
+                                     layer_end, _opts(opts), wp, wb, _stream(stream)))
 
 
 def sv_simulate_dot(amps, c, other, out_dev, branch=0, init_kind=INIT_ZERO, basis=0, layer_begin=0,
-                    layer_end=-1, opts=None, stream=None):
+                    layer_end=-1, opts=None, stream=None, workspace=None):
     """out_dev (device float64[2]) = <U init | other>; amps is a work buffer."""
+    wp, wb, _keep = _ws(workspace, c, layer_begin, layer_end, opts, stream)
     _check(lib().sv_simulate_dot(_ptr(amps), c, ctypes.c_uint64(branch), init_kind, ctypes.c_uint64(basis),
                                  layer_begin, layer_end, _opts(opts), _ptr(other), _ptr(out_dev),
-                                 _stream(stream)))
+                                 wp, wb, _stream(stream)))
 
 
 def sv_apply_plain(amps, c, branch=0, layer_begin=0, layer_end=-1, stream=None):
@@ -297,6 +363,10 @@ def sv_amplitudes(amps, n_qubits, bitstrings, out, c128=False, stream=None):
 
 def sv_norm_fp64(amps, n_qubits, out, stream=None):
     _check(lib().sv_norm_fp64(_ptr(amps), n_qubits, _ptr(out), _stream(stream)))
+
+
+def sv_stream_copy(src, dst, nbytes, stream=None):
+    _check(lib().sv_stream_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)))
 
 
 def sv_branch_combine(a_tab, b_tab, n_branches, m, sign, out, stream=None):
@@ -339,6 +409,26 @@ def sv_batch_run(batch, amps_list, init_plus=False, bitstrings=None, m=0, amp_ta
     arr = (ctypes.c_void_p * len(amps_list))(*[_ptr(a) for a in amps_list])
     _check(lib().sv_batch_run(batch, arr, 1 if init_plus else 0, _ptr(bitstrings), m,
                               _ptr(amp_table), _stream(stream)))
+
+
+def sv_batch_status(batch, stream=None):
+    _check(lib().sv_batch_status(batch, _stream(stream)))
+
+
+def sv_batch_abort(batch):
+    _check(lib().sv_batch_abort(batch))
+
+
+def sv_debug_batch_schedule(n_qubits, passes, tile_qubits, workers, seed=1, planted_early_start=False) -> int:
+    """Host emulation of a persistent batch launch's schedule; returns the
+    number of work items (raises if the ordering rule is violated)."""
+    nq = np.ascontiguousarray(np.asarray(n_qubits, dtype=np.int32))
+    pp = np.ascontiguousarray(np.asarray(passes, dtype=np.int32))
+    items = ctypes.c_uint64()
+    _check(lib().sv_debug_batch_schedule(_ptr(nq), _ptr(pp), nq.size, tile_qubits, workers,
+                                         ctypes.c_uint64(seed), 1 if planted_early_start else 0,
+                                         ctypes.byref(items)))
+    return items.value
 
 
 def sv_plan_info(c, layer_begin=0, layer_end=-1, opts=None):
@@ -397,29 +487,35 @@ def sv_inner_product(a, b, n_qubits, out_dev, stream=None):
     _check(lib().sv_inner_product(_ptr(a), _ptr(b), n_qubits, _ptr(out_dev), _stream(stream)))
 
 
+COMBINE_OUT_C128, COMBINE_FP32 = 1, 2
+
+
 def sv_branch_combine_full(a_states, b_states, n_branches, n_a, n_b, side_a_mask, folded_a,
-                           folded_b, out_state, stream=None):
+                           folded_b, out_state, flags=0, stream=None):
     """Complete state of a cut circuit from all branch states of both halves
-    (folded pairs as returned by circuit_split, host int32 arrays)."""
+    (folded pairs as returned by circuit_split, host int32 arrays).  flags:
+    0 = FP64 products and sums into a complex64 state; COMBINE_OUT_C128 =
+    the same into a complex128 state; COMBINE_FP32 = FP32 accumulation."""
     fa = np.ascontiguousarray(np.asarray(folded_a, dtype=np.int32))
     fb = np.ascontiguousarray(np.asarray(folded_b, dtype=np.int32))
     _check(lib().sv_branch_combine_full(_ptr(a_states), _ptr(b_states), n_branches, n_a, n_b,
                                         ctypes.c_uint64(side_a_mask), fa.ctypes.data if fa.size else None,
                                         fb.ctypes.data if fb.size else None, fa.size, _ptr(out_state),
-                                        _stream(stream)))
+                                        flags, _stream(stream)))
 
 
 def release_device_buffers():
-    """Free the library's device buffers on the current device (second state
-    buffer of out-of-place sweeps, norm partial sums)."""
+    """Free the library's device buffers on the current device (the partial
+    sums of sv_norm_fp64 / sv_inner_product per stream)."""
     _check(lib().qsv_release_device_buffers())
 
 
-def sv_tune(amps_scratch, c, layer_begin=0, layer_end=-1, stream=None):
+def sv_tune(amps_scratch, c, layer_begin=0, layer_end=-1, stream=None, workspace=None):
     """Autotune the tile shape; returns (opts dict, best ms)."""
     o = FuseOpts()
     ms = ctypes.c_double()
-    _check(lib().sv_tune(_ptr(amps_scratch), c, layer_begin, layer_end, ctypes.byref(o),
+    wp, wb, _keep = _ws(workspace, c, layer_begin, layer_end, None, stream)
+    _check(lib().sv_tune(_ptr(amps_scratch), c, layer_begin, layer_end, wp, wb, ctypes.byref(o),
                          ctypes.byref(ms), _stream(stream)))
     return ({"reg_qubits": o.reg_qubits, "thread_qubits": o.thread_qubits,
              "low_qubits": o.low_qubits, "plain": 0, "jit": o.jit,
@@ -547,7 +643,9 @@ def sv_sampler_create(c, bitstrings, layer_begin=0, layer_end=-1, opts=None) -> 
     out = ctypes.c_void_p()
     _check(lib().sv_sampler_create(c, layer_begin, layer_end, _opts(opts), _ptr(xs), xs.size,
                                    ctypes.byref(out)))
-    return Sampler(out.value, c, xs.size)
+    smp = Sampler(out.value, c, xs.size)
+    smp.range = (layer_begin, layer_end, opts)
+    return smp
 
 
 def sv_sampler_create_tiles(c, indices, layer_begin=0, layer_end=-1, opts=None) -> Sampler:
@@ -555,7 +653,9 @@ def sv_sampler_create_tiles(c, indices, layer_begin=0, layer_end=-1, opts=None) 
     out = ctypes.c_void_p()
     _check(lib().sv_sampler_create_tiles(c, layer_begin, layer_end, _opts(opts), _ptr(xs), xs.size,
                                          ctypes.byref(out)))
-    return Sampler(out.value, c, xs.size)
+    smp = Sampler(out.value, c, xs.size)
+    smp.range = (layer_begin, layer_end, opts)
+    return smp
 
 
 def sv_sampler_inputs(sampler) -> np.ndarray:
@@ -567,17 +667,25 @@ def sv_sampler_inputs(sampler) -> np.ndarray:
     return out
 
 
-def sv_sampler_run(sampler, src, work, out, branch=0, stream=None):
+def _sampler_ws(sampler, workspace, stream):
+    lb, le, opts = sampler.range
+    return _ws(workspace, sampler.circuit, lb, le, opts, stream)
+
+
+def sv_sampler_run(sampler, src, work, out, branch=0, stream=None, workspace=None):
+    wp, wb, _keep = _sampler_ws(sampler, workspace, stream)
     _check(lib().sv_sampler_run(sampler, _ptr(src), _ptr(work), ctypes.c_uint64(branch), _ptr(out),
-                                _stream(stream)))
+                                wp, wb, _stream(stream)))
 
 
-def sv_sampler_run_subtree(sampler, src, work, out, prefix, mask, stream=None):
+def sv_sampler_run_subtree(sampler, src, work, out, prefix, mask, stream=None, workspace=None):
+    wp, wb, _keep = _sampler_ws(sampler, workspace, stream)
     _check(lib().sv_sampler_run_subtree(sampler, _ptr(src), _ptr(work), ctypes.c_uint64(prefix),
-                                        ctypes.c_uint64(mask), _ptr(out), _stream(stream)))
+                                        ctypes.c_uint64(mask), _ptr(out), wp, wb, _stream(stream)))
 
 
-def sv_sampler_run_branches(sampler, src, work, out, branches, stream=None):
+def sv_sampler_run_branches(sampler, src, work, out, branches, stream=None, workspace=None):
     br = np.ascontiguousarray(np.asarray(branches, dtype=np.uint64).reshape(-1))
+    wp, wb, _keep = _sampler_ws(sampler, workspace, stream)
     _check(lib().sv_sampler_run_branches(sampler, _ptr(src), _ptr(work), _ptr(br), br.size, _ptr(out),
-                                         _stream(stream)))
+                                         wp, wb, _stream(stream)))

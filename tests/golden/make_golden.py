@@ -2,7 +2,9 @@
 
 Outputs: tests/golden/<workload>_amplitudes.txt for the 30-qubit depth-20
 workload (4096 bitstrings) and the 30-qubit depth-16 workload used by the
-split check (1024 bitstrings), one line per sampled bitstring:
+split check (1024 bitstrings), and tests/golden/7x7-d16_A_branch<b>.txt for
+branch states of the 28-qubit half of the 49-qubit split (branches 0, 1337
+and 16 seeded random ones), one line per sampled bitstring:
 "<bitstring> <re> <im>" with %.17g doubles, plus a header with the workload,
 the oracle norm and the oracle's own timing.  The 4096 bitstrings are the
 seeded uniform sample of paper_1804_04797_amd.workloads.bitstrings.
@@ -73,7 +75,25 @@ def split_branch(name="7x7-d16", after_col=3, branches=(0, 1337), m=1024):
         print(out, dt)
 
 
+def random_branches(count=16, c_eff=11, seed=workloads.BITSTRING_SEED_BASE + 41):
+    """count distinct branch indices drawn uniformly from [0, 2^c_eff) (seeded),
+    excluding 0 and 1337, which have their own files."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        b = int(rng.integers(0, 1 << c_eff))
+        if b not in out and b not in (0, 1337):
+            out.append(b)
+    return sorted(out)
+
+
 if __name__ == "__main__":
-    main("5x6-d20", 4096, workloads.BITSTRING_SEED_BASE + 2)
-    main("5x6-d16", 1024, workloads.BITSTRING_SEED_BASE + 6)
-    split_branch("7x7-d16", 3, (0, 1337), 1024)
+    what = sys.argv[1] if len(sys.argv) > 1 else "all"
+    if what in ("all", "sweeps"):
+        main("5x6-d20", 4096, workloads.BITSTRING_SEED_BASE + 2)
+        main("5x6-d16", 1024, workloads.BITSTRING_SEED_BASE + 6)
+    if what in ("all", "branches"):
+        split_branch("7x7-d16", 3, (0, 1337), 1024)
+    if what in ("all", "random_branches"):
+        split_branch("7x7-d16", 3, tuple(random_branches()), 1024)

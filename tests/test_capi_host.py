@@ -283,7 +283,7 @@ def test_emulated_split_branches():
     assert np.max(np.abs(total - ref)) < 1e-5
 
 
-@pytest.mark.parametrize("k", [4, 5, 6])
+@pytest.mark.parametrize("k", [4, 5, 6, 7])
 def test_dense_blocks_emulated_match_oracle(k):
     """Dense-block plan (FP64 block matrices rounded to complex64) applied on
     the host reproduces the oracle state."""
@@ -522,9 +522,9 @@ def test_sampler_argument_checks():
     assert e.value.status == 2
     # the multi-branch run refuses a missing sampler, branch list or output on the host
     br = np.array([0, 1], np.uint64)
-    assert qsv.lib().sv_sampler_run_branches(None, 256, 512, br.ctypes.data, 2, 1024, None) == 1
-    assert qsv.lib().sv_sampler_run_branches(None, 256, 512, None, 2, 1024, None) == 1
-    assert qsv.lib().sv_sampler_run_branches(None, 256, 512, br.ctypes.data, 2, None, None) == 1
+    assert qsv.lib().sv_sampler_run_branches(None, 256, 512, br.ctypes.data, 2, 1024, None, 0, None) == 1
+    assert qsv.lib().sv_sampler_run_branches(None, 256, 512, None, 2, 1024, None, 0, None) == 1
+    assert qsv.lib().sv_sampler_run_branches(None, 256, 512, br.ctypes.data, 2, None, None, 0, None) == 1
 
 
 # --- branch stages (prefix sharing among the branches of a split half) -------
@@ -595,3 +595,87 @@ def test_tune_set_applies_to_plans():
     assert qsv.sv_plan_info(same, 1, -1)["resident"] == want
     assert qsv.lib().sv_tune_set(None, 0, -1, None) == 1
 
+
+
+def test_workspace_bytes():
+    # sv_workspace_bytes: the second state buffer when the options run out
+    # of place (n >= 24 by default with compiled passes), plus the FP64
+    # partial sums (16 bytes per 2^11-amplitude tile, at least 1 MiB)
+    c30 = qsv.circuit_create(5, 6, None, 6, 1)
+    part30 = 16 * max(1 << (30 - 11), 65536)
+    assert qsv.sv_workspace_bytes(c30, 1) == (8 << 30) + part30
+    assert qsv.sv_workspace_bytes(c30, 1, opts={"out_of_place": -1}) == part30
+    assert qsv.sv_workspace_bytes(c30, 1, opts={"jit": -1}) == part30
+    assert qsv.sv_workspace_bytes(c30, 1, opts={"plain": 1}) == part30
+    c20 = qsv.circuit_create(4, 5, None, 6, 1)
+    assert qsv.sv_workspace_bytes(c20, 1) == 16 * 65536
+    assert qsv.sv_workspace_bytes(c20, 1, opts={"jit": 1, "out_of_place": 1}) == (8 << 20) + 16 * 65536
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.sv_workspace_bytes(c20, -1)
+    assert e.value.status == 1
+
+
+@pytest.mark.parametrize("seed,workers", [(1, 1), (2, 3), (3, 64), (4, 512)])
+def test_persistent_batch_schedule(seed, workers):
+    # The persistent batch launch's work-item order and waiting rule (host
+    # emulation): uneven entries with different pass counts, every item run
+    # once, never before its entry's earlier passes, and no stall for any
+    # number of workgroups, including one.
+    rng = np.random.default_rng(seed)
+    n = rng.integers(11, 17, size=40)
+    passes = rng.integers(0, 5, size=40)
+    items = qsv.sv_debug_batch_schedule(n, passes, 11, workers, seed)
+    assert items == int(sum(int(p) << (int(q) - 11) for q, p in zip(n, passes)))
+
+
+def test_persistent_batch_schedule_detects_a_broken_rule():
+    # a planted wrong rule (an item may start one tile early) must fail the
+    # check; edge cases: one entry, entries with zero passes; a tile larger
+    # than a state is refused
+    rng = np.random.default_rng(9)
+    n = rng.integers(11, 15, size=20)
+    passes = rng.integers(1, 4, size=20)
+    with pytest.raises(qsv.QsvError):
+        qsv.sv_debug_batch_schedule(n, passes, 11, 64, 5, planted_early_start=True)
+    assert qsv.sv_debug_batch_schedule([11], [3], 11, 2) == 3
+    assert qsv.sv_debug_batch_schedule([12, 11], [0, 2], 11, 4) == 2
+    with pytest.raises(qsv.QsvError):
+        qsv.sv_debug_batch_schedule([10], [1], 11, 2)
+
+
+def test_whole_state_tile_plans():
+    """A state of 2^14 amplitudes or fewer fits one tile: its plan on that
+    tile has every qubit resident and a single pass for these depths."""
+    for n, d in [(11, 9), (12, 14), (13, 20), (14, 24)]:
+        rows, cols, pres = workloads.lattice_for_qubits(n)
+        c = qsv.circuit_create(rows, cols, pres, d, 5)
+        R, T = {11: (4, 7), 12: (5, 7), 13: (5, 8), 14: (5, 9)}[n]
+        info = qsv.sv_plan_info(c, 1, -1, dict(reg_qubits=R, thread_qubits=T, low_qubits=5, plain=0, jit=-1))
+        assert info["n_passes"] == 1, (n, info["n_passes"])
+
+
+def test_jit_code_object_disk_cache(tmp_path):
+    # QSV_JIT_CACHE: the first process compiles and stores the code objects,
+    # a second process loads them (no compile) and gets the same code size
+    import subprocess
+    import sys
+    prog = (
+        "import sys, time; sys.path.insert(0, %r)\n"
+        "from paper_1804_04797_amd import qsv, workloads\n"
+        "spec = workloads.WORKLOADS['4x5-d10']\n"
+        "c = qsv.circuit_create(spec['rows'], spec['cols'], None, spec['depth'], spec['seed'])\n"
+        "o = dict(reg_qubits=4, thread_qubits=7, low_qubits=4, plain=0, jit=1)\n"
+        "t = time.time(); b, _ = qsv.sv_debug_jit_compile(c, 1, -1, o); print(b, time.time() - t)\n"
+    ) % ROOT
+    env = dict(os.environ, QSV_JIT_CACHE=str(tmp_path))
+    r1 = subprocess.run([sys.executable, "-c", prog], env=env, capture_output=True, text=True, timeout=600)
+    assert r1.returncode == 0, r1.stderr
+    files = sorted(p.name for p in tmp_path.iterdir())
+    assert files and all(f.startswith("qsv_") and f.endswith(".co") for f in files)
+    r2 = subprocess.run([sys.executable, "-c", prog], env=env, capture_output=True, text=True, timeout=600)
+    assert r2.returncode == 0, r2.stderr
+    b1, t1 = r1.stdout.split()
+    b2, t2 = r2.stdout.split()
+    assert b1 == b2
+    assert float(t2) < 0.5 * float(t1)
+    assert sorted(p.name for p in tmp_path.iterdir()) == files
