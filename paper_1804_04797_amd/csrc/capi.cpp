@@ -300,7 +300,7 @@ qsv_status qsv_release_device_buffers(void) {
     return QSV_OK;
 }
 
-const char *qsv_version(void) { return "qsv 0.6 gfx950"; }
+const char *qsv_version(void) { return "qsv 0.7 gfx950"; }
 
 qsv_status circuit_create(int rows, int cols, const uint8_t *present, int depth, uint64_t seed,
                           const qsv_gate *gates, size_t n_gates, qsv_circuit **out) {
@@ -999,7 +999,7 @@ qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int in
             return fail(QSV_EINVAL, "sv_simulate: the FP64 norm needs a workspace of sv_workspace_bytes bytes");
         hipError_t e = launch_init(static_cast<float2 *>(amps), c->n, init_kind, basis, s);
         if (e != hipSuccess) return hip_fail(e, "sv_simulate");
-        st = fused ? sv_apply_fused(amps, c, branch, layer_begin, layer_end, opts, nullptr, 0, stream)
+        st = fused ? sv_apply_fused(amps, c, branch, layer_begin, layer_end, opts, workspace, ws_bytes, stream)
                    : sv_apply_plain(amps, c, branch, layer_begin, layer_end, stream);
         if (st != QSV_OK) return st;
         if (norm_out_dev) {
@@ -1056,7 +1056,7 @@ qsv_status sv_simulate_dot(void *amps, const qsv_circuit *c, uint64_t branch, in
         if (!ws.p || ws.bytes < need)
             return fail(QSV_EINVAL, "sv_simulate_dot: needs a workspace of sv_workspace_bytes bytes");
         if ((st = sv_simulate(amps, c, branch, init_kind, basis, layer_begin, layer_end, opts, nullptr, nullptr,
-                              0, nullptr, 0, nullptr, 0, stream)) != QSV_OK)
+                              0, nullptr, 0, workspace, ws_bytes, stream)) != QSV_OK)
             return st;
         hipError_t e = launch_dot(static_cast<const float2 *>(amps), static_cast<const float2 *>(other), c->n,
                                   out_dev, reinterpret_cast<double *>(ws.p), s);
