@@ -432,6 +432,19 @@ qsv_status sv_stream_copy(const void *src, void *dst, size_t bytes, void *stream
 qsv_status sv_norm_fp64(const void *amps, int n_qubits, double *out_dev, void *stream);
 
 /*
+ * sv_norm_fp64_noalloc - sv_norm_fp64 for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  Same kernels, same result bit for bit;
+ * the partial sums live in a fixed device array of 65536 doubles (512 KiB)
+ * that each GPU holds from the first call on it until the process ends.
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine).  Calls that overlap on one device share that array and race:
+ * serialise them (one stream, or events between streams).  n_qubits <= 34
+ * (QSV_ERANGE otherwise); the state needs at most 65536 partials at any n.
+ */
+qsv_status sv_norm_fp64_noalloc(const void *amps, int n_qubits, double *out_dev, void *stream);
+
+/*
  * sv_inner_product - <a|b> = sum_i conj(a_i) b_i of two complex64[2^n]
  * device states, every product and partial sum in FP64, fixed-order tree
  * (deterministic).  out_dev: device double[2] = (re, im).  With a = U2^dagger

@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqsv.so")
 SOURCES = ["kernels.hip", "combine.hip", "capi.cpp", "circuit.cpp", "planner.cpp", "emulate.cpp", "batch.cpp",
-           "jit.cpp", "tune.cpp", "dense.cpp", "partition.cpp"]
+           "jit.cpp", "tune.cpp", "dense.cpp", "partition.cpp", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled for device code on this target.

@@ -37,7 +37,7 @@ EXPORTS = ["circuit_create", "circuit_destroy", "circuit_info", "circuit_gates",
            "sv_simulate_dot", "sv_sampler_create", "sv_sampler_run", "sv_sampler_destroy", "sv_sampler_run_branches", "sv_sampler_run_subtree",
            "sv_sampler_create_tiles", "sv_sampler_inputs",
            "circuit_branch_levels", "circuit_branch_stage", "sv_tune_set",
-           "qsv_last_error", "qsv_version", "sv_workspace_bytes",
+           "qsv_last_error", "qsv_version", "sv_norm_fp64_noalloc", "sv_workspace_bytes",
            "sv_stream_copy", "sv_batch_status", "sv_batch_abort", "sv_debug_batch_schedule"]
 
 
@@ -95,6 +95,7 @@ def lib():
         "sv_simulate_c128": (st, [vp, vp, u64, i32, u64, i32, i32, vp, vp, sz, vp, vp, sz, vp]),
         "sv_amplitudes": (st, [vp, i32, vp, sz, vp, i32, vp]),
         "sv_norm_fp64": (st, [vp, i32, vp, vp]),
+        "sv_norm_fp64_noalloc": (st, [vp, i32, vp, vp]),
         "sv_stream_copy": (st, [vp, vp, sz, vp]),
         "sv_branch_combine": (st, [vp, vp, sz, sz, vp, vp, vp]),
         "sv_batch_create": (st, [vp, vp, sz, vp, P(vp)]),
@@ -367,6 +368,10 @@ def sv_norm_fp64(amps, n_qubits, out, stream=None):
 
 def sv_stream_copy(src, dst, nbytes, stream=None):
     _check(lib().sv_stream_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)))
+
+
+def sv_norm_fp64_noalloc(amps, n_qubits, out, stream=None):
+    _check(lib().sv_norm_fp64_noalloc(_ptr(amps), n_qubits, _ptr(out), _stream(stream)))
 
 
 def sv_branch_combine(a_tab, b_tab, n_branches, m, sign, out, stream=None):
