@@ -541,24 +541,27 @@ k_dense(float2 *__restrict__ amps, const float *__restrict__ mat_t, const DenseA
 // registers.  Wave w of a workgroup owns output rows [16 w, 16 w + 16) (its
 // strip of Mr and Mi, 2^k / 2 registers per lane, loaded once) and computes
 // them for a tile of 64 columns: Yr = Mr Xr - Mi Xi and Yi = Mr Xi + Mi Xr on
-// v_mfma_f32_16x16x4f32 (FP32 accumulation), the X tile staged in LDS as
-// separate re/im planes with a row stride of 80 floats (the 4 rows one
-// MFMA operand read covers fall on distinct bank groups).  Persistent
-// workgroups walk the tiles; the next tile's 16-byte global loads are issued
-// into registers before the current tile's matrix-core work, and each wave
-// stores its outputs straight from the accumulators.  pair_cols: column
-// index bit 0 is physical bit 0, so a 16-byte access holds columns 2c and
-// 2c + 1 (otherwise 8-byte accesses).
+// v_mfma_f32_16x16x4f32 (FP32 accumulation; the two products of Yi of a
+// block are issued four instructions apart).  A tile is 2^(k+6) amplitudes whose
+// local index bits are its physical bits from the lowest up (the block's k
+// qubits and the 6 lowest other qubits; physical bit 0 is always among
+// them), so thread t's 16-byte accesses at local indices 2 (i NT + t) are
+// contiguous across a wave whatever the block's qubits.  Loads go to
+// registers, then to LDS planes (re, im; row stride 80 floats, so the 4 rows
+// one MFMA operand read covers fall on distinct bank groups) at each
+// element's (row, column); the results go back through the same planes and
+// leave in the same physical order.  Persistent workgroups walk the tiles;
+// the next tile's loads are issued before the current tile's matrix-core work.
 template <int K>
 __global__ void __launch_bounds__(64 * (1 << K) / 16)
-k_dense_strip(float2 *__restrict__ amps, const float *__restrict__ mat_t, const DenseArgs A, int pair_cols) {
+k_dense_strip(float2 *__restrict__ amps, const float *__restrict__ mat_t, const DenseArgs A) {
     constexpr int DIM = 1 << K;
     constexpr int WAVES = DIM / 16;
     constexpr int NT = 64 * WAVES;          // threads
     constexpr int COLS = 64;
     constexpr int XS = 80;                   // row stride of the X planes (floats)
     constexpr int KS = DIM / 4;              // k-steps of 4
-    constexpr int PAIRS = DIM * COLS / 2;    // column pairs of a tile
+    constexpr int PAIRS = DIM * COLS / 2;    // amplitude pairs of a tile
     constexpr int PER = PAIRS / NT;          // pairs per thread (8)
     static_assert(PER * NT == PAIRS, "tile split");
     __shared__ float xr[DIM * XS], xi[DIM * XS];
@@ -572,66 +575,70 @@ k_dense_strip(float2 *__restrict__ amps, const float *__restrict__ mat_t, const 
         mr[ks] = mat_t[k * DIM + row];
         mi[ks] = mat_t[DIM * DIM + k * DIM + row];
     }
-    // physical offsets of tile-local row and column indices
-    auto row_off = [&](uint32_t row) {
-        uint64_t o = 0;
+    // pair it of this thread: local index l = 2 (it NT + t).  Bits 1..TB of
+    // l come from t and the higher ones from it, so its physical offset and
+    // its LDS position (row * XS + column) are sums of a per-thread part and
+    // a part common to the workgroup; l + 1 is the next amplitude in memory
+    // and sits d0 further on in LDS.
+    constexpr int TB = K + 2;  // log2(NT)
+    static_assert((1 << TB) == NT && (PER << TB) == PAIRS, "pair index split");
+    uint64_t off_t = 0;
+    uint32_t pos_t = 0;
 #pragma unroll
-        for (int b = 0; b < K; ++b)
-            if ((row >> b) & 1u) o |= 1ull << A.phys[A.sub_row[b]];
-        return o;
-    };
-    auto col_off = [&](uint32_t col) {
-        uint64_t o = 0;
-#pragma unroll
-        for (int b = 0; b < 6; ++b)
-            if ((col >> b) & 1u) o |= 1ull << A.phys[A.sub_col[b]];
-        return o;
-    };
-    // load assignment: pair p = it * NT + t -> row p / 32, column pair p % 32
-    uint64_t loff[PER];
-#pragma unroll
-    for (int it = 0; it < PER; ++it) {
-        const uint32_t p = uint32_t(it) * NT + t, row = p >> 5, cp = p & 31u;
-        loff[it] = row_off(row) | col_off(2u * cp);
+    for (int b = 1; b <= TB; ++b) {
+        if (!((t >> (b - 1)) & 1u)) continue;
+        off_t |= 1ull << A.phys[b];
+        pos_t += ((A.rowmask >> b) & 1u) ? (1u << A.sub[b]) * XS : (1u << A.sub[b]);
     }
-    // store offsets: row 16 w + 4 lk + r, column 16 c + lr
-    uint64_t srow[4], scol[4];
+    auto off_it = [&](int it) {
+        uint64_t o = 0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) srow[r] = row_off(w * 16u + 4u * lk + uint32_t(r));
+        for (int b = TB + 1; b < K + 6; ++b)
+            if ((it >> (b - TB - 1)) & 1) o |= 1ull << A.phys[b];
+        return o;
+    };
+    auto pos_it = [&](int it) {
+        uint32_t q = 0;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) scol[c] = col_off(uint32_t(c) * 16u + lr);
-    const uint64_t c1 = col_off(1u);  // physical offset of column bit 0
+        for (int b = TB + 1; b < K + 6; ++b)
+            if ((it >> (b - TB - 1)) & 1) q += ((A.rowmask >> b) & 1u) ? (1u << A.sub[b]) * XS : (1u << A.sub[b]);
+        return q;
+    };
+    const uint32_t d0 = (A.rowmask & 1u) ? (1u << A.sub[0]) * XS : (1u << A.sub[0]);
     v4f nx[PER];
-    auto fetch = [&](uint64_t tile) {
+    auto tile_base = [&](uint64_t tile) {
         uint64_t base = 0;
         for (int i = 0; i < A.n_glob; ++i) base |= ((tile >> i) & 1ull) << A.glob_bits[i];
+        return base;
+    };
+    auto fetch = [&](uint64_t tile) {
+        const uint64_t base = tile_base(tile);
 #pragma unroll
-        for (int it = 0; it < PER; ++it) {
-            if (pair_cols) {
-                nx[it] = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(amps + (base | loff[it])));
-            } else {
-                const float2 a = amps[base | loff[it]], b = amps[base | loff[it] | c1];
-                nx[it] = v4f{a.x, a.y, b.x, b.y};
-            }
-        }
+        for (int it = 0; it < PER; ++it)
+            nx[it] = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(amps + (base | off_t | off_it(it))));
     };
     uint64_t tile = blockIdx.x;
     if (tile < A.tiles) fetch(tile);
     for (; tile < A.tiles; tile += gridDim.x) {
-        uint64_t base = 0;
-        for (int i = 0; i < A.n_glob; ++i) base |= ((tile >> i) & 1ull) << A.glob_bits[i];
+        const uint64_t base = tile_base(tile);
         __syncthreads();  // the previous tile's LDS reads are complete
 #pragma unroll
         for (int it = 0; it < PER; ++it) {
-            const uint32_t p = uint32_t(it) * NT + t, row = p >> 5, cp = p & 31u;
-            *reinterpret_cast<float2 *>(&xr[row * XS + 2 * cp]) = make_float2(nx[it].x, nx[it].z);
-            *reinterpret_cast<float2 *>(&xi[row * XS + 2 * cp]) = make_float2(nx[it].y, nx[it].w);
+            const uint32_t at = pos_t + pos_it(it);
+            xr[at] = nx[it].x;
+            xi[at] = nx[it].y;
+            xr[at + d0] = nx[it].z;
+            xi[at + d0] = nx[it].w;
         }
         __syncthreads();
         if (tile + gridDim.x < A.tiles) fetch(tile + gridDim.x);  // in flight during the MFMA work
         v4f arr[4], aii[4], ai[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) { arr[c] = v4f{0, 0, 0, 0}; aii[c] = arr[c]; ai[c] = arr[c]; }
+        for (int c = 0; c < 4; ++c) {
+            arr[c] = v4f{0, 0, 0, 0};
+            aii[c] = arr[c];
+            ai[c] = arr[c];
+        }
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const uint32_t krow = uint32_t(ks) * 4u + lk;
@@ -642,24 +649,36 @@ k_dense_strip(float2 *__restrict__ amps, const float *__restrict__ mat_t, const 
                 bi[c] = xi[krow * XS + uint32_t(c) * 16u + lr];
             }
 #pragma unroll
+            for (int c = 0; c < 4; ++c) ai[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(mr[ks], bi[c], ai[c], 0, 0, 0);
+#pragma unroll
             for (int c = 0; c < 4; ++c) {
                 arr[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(mr[ks], br[c], arr[c], 0, 0, 0);
                 aii[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(mi[ks], bi[c], aii[c], 0, 0, 0);
-                ai[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(mr[ks], bi[c], ai[c], 0, 0, 0);
                 ai[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(mi[ks], br[c], ai[c], 0, 0, 0);
             }
         }
+        // element r of block c: row 16 w + 4 lk + r, column 16 c + lr
+        __syncthreads();  // every wave's operand reads of X are complete
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                amps[base | srow[r] | scol[c]] = make_float2(arr[c][r] - aii[c][r], ai[c][r]);
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t at = (w * 16u + 4u * lk + uint32_t(r)) * XS + uint32_t(c) * 16u + lr;
+                xr[at] = arr[c][r] - aii[c][r];
+                xi[at] = ai[c][r];
+            }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const uint32_t at = pos_t + pos_it(it);
+            const v4f y = {xr[at], xi[at], xr[at + d0], xi[at + d0]};
+            __builtin_nontemporal_store(y, reinterpret_cast<v4f *>(amps + (base | off_t | off_it(it))));
+        }
     }
 }
 
 template <int K>
-hipError_t launch_dense_strip_t(float2 *amps, const float *mat_t, const DenseArgs &A, int pair_cols,
-                                hipStream_t s) {
+hipError_t launch_dense_strip_t(float2 *amps, const float *mat_t, const DenseArgs &A, hipStream_t s) {
     constexpr int NT = 64 * (1 << K) / 16;
     int per_cu = 0, dev = 0, cus = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -669,7 +688,7 @@ hipError_t launch_dense_strip_t(float2 *amps, const float *mat_t, const DenseArg
     if (e != hipSuccess) return e;
     const uint64_t resident = uint64_t(std::max(1, per_cu)) * uint64_t(std::max(1, cus));
     const uint64_t grid = A.tiles < resident ? A.tiles : resident;
-    hipLaunchKernelGGL((k_dense_strip<K>), dim3(unsigned(grid)), dim3(NT), 0, s, amps, mat_t, A, pair_cols);
+    hipLaunchKernelGGL((k_dense_strip<K>), dim3(unsigned(grid)), dim3(NT), 0, s, amps, mat_t, A);
     return hipGetLastError();
 }
 
@@ -712,9 +731,7 @@ hipError_t launch_dense_t(float2 *amps, int n, const int *qubits, const float *m
         else A.sub_col[A.sub[l]] = uint8_t(l);
     }
     if constexpr (K >= 6) {
-        // column bit 0 is physical bit 0 when qubit 0 is outside the block
-        const int pair_cols = (qmask & 1ull) ? 0 : 1;
-        return launch_dense_strip_t<K>(amps, mat_t, A, pair_cols, s);
+        return launch_dense_strip_t<K>(amps, mat_t, A, s);
     } else {
         const uint64_t grid = A.tiles < 1024 ? A.tiles : 1024;
         hipLaunchKernelGGL((k_dense<K>), dim3(unsigned(grid)), dim3(256), 0, s, amps, mat_t, A);

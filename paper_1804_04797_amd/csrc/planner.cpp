@@ -233,6 +233,8 @@ namespace {
 // One plan.  The resident set of each pass maximises the summed weight of
 // the gates the pass can apply; gate i of the range weighs
 // 1 + lambda * (1 - i / count), so lambda > 0 favours finishing old gates.
+// nd_cap > 0: a pass applies at most nd_cap non-diagonal gates (the rest
+// wait for a later pass), which spreads the butterfly work over the passes.
 //
 // follow (out-of-place plans): each pass writes the map its final slot
 // layout gives, so the store needs no restoring exchange; the qubits in
@@ -240,7 +242,7 @@ namespace {
 // forced into the next pass.  Otherwise the map puts the next pass's best
 // qubits at the low bits and the pass restores that layout before its store.
 qsv_status build_plan_weighted(const qsv_circuit &c, int lb, int le, TileShape shape, double lambda,
-                               bool follow, Plan &out) {
+                               bool follow, int nd_cap, Plan &out) {
     const int n = c.n;
     const int R = shape.R, T = shape.T, L = R + T, cl = shape.c;
     if (R < 1 || T < 1 || L > n || L > kMaxSlots || cl < 1 || cl - 1 > T || cl > L)
@@ -355,6 +357,7 @@ qsv_status build_plan_weighted(const qsv_circuit &c, int lb, int le, TileShape s
                     if (dn[i] || pd[i] != 0) continue;
                     const G &x = d.g[i];
                     if (x.nd && !(sl.where[x.q0] >= 0 && sl.where[x.q0] < R)) continue;
+                    if (x.nd && nd_cap > 0 && m_nd >= nd_cap) continue;
                     if (int(pb.ops.size()) + 1 > budget) break;
                     // emit
                     switch (x.kind) {
@@ -382,6 +385,7 @@ qsv_status build_plan_weighted(const qsv_circuit &c, int lb, int le, TileShape s
                 if (int(pb.ops.size()) + 1 > budget) break;
             }
             if (remaining == 0 || int(pb.ops.size()) + 3 > budget) break;
+            if (nd_cap > 0 && m_nd >= nd_cap) break;  // the other gates wait for a later pass
             // Stuck: bring the qubits of ready non-diagonal gates into registers.
             std::vector<int> want;
             std::vector<int> next_use(n, 1 << 30);
@@ -669,13 +673,44 @@ int exchanges(const Plan &p) {
     return k;
 }
 
+// Non-diagonal (butterfly) ops of a pass program.
+int butterflies(const Pass &x) {
+    int k = 0;
+    for (int pc = 0; pc < x.prog.n_ops; ++pc) {
+        const int code = int(x.prog.ops[pc] & 0xff);
+        if (code == OP_XCHG) ++pc;
+        else if (code >= OP_H && code <= OP_SYDG) ++k;
+    }
+    return k;
+}
+
+// Estimated time of a plan in units of one full-state read and write.  A
+// pass streams the state once (its first pass, which usually generates the
+// state, only writes it); its butterflies cost 2 vector instructions per
+// amplitude each, and about kBalance of them take as long as the pass's
+// memory traffic at the copy rate (8 B per amplitude each way at ~6 TB/s
+// against ~39e12 vector instructions per second, less the pass's other
+// instructions).  A pass takes the longer of the two.
+constexpr double kBalance = 43.0;
+double plan_cost(const Plan &p) {
+    double t = 0;
+    for (size_t i = 0; i < p.passes.size(); ++i)
+        t += std::max(i == 0 ? 0.5 : 1.0, butterflies(p.passes[i]) / kBalance);
+    return t;
+}
+
 }  // namespace
 
 // The greedy selection is tried with a few gate weightings (and, out of
 // place, both map policies); the plan with the fewest passes, then the
-// fewest LDS exchanges, is kept.
+// fewest LDS exchanges, is kept.  Then the same greedy runs with a cap on
+// the butterflies per pass, from the even share upwards: a capped plan
+// with no more passes replaces it when its estimated time (plan_cost) is
+// lower, so that no pass is bound by vector-instruction issue while
+// another has room.
 qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Plan &out) {
     static const double kLambda[] = {0.0, 0.5, 1.0};
+    static const int kCapSlack[] = {0, 3, 6, 10, 15};
     const int nl = int(sizeof(kLambda) / sizeof(kLambda[0]));
     const int variants = nl * (shape.oop ? 2 : 1);
     // the variants are independent: plan them concurrently
@@ -685,11 +720,11 @@ qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Pla
     for (int v = 1; v < variants; ++v) {
         alt[size_t(v - 1)].reset(new Plan);
         pool.emplace_back([&, v] {
-            ast[size_t(v - 1)] = build_plan_weighted(c, lb, le, shape, kLambda[v % nl], v >= nl,
+            ast[size_t(v - 1)] = build_plan_weighted(c, lb, le, shape, kLambda[v % nl], v >= nl, 0,
                                                      *alt[size_t(v - 1)]);
         });
     }
-    qsv_status st = build_plan_weighted(c, lb, le, shape, kLambda[0], false, out);
+    qsv_status st = build_plan_weighted(c, lb, le, shape, kLambda[0], false, 0, out);
     for (auto &th : pool) th.join();
     if (st != QSV_OK) return st;
     for (int v = 1; v < variants; ++v) {
@@ -697,6 +732,36 @@ qsv_status build_plan(const qsv_circuit &c, int lb, int le, TileShape shape, Pla
         if (ast[size_t(v - 1)] != QSV_OK) continue;
         const size_t pa = a.passes.size(), po = out.passes.size();
         if (pa < po || (pa == po && exchanges(a) < exchanges(out))) out.passes = std::move(a.passes);
+    }
+    // balanced variants
+    const size_t P0 = out.passes.size();
+    int nd_total = 0;
+    for (const Pass &x : out.passes) nd_total += butterflies(x);
+    if (P0 < 2 || nd_total == 0) return QSV_OK;
+    const int share = int((size_t(nd_total) + P0 - 1) / P0);
+    const int ncap = int(sizeof(kCapSlack) / sizeof(kCapSlack[0]));
+    const int cvariants = ncap * variants;
+    std::vector<std::unique_ptr<Plan>> cap(static_cast<size_t>(cvariants));
+    std::vector<qsv_status> cst(static_cast<size_t>(cvariants), QSV_EINTERNAL);
+    pool.clear();
+    for (int v = 0; v < cvariants; ++v) {
+        cap[size_t(v)].reset(new Plan);
+        pool.emplace_back([&, v] {
+            const int w = v % variants;
+            cst[size_t(v)] = build_plan_weighted(c, lb, le, shape, kLambda[w % nl], w >= nl,
+                                                 share + kCapSlack[v / variants], *cap[size_t(v)]);
+        });
+    }
+    for (auto &th : pool) th.join();
+    double best = plan_cost(out);
+    for (int v = 0; v < cvariants; ++v) {
+        Plan &a = *cap[size_t(v)];
+        if (cst[size_t(v)] != QSV_OK || a.passes.size() > P0) continue;
+        const double ca = plan_cost(a);
+        if (ca < best - 1e-9) {
+            best = ca;
+            out.passes = std::move(a.passes);
+        }
     }
     return QSV_OK;
 }

@@ -290,6 +290,45 @@ def test_product_state_full_size_n34():
     torch.cuda.empty_cache()
 
 
+def test_full_circuit_n34_against_complex128():
+    """The whole 34-qubit circuit (566 gates, 128 GiB state) as the benchmark
+    runs it (|+> folded into the first pass, the FP64 norm into the last, the
+    tile shape and form the autotuner picks for it): 4096 sampled amplitudes
+    against the complex128 instantiation of the passes run on a 256 GiB state
+    after the complex64 one is freed (no oracle can hold 2^34 complex128
+    amplitudes on the host; the closed-form tests above check the same
+    circuit's CZ/T and single-qubit parts against the mathematics)."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("6x6m2-d30")
+    n = lat.n
+    xs = workloads.bitstrings(n, 4096, workloads.BITSTRING_SEED_BASE + 3)
+    bits = torch.from_numpy(xs.view(np.int64)).to(DEV)
+    out = torch.empty(xs.size, dtype=torch.complex128, device=DEV)
+    out64 = torch.empty(xs.size, dtype=torch.complex128, device=DEV)
+    nrm = torch.zeros(1, dtype=torch.float64, device=DEV)
+    opts = dict(reg_qubits=5, thread_qubits=8, low_qubits=4, plain=0, jit=2)
+    a = _state(n)
+    ws = qsv.alloc_workspace(c, 1, -1, opts)
+    qsv.sv_simulate(a, c, init_kind=qsv.INIT_PLUS, layer_begin=1, opts=opts, norm_out=nrm,
+                    bitstrings=bits, amps_out=out, c128=True, workspace=ws)
+    torch.cuda.synchronize()
+    norm32 = nrm.item()
+    del a, ws
+    torch.cuda.empty_cache()
+    ref = torch.empty(1 << n, dtype=torch.complex128, device=DEV)
+    qsv.sv_simulate_c128(ref, c, init_kind=qsv.INIT_PLUS, layer_begin=1, norm_out=nrm,
+                         bitstrings=bits, amps_out=out64)
+    torch.cuda.synchronize()
+    del ref
+    torch.cuda.empty_cache()
+    got, want = out.cpu().numpy(), out64.cpu().numpy()
+    d = float(np.max(np.abs(got - want)))
+    assert d <= TOL and d * 2 ** (n / 2) <= TOL_SCALED, d
+    assert abs(norm32 - 1.0) <= 1e-4 and abs(nrm.item() - 1.0) <= 1e-9, (norm32, nrm.item())
+    # a typical amplitude has modulus ~2^{-17}: the sample is not degenerate
+    assert 1e-7 < float(np.median(np.abs(want))) < 1e-4
+
+
 def test_unitarity_circuit_then_adjoint():
     _gpu()
     rows, cols, depth = 4, 6, 24
