@@ -18,6 +18,7 @@ namespace {
 __device__ __forceinline__ float2 f2(float x, float y) { return make_float2(x, y); }
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
 
 // e^{i pi k / 4}, k = 0..7
 __constant__ float c_wr[8] = {1.f, 0.70710678118654752f, 0.f, -0.70710678118654752f,
@@ -547,13 +548,18 @@ k_dense(float2 *__restrict__ amps, const float *__restrict__ mat_t, const DenseA
 // qubits and the 6 lowest other qubits; physical bit 0 is always among
 // them), so thread t's 16-byte accesses at local indices 2 (i NT + t) are
 // contiguous across a wave whatever the block's qubits.  Loads go to
-// registers, then to LDS planes (re, im; row stride 80 floats, so the 4 rows
-// one MFMA operand read covers fall on distinct bank groups) at each
-// element's (row, column); the results go back through the same planes and
-// leave in the same physical order.  Persistent workgroups walk the tiles;
+// registers, then to LDS planes (re, im) at each element's (row, column):
+// element (r, c) at 80 r + r / 4 + c (a stride of 80 puts the 4 rows one
+// MFMA operand read covers on distinct bank groups; the extra r / 4 spreads
+// rows that differ in their higher bits, as when the block holds the lowest
+// qubits and a wave's lanes walk its rows, over distinct banks, and is a
+// constant per operand read).  The results go back through the same planes
+// and leave in the same physical order (16-byte stores from every lane:
+// faster than storing the accumulators' 8-byte elements directly, even
+// where 16 lanes would write 16 consecutive amplitudes).  Persistent workgroups walk the tiles;
 // the next tile's loads are issued before the current tile's matrix-core work.
 template <int K>
-__global__ void __launch_bounds__(64 * (1 << K) / 16)
+__global__ void __launch_bounds__(64 * (1 << K) / 16, K == 6 ? 2 : 1)
 k_dense_strip(float2 *__restrict__ amps, const float *__restrict__ mat_t, const DenseArgs A) {
     constexpr int DIM = 1 << K;
     constexpr int WAVES = DIM / 16;
@@ -564,9 +570,11 @@ k_dense_strip(float2 *__restrict__ amps, const float *__restrict__ mat_t, const 
     constexpr int PAIRS = DIM * COLS / 2;    // amplitude pairs of a tile
     constexpr int PER = PAIRS / NT;          // pairs per thread (8)
     static_assert(PER * NT == PAIRS, "tile split");
-    __shared__ float xr[DIM * XS], xi[DIM * XS];
+    constexpr int PLANE = DIM * XS + DIM / 4;
+    __shared__ float xr[PLANE], xi[PLANE];
     const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
     const uint32_t lr = lane & 15u, lk = lane >> 4;
+    auto at = [](uint32_t row, uint32_t col) { return row * XS + (row >> 2) + col; };
     // this wave's strip of M: A operand of k-step ks, lane (k % 4) * 16 + i
     float mr[KS], mi[KS];
 #pragma unroll
@@ -577,18 +585,19 @@ k_dense_strip(float2 *__restrict__ amps, const float *__restrict__ mat_t, const 
     }
     // pair it of this thread: local index l = 2 (it NT + t).  Bits 1..TB of
     // l come from t and the higher ones from it, so its physical offset and
-    // its LDS position (row * XS + column) are sums of a per-thread part and
-    // a part common to the workgroup; l + 1 is the next amplitude in memory
-    // and sits d0 further on in LDS.
+    // its (row, column) are the OR of a per-thread part and a part common to
+    // the workgroup; l + 1 is the next amplitude in memory and differs in
+    // local bit 0 (a row or a column bit).
     constexpr int TB = K + 2;  // log2(NT)
     static_assert((1 << TB) == NT && (PER << TB) == PAIRS, "pair index split");
     uint64_t off_t = 0;
-    uint32_t pos_t = 0;
+    uint32_t row_t = 0, col_t = 0;
 #pragma unroll
     for (int b = 1; b <= TB; ++b) {
         if (!((t >> (b - 1)) & 1u)) continue;
         off_t |= 1ull << A.phys[b];
-        pos_t += ((A.rowmask >> b) & 1u) ? (1u << A.sub[b]) * XS : (1u << A.sub[b]);
+        if ((A.rowmask >> b) & 1u) row_t |= 1u << A.sub[b];
+        else col_t |= 1u << A.sub[b];
     }
     auto off_it = [&](int it) {
         uint64_t o = 0;
@@ -597,14 +606,18 @@ k_dense_strip(float2 *__restrict__ amps, const float *__restrict__ mat_t, const 
             if ((it >> (b - TB - 1)) & 1) o |= 1ull << A.phys[b];
         return o;
     };
-    auto pos_it = [&](int it) {
-        uint32_t q = 0;
+    auto rc_it = [&](int it, uint32_t &row, uint32_t &col) {
+        row = row_t;
+        col = col_t;
 #pragma unroll
-        for (int b = TB + 1; b < K + 6; ++b)
-            if ((it >> (b - TB - 1)) & 1) q += ((A.rowmask >> b) & 1u) ? (1u << A.sub[b]) * XS : (1u << A.sub[b]);
-        return q;
+        for (int b = TB + 1; b < K + 6; ++b) {
+            if (!((it >> (b - TB - 1)) & 1)) continue;
+            if ((A.rowmask >> b) & 1u) row |= 1u << A.sub[b];
+            else col |= 1u << A.sub[b];
+        }
     };
-    const uint32_t d0 = (A.rowmask & 1u) ? (1u << A.sub[0]) * XS : (1u << A.sub[0]);
+    const bool b0row = (A.rowmask & 1u) != 0;
+    const uint32_t b0 = 1u << A.sub[0];
     v4f nx[PER];
     auto tile_base = [&](uint64_t tile) {
         uint64_t base = 0;
@@ -624,11 +637,13 @@ k_dense_strip(float2 *__restrict__ amps, const float *__restrict__ mat_t, const 
         __syncthreads();  // the previous tile's LDS reads are complete
 #pragma unroll
         for (int it = 0; it < PER; ++it) {
-            const uint32_t at = pos_t + pos_it(it);
-            xr[at] = nx[it].x;
-            xi[at] = nx[it].y;
-            xr[at + d0] = nx[it].z;
-            xi[at + d0] = nx[it].w;
+            uint32_t row, col;
+            rc_it(it, row, col);
+            const uint32_t p0 = at(row, col), p1 = b0row ? at(row | b0, col) : at(row, col | b0);
+            xr[p0] = nx[it].x;
+            xi[p0] = nx[it].y;
+            xr[p1] = nx[it].z;
+            xi[p1] = nx[it].w;
         }
         __syncthreads();
         if (tile + gridDim.x < A.tiles) fetch(tile + gridDim.x);  // in flight during the MFMA work
@@ -645,8 +660,8 @@ k_dense_strip(float2 *__restrict__ amps, const float *__restrict__ mat_t, const 
             float br[4], bi[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                br[c] = xr[krow * XS + uint32_t(c) * 16u + lr];
-                bi[c] = xi[krow * XS + uint32_t(c) * 16u + lr];
+                br[c] = xr[at(krow, uint32_t(c) * 16u + lr)];
+                bi[c] = xi[at(krow, uint32_t(c) * 16u + lr)];
             }
 #pragma unroll
             for (int c = 0; c < 4; ++c) ai[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(mr[ks], bi[c], ai[c], 0, 0, 0);
@@ -663,15 +678,17 @@ k_dense_strip(float2 *__restrict__ amps, const float *__restrict__ mat_t, const 
         for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const uint32_t at = (w * 16u + 4u * lk + uint32_t(r)) * XS + uint32_t(c) * 16u + lr;
-                xr[at] = arr[c][r] - aii[c][r];
-                xi[at] = ai[c][r];
+                const uint32_t p = at(w * 16u + 4u * lk + uint32_t(r), uint32_t(c) * 16u + lr);
+                xr[p] = arr[c][r] - aii[c][r];
+                xi[p] = ai[c][r];
             }
         __syncthreads();
 #pragma unroll
         for (int it = 0; it < PER; ++it) {
-            const uint32_t at = pos_t + pos_it(it);
-            const v4f y = {xr[at], xi[at], xr[at + d0], xi[at + d0]};
+            uint32_t row, col;
+            rc_it(it, row, col);
+            const uint32_t p0 = at(row, col), p1 = b0row ? at(row | b0, col) : at(row, col | b0);
+            const v4f y = {xr[p0], xi[p0], xr[p1], xi[p1]};
             __builtin_nontemporal_store(y, reinterpret_cast<v4f *>(amps + (base | off_t | off_it(it))));
         }
     }
