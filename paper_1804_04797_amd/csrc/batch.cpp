@@ -178,7 +178,7 @@ qsv_status build_tables(qsv_batch *b, int lb) {
                 // the autotuned shape of this circuit (sv_tune / sv_tune_set), if any
                 qsv_fuse_opts t;
                 if (tuned_opts(c, lb, -1, &t) && t.reg_qubits > 0 && t.thread_qubits > 0 &&
-                    fused_shape_supported(t.reg_qubits, t.thread_qubits) &&
+                    compiled_shape_supported(t.reg_qubits, t.thread_qubits) &&
                     t.reg_qubits + t.thread_qubits <= c->n) {
                     sh.R = t.reg_qubits;
                     sh.T = t.thread_qubits;

@@ -130,7 +130,7 @@ qsv_status resolve_shape(const qsv_circuit *c, const qsv_fuse_opts *opts, TileSh
         else if (opts->reg_qubits || opts->thread_qubits) sh.c = std::min(5, sh.T + 1);
     }
     if (sh.R == 0) return QSV_OK;  // too small for a tile: plain path
-    if (!fused_shape_supported(sh.R, sh.T))
+    if (!compiled_shape_supported(sh.R, sh.T))
         return fail(QSV_EUNSUPPORTED, "no fused kernel compiled for this (reg, thread) shape");
     if (sh.R + sh.T > c->n) return fail(QSV_EUNSUPPORTED, "tile larger than the state");
     if (sh.c < 1 || sh.c - 1 > sh.T || sh.c > sh.R + sh.T)
@@ -435,6 +435,8 @@ qsv_status sv_apply_fused(void *amps, const qsv_circuit *c, uint64_t branch, int
         }
         return jit_launch(*plan, variant, amps, scratch, branch, 0, nullptr, s);
     }
+    if (!fused_shape_supported(sh.R, sh.T))
+        return fail(QSV_EUNSUPPORTED, "sv_apply_fused: this tile shape runs compiled passes only (jit >= 1)");
     if ((st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) return st;
     for (const Pass &p : plan->passes) {
         hipError_t e = launch_fused(static_cast<float2 *>(amps), c->n, sh.R, sh.T, p.prog, branch, s);

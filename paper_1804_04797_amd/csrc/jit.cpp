@@ -451,7 +451,10 @@ struct Gen {
     // LDS staging of one exchange.  When some register slot s of the new
     // layout takes an old register slot (perm[s] < R), the data splits into
     // two independent halves by that bit, which go through LDS one after the
-    // other: half the buffer, so twice the workgroups per CU.
+    // other: half the buffer, so twice the workgroups per CU.  A tile whose
+    // whole buffer exceeds the LDS (2^15 amplitudes) may also split on a
+    // qubit that is a thread slot in both layouts: in each half the threads
+    // whose old bit has that value store and those whose new bit has it load.
     //
     // The buffer is indexed in the slot coordinates of either the old layout
     // (the store is a plain register store, the load gathers) or the new one
@@ -465,6 +468,7 @@ struct Gen {
     struct XLayout {
         bool by_new = false;
         int split = -1;      // new register slot s of the split, or -1
+        int tsplit = -1;     // new thread slot s of a thread split (perm[s] >= R), or -1
         int skip = -1;       // coordinate left out (perm[s] or s), or -1
         int M = 0;           // registers per staged part
         int tau[kMaxSlots] = {};
@@ -509,14 +513,31 @@ struct Gen {
         // times the conflict-free rate, odd strides are conflict-free)
         return conflict(ww, T, 4, 32) + conflict(wr, T, 4, 32);
     }
-    void base_layout(XLayout &x, bool by_new, int split, const int *perm) const {
+    void base_layout(XLayout &x, bool by_new, int split, const int *perm, int tsplit = -1) const {
         x.by_new = by_new;
         x.split = split;
-        x.skip = split < 0 ? -1 : (by_new ? split : perm[split]);
+        x.tsplit = split < 0 ? tsplit : -1;
+        x.skip = split >= 0 ? (by_new ? split : perm[split]) : x.tsplit >= 0 ? (by_new ? x.tsplit : perm[x.tsplit]) : -1;
         x.M = split < 0 ? N : N / 2;
         int k = 0;
         for (int q = 0; q < R; ++q) x.tau[q] = (q == x.skip) ? 0 : k++;
-        for (int u = 0; u < T; ++u) x.sigma[u] = u;
+        k = 0;
+        for (int u = 0; u < T; ++u) x.sigma[u] = (R + u == x.skip) ? 0 : k++;
+    }
+    // thread slots of the buffer: all, or all but a thread split's
+    int buf_threads_log2(const XLayout &x) const { return x.tsplit >= 0 ? T - 1 : T; }
+    // new thread slot of a qubit that is a thread slot in both layouts, or
+    // -1: preferably one that keeps its slot (a thread then stores and loads
+    // in the same half, straight back into its registers) and is a wave
+    // index bit (whole waves sit out a half)
+    int tsplit_slot(const int *perm) const {
+        int best = -1, best_score = -1;
+        for (int u = 0; u < T; ++u) {
+            if (perm[R + u] < R) continue;
+            const int score = (perm[R + u] == R + u ? 2 : 0) + (u >= 6 && perm[R + u] - R >= 6 ? 1 : 0);
+            if (score > best_score) { best_score = score; best = R + u; }
+        }
+        return best;
     }
     int split_slot(const int *perm) const {  // prefer a register slot that stays in place
         for (int q = 0; q < R; ++q)
@@ -532,10 +553,13 @@ struct Gen {
         // (2^14-amplitude tiles); 2^13-amplitude tiles measured faster staged whole.
         // The persistent form holds two register sets, which limits it to two
         // workgroups per CU anyway: it always stages whole.
-        const bool big = (size_t(N + 1) << T) * (dp ? 16 : 8) > size_t(80) << 10;
-        const int split = (big && !persistent) ? split_slot(perm) : -1;
+        const size_t whole = (size_t(N + 1) << T) * (dp ? 16 : 8);
+        const bool big = whole > size_t(80) << 10;
+        const bool huge = whole > size_t(160) << 10;  // more than a workgroup's LDS
+        const int split = (big && (!persistent || huge)) ? split_slot(perm) : -1;
+        const int tsplit = (huge && split < 0) ? tsplit_slot(perm) : -1;
         XLayout best;
-        base_layout(best, false, split, perm);
+        base_layout(best, false, split, perm, tsplit);
         int best_cost = xcost(best, perm, inv);
         const int floor_cost = 2;  // store and load conflict-free
         uint64_t rng = 0x9E3779B97F4A7C15ull ^ uint64_t(uid);
@@ -545,14 +569,18 @@ struct Gen {
         };
         for (int trial = 0; trial < 4000 && best_cost > floor_cost; ++trial) {
             XLayout x;
-            base_layout(x, (trial & 1) != 0, split, perm);
+            base_layout(x, (trial & 1) != 0, split, perm, tsplit);
             if (trial >= 2) {
                 int regs[kMaxSlots], nr = 0;
                 for (int q = 0; q < R; ++q)
                     if (q != x.skip) regs[nr++] = q;
                 for (int i = nr - 1; i > 0; --i)
                     std::swap(x.tau[regs[i]], x.tau[regs[next() % uint64_t(i + 1)]]);
-                for (int u = T - 1; u > 0; --u) std::swap(x.sigma[u], x.sigma[next() % uint64_t(u + 1)]);
+                int thr[kMaxSlots], nt = 0;
+                for (int u = 0; u < T; ++u)
+                    if (R + u != x.skip) thr[nt++] = u;
+                for (int i = nt - 1; i > 0; --i)
+                    std::swap(x.sigma[thr[i]], x.sigma[thr[next() % uint64_t(i + 1)]]);
             }
             const int c = xcost(x, perm, inv);
             if (c < best_cost) { best_cost = c; best = x; }
@@ -614,36 +642,47 @@ struct Gen {
             return;
         }
         const XLayout x = choose_layout(perm, inv);
-        lds_elems = std::max(lds_elems, (x.M + 1) << T);
+        lds_elems = std::max(lds_elems, (x.M + 1) << buf_threads_log2(x));
         uint32_t ww[kMaxSlots], wr[kMaxSlots];
         lane_weights(x, perm, inv, ww, wr);
         const int id = uid++;
-        const int parts = x.split < 0 ? 1 : 2;
+        const int parts = (x.split < 0 && x.tsplit < 0) ? 1 : 2;
+        // thread split: the old and the new thread bit of the split qubit
+        const int tso = x.tsplit >= 0 ? perm[x.tsplit] - R : -1, tsn = x.tsplit >= 0 ? x.tsplit - R : -1;
         // register j of the old layout is stored at wb + offset, register j
         // of the new layout is loaded from rb + offset (into nv: the old
         // values of the second part are still to be stored)
         o << "{const unsigned wb" << id << " = " << lane_base(ww, x.M) << ";\n";
         o << "const unsigned rb" << id << " = " << lane_base(wr, x.M) << ";\n";
-        o << CT << " nv" << id << "[" << N << "];\n";
+        // a thread split on a qubit that keeps its thread slot: each thread
+        // stores and loads in the same half, so it loads into v directly
+        const bool direct = tso >= 0 && tso == tsn;
+        const std::string dst = direct ? std::string("v") : "nv" + std::to_string(id);
+        if (!direct) o << CT << " nv" << id << "[" << N << "];\n";
         for (int h = 0; h < parts; ++h) {
             o << "__syncthreads();\n";
+            if (tso >= 0) o << "if (((t >> " << tso << ") & 1u) == " << h << "u) {\n";
             for (int j = 0; j < N; ++j) {
-                if (parts == 2 && ((j >> perm[x.split]) & 1) != h) continue;
+                if (x.split >= 0 && ((j >> perm[x.split]) & 1) != h) continue;
                 uint32_t off = 0;
                 for (int s = 0; s < R; ++s)
                     if ((j >> s) & 1) off += xweight(x, x.by_new ? inv[s] : s);
                 o << "lds[wb" << id << "+" << off << "u]=v[" << j << "];\n";
             }
+            if (tso >= 0) o << "}\n";
             o << "__syncthreads();\n";
+            if (tsn >= 0) o << "if (((t >> " << tsn << ") & 1u) == " << h << "u) {\n";
             for (int j = 0; j < N; ++j) {
-                if (parts == 2 && ((j >> x.split) & 1) != h) continue;
+                if (x.split >= 0 && ((j >> x.split) & 1) != h) continue;
                 uint32_t off = 0;
                 for (int s = 0; s < R; ++s)
                     if ((j >> s) & 1) off += xweight(x, x.by_new ? s : perm[s]);
-                o << "nv" << id << "[" << j << "]=lds[rb" << id << "+" << off << "u];\n";
+                o << dst << "[" << j << "]=lds[rb" << id << "+" << off << "u];\n";
             }
+            if (tsn >= 0) o << "}\n";
         }
-        for (int j = 0; j < N; ++j) o << "v[" << j << "]=nv" << id << "[" << j << "];\n";
+        if (!direct)
+            for (int j = 0; j < N; ++j) o << "v[" << j << "]=nv" << id << "[" << j << "];\n";
         o << "}\n";
         if (carry) rename_factors(perm);
     }
@@ -1160,6 +1199,10 @@ qsv_status jit_prepare(Plan &plan, int variant) {
     }
     std::vector<size_t> lds;
     std::string src = jit_source(plan, &lds, variant);
+    for (size_t b : lds)  // a workgroup holds at most 160 KiB of LDS on gfx950
+        if (b > (size_t(160) << 10))
+            return fail(QSV_EUNSUPPORTED, "compiled pass needs more LDS than a workgroup holds "
+                                          "(tiles of 2^15 amplitudes run one tile per workgroup)");
     auto key = std::make_pair(dev, src);
     {
         std::lock_guard<std::mutex> g(g_mu);

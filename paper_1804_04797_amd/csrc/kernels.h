@@ -7,7 +7,12 @@
 
 namespace qsv {
 
+// (R, T) of the generic tile kernel (every fused path)
 bool fused_shape_supported(int R, int T);
+// (R, T) of the compiled passes: the generic shapes plus tiles of 2^15
+// amplitudes, whose exchanges only fit LDS staged in halves (one tile per
+// workgroup; compiled passes only)
+bool compiled_shape_supported(int R, int T);
 hipError_t launch_fused(float2 *amps, int n, int R, int T, const PassProg &p, uint64_t branch,
                         hipStream_t s);
 hipError_t launch_fused_batch(int R, int T, const BatchSeg *segs, int nseg, const BatchEntry *ents,

@@ -1186,6 +1186,8 @@ bool fused_shape_supported(int R, int T) {
     }
 }
 
+bool compiled_shape_supported(int R, int T) { return fused_shape_supported(R, T) || (R == 6 && T == 9); }
+
 hipError_t launch_fused(float2 *amps, int n, int R, int T, const PassProg &p, uint64_t branch,
                         hipStream_t s) {
     switch (R * 16 + T) {

@@ -139,6 +139,8 @@ extern "C" qsv_status sv_tune(void *amps_scratch, const qsv_circuit *c, int laye
         }
     }
     struct Cand { int R, T, c; };
+    // (tiles of 2^15 amplitudes, R = 6, T = 9, are not candidates: at 34
+    // qubits they save a pass but each pass runs 30 % longer)
     static const Cand cands[] = {{5, 8, 4}, {5, 8, 5}, {4, 8, 4}, {4, 8, 5}, {5, 9, 4}, {5, 9, 5},
                                  {6, 8, 4}, {5, 7, 4}, {4, 7, 4}};
     std::vector<std::pair<int, qsv_fuse_opts>> plans;

@@ -186,7 +186,7 @@ def test_plan_respects_dependencies(shape):
     assert 1 <= info["n_passes"] <= 25
 
 
-OOP_SHAPES = [(4, 6, 5), (3, 6, 4), (2, 3, 2), (3, 4, 3), (4, 7, 4), (5, 8, 4), (4, 6, 3)]
+OOP_SHAPES = [(4, 6, 5), (3, 6, 4), (2, 3, 2), (3, 4, 3), (4, 7, 4), (5, 8, 4), (4, 6, 3), (6, 9, 4)]
 
 
 @pytest.mark.parametrize("name", ["4x5-d10", "5x6-d16"])

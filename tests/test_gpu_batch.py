@@ -102,6 +102,21 @@ def test_batch_whole_state_tiles_replayed():
         torch.cuda.synchronize()
 
 
+def test_batch_21_and_22_qubit_entries():
+    """The compiled class's lower edge: states of 21 and 22 qubits (compiled
+    kernels from 2^21 amplitudes), one at the default tile shape and one at a
+    shape set with sv_tune_set, beside 16- and 13-qubit states of the generic
+    classes; every state against the oracle."""
+    items = _items([(21, 10), (22, 12), (16, 10), (13, 12)], 0x2122)
+    qsv.sv_tune_set(items[1][0], dict(reg_qubits=4, thread_qubits=7, low_qubits=4, plain=0, jit=1), layer_begin=1)
+    b = _batch(items)
+    states = [torch.empty(1 << n, dtype=torch.complex64, device=DEV) for _, _, n in items]
+    qsv.sv_batch_run(b, states, init_plus=True)
+    qsv.sv_batch_status(b)
+    for st, ref, (_, _, n) in zip(states, _refs(items), items):
+        _check(st, ref, n)
+
+
 PERSISTENT_OFF = ("the persistent batch launch is switched off: its first two runs on the device did not "
                   "finish (a run killed for silence, then a 120 s test timeout in sv_batch_status) and the "
                   "cause is not yet found")

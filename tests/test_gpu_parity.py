@@ -544,6 +544,54 @@ def test_out_of_place_sweeps(shape, jit):
         assert abs(nrm.item() - n2.item()) <= 1e-12
 
 
+@pytest.mark.parametrize("jit", [1, 2])
+def test_tiles_of_2_15_amplitudes(jit):
+    """R = 6, T = 9 (compiled passes only): exchanges staged in halves split
+    on a register slot or on a thread slot (the whole tile does not fit the
+    LDS).  A 24-qubit circuit against the oracle, every amplitude, in place
+    and out of place, from a loaded state and from |+>; the generic kernel
+    refuses the shape."""
+    _gpu()
+    rows, cols, depth, seed = 4, 6, 14, 0x69
+    n = rows * cols
+    c = qsv.circuit_create(rows, cols, None, depth, seed)
+    gates = _oracle_gates(c)
+    ref = sim.simulate(gates, n)
+    ref_plus = sim.run(np.full(1 << n, 2.0 ** (-n / 2), np.complex128), n, [g for g in gates if g[3] >= 1])
+    o = dict(reg_qubits=6, thread_qubits=9, low_qubits=4, plain=0, jit=jit)
+    assert qsv.sv_plan_info(c, opts=o)["n_passes"] >= 2
+    for oop in (1, -1):
+        a = _state(n)
+        qsv.sv_apply_fused(a, c, opts=dict(o, out_of_place=oop))
+        _check_full(a, ref, n)
+        b = torch.empty(1 << n, dtype=torch.complex64, device=DEV)
+        qsv.sv_simulate(b, c, init_kind=qsv.INIT_PLUS, layer_begin=1, opts=dict(o, out_of_place=oop))
+        _check_full(b, ref_plus, n)
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.sv_apply_fused(_state(n), c, opts=dict(o, jit=-1))
+    assert e.value.status == 5
+
+
+def test_tiles_of_2_15_amplitudes_full_size():
+    """The 30-qubit workload on tiles of 2^15 amplitudes against the stored
+    oracle amplitudes."""
+    _gpu()
+    spec, c, lat = _lattice_circuit("5x6-d20")
+    xs, ref = _golden("5x6-d20")
+    a = torch.empty(1 << 30, dtype=torch.complex64, device=DEV)
+    bits = torch.from_numpy(xs.view(np.int64)).to(DEV)
+    out = torch.empty(xs.size, dtype=torch.complex128, device=DEV)
+    nrm = torch.zeros(1, dtype=torch.float64, device=DEV)
+    o = dict(reg_qubits=6, thread_qubits=9, low_qubits=4, plain=0, jit=1)
+    qsv.sv_simulate(a, c, init_kind=qsv.INIT_PLUS, layer_begin=1, opts=o, norm_out=nrm, bitstrings=bits,
+                    amps_out=out, c128=True)
+    d = np.max(np.abs(out.cpu().numpy() - ref))
+    assert d <= TOL and d * 2 ** 15 <= TOL_SCALED, d
+    assert abs(nrm.item() - 1) <= 1e-4
+    del a
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("forms", [0b101, 0b010, 0b1])
 def test_per_pass_kernel_forms(forms):
     """jit = 3: each pass in its own kernel form (bit p of pass_forms = pass p
