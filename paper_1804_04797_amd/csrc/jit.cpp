@@ -547,17 +547,20 @@ struct Gen {
         return -1;
     }
     XLayout choose_layout(const int *perm, const int *inv) const {
-        // Staging in two halves (split >= 0, a register slot that stays a
-        // register slot) halves the buffer but doubles the barriers: worth it
-        // only when the whole tile's buffer would leave one workgroup per CU
-        // (2^14-amplitude tiles); 2^13-amplitude tiles measured faster staged whole.
-        // The persistent form holds two register sets, which limits it to two
-        // workgroups per CU anyway: it always stages whole.
+        // Staging in two halves (on a register slot that stays a register
+        // slot, else on a qubit that is a thread slot in both layouts) halves
+        // the buffer but doubles the barriers.  For one tile per workgroup it
+        // pays from 2^13-amplitude tiles up: twice the workgroups fit a CU
+        // (the 34-qubit sweep on (5, 8, 4): 286 against 312 ms).  The
+        // persistent form holds two register sets, which limits it to two
+        // workgroups per CU anyway: it stages whole (measured 6 % faster)
+        // unless the whole buffer exceeds the LDS (2^15-amplitude tiles).
         const size_t whole = (size_t(N + 1) << T) * (dp ? 16 : 8);
-        const bool big = whole > size_t(80) << 10;
+        const bool big = whole > size_t(32) << 10;
         const bool huge = whole > size_t(160) << 10;  // more than a workgroup's LDS
-        const int split = (big && (!persistent || huge)) ? split_slot(perm) : -1;
-        const int tsplit = (huge && split < 0) ? tsplit_slot(perm) : -1;
+        const bool halves = big && (!persistent || huge);
+        const int split = halves ? split_slot(perm) : -1;
+        const int tsplit = (halves && split < 0) ? tsplit_slot(perm) : -1;
         XLayout best;
         base_layout(best, false, split, perm, tsplit);
         int best_cost = xcost(best, perm, inv);
