@@ -87,7 +87,10 @@ typedef struct qsv_batch qsv_batch;      /* opaque */
  *                  per workgroup; 2 = the same kernels as persistent workgroups
  *                  that prefetch their next tile into registers while they
  *                  compute the current one; 3 = per pass: pass p persistent iff
- *                  bit p of pass_forms is set (p < 20); -1 = always use the
+ *                  bit p of pass_forms is set (p < 19); 4 = as 1, but each
+ *                  LDS exchange staged whole rather than in two halves (half
+ *                  the buffer, twice the workgroups per CU, twice the
+ *                  barriers: 1 stages in halves from 32 KiB buffers); -1 = always use the
  *                  generic pass kernel; 0 = 1 for states of 2^24 amplitudes or
  *                  more, else -1 (the environment variable QSV_JIT=0 makes 0
  *                  mean -1 everywhere; QSV_JIT_DUMP=<file> writes the last
@@ -541,10 +544,13 @@ void sv_batch_destroy(qsv_batch *b);
  * qubits) are planned; those within one pass of the fewest passes are timed
  * on the device on amps_scratch (device complex64[2^n], contents destroyed)
  * with the workspace given (out-of-place forms are considered only when it
- * holds a second state buffer; see sv_workspace_bytes) and the fastest is
- * written to *out (and its median time in ms to *best_ms, may be NULL).
- * States above 2^30 amplitudes are timed on the first 2^30 amplitudes' worth
- * of tiles of every pass.  The choice is remembered for this circuit content
+ * holds a second state buffer; see sv_workspace_bytes), the three fastest
+ * also in the persistent form (jit = 2) and with exchanges staged whole
+ * (jit = 4), and the fastest with each pass in the faster of forms 1 and 2
+ * (jit = 3); the fastest of all is written to *out (and its median time in
+ * ms to *best_ms, may be NULL).
+ * States above 2^31 amplitudes are timed on the first 2^31 amplitudes' worth
+ * of tiles of every pass; every timing is the median of five.  The choice is remembered for this circuit content
  * and layer range: later calls with opts == NULL use it.  This is the
  * scheduling preprocessing of Section 2.4 done by measurement.  Synchronises
  * the stream.  With the environment variable QSV_TUNE_CACHE=<file> the

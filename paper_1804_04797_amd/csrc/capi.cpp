@@ -227,6 +227,7 @@ int jit_mode(const qsv_circuit *c, const qsv_fuse_opts *opts) {
     }
     if (j < 0) return 0;
     if (j == 3) return 1 | kJitPerPass | int((opts->pass_forms & ((1u << kJitPassBits) - 1u)) << 8);
+    if (j == 4) return 1 | kJitWhole;
     return j >= 2 ? (1 | kJitLoop) : 1;
 }
 

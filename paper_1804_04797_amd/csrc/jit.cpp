@@ -476,6 +476,7 @@ struct Gen {
     };
     int lds_elems = 0;       // largest staging buffer of the pass (elements)
     bool persistent = false; // generating the persistent (prefetching) form
+    bool stage_whole = false; // one tile per workgroup, exchanges staged whole when they fit
     bool sample_rows = false; // sampling pass with one grid row per sibling branch
 
     uint32_t xweight(const XLayout &x, int q) const {
@@ -558,7 +559,7 @@ struct Gen {
         const size_t whole = (size_t(N + 1) << T) * (dp ? 16 : 8);
         const bool big = whole > size_t(32) << 10;
         const bool huge = whole > size_t(160) << 10;  // more than a workgroup's LDS
-        const bool halves = big && (!persistent || huge);
+        const bool halves = big && ((!persistent && !stage_whole) || huge);
         const int split = halves ? split_slot(perm) : -1;
         const int tsplit = (halves && split < 0) ? tsplit_slot(perm) : -1;
         XLayout best;
@@ -1143,6 +1144,7 @@ std::string jit_source(const Plan &plan, std::vector<size_t> *lds_bytes, int var
     std::string src = kPrelude;
     for (size_t p = 0; p < plan.passes.size(); ++p) {
         Gen g(plan.passes[p].prog, plan.R, plan.T, dp);
+        g.stage_whole = (variant & kJitWhole) != 0;
         bool uses_lds = false;
         const bool loop = jit_pass_loop(variant, p) && !batched;
         const bool last = p + 1 == plan.passes.size();

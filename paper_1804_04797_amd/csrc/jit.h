@@ -19,8 +19,9 @@ constexpr int kJitNorm = 8;
 constexpr int kJitDouble = 16;  // complex128 state (validation instantiation)
 constexpr int kJitBatched = 32; // state and branch per blockIdx.y from a batch entry table
 constexpr int kJitLoop = 64;    // persistent workgroups, next tile prefetched into registers
-constexpr int kJitPerPass = 128; // pass p persistent iff bit (8 + p) of the variant (p < 20)
-constexpr int kJitPassBits = 20;
+constexpr int kJitPerPass = 128; // pass p persistent iff bit (8 + p) of the variant (p < 19)
+constexpr int kJitPassBits = 19;
+constexpr int kJitWhole = 1 << 27; // one tile per workgroup, exchanges staged whole (not in halves)
 constexpr int kJitTiles = 1 << 28;  // with kJitSample: the listed tiles are stored whole instead
 constexpr int kJitSample = 1 << 29; // the last pass runs only listed tiles and writes listed amplitudes
 constexpr int kJitDot = 1 << 30; // the last pass stores nothing: FP64 <result|other> partials per tile

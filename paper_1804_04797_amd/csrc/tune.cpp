@@ -22,6 +22,7 @@
 #include <string>
 #include <vector>
 
+#include "jit.h"
 #include "qsv_internal.h"
 
 namespace qsv {
@@ -160,39 +161,40 @@ extern "C" qsv_status sv_tune(void *amps_scratch, const qsv_circuit *c, int laye
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(QSV_EHIP, "sv_tune: event create");
-    // States above 2^30 amplitudes are timed on a sample: every pass runs
-    // its first 2^(30 - R - T) tiles only (tens of thousands of workgroups,
+    // States above 2^31 amplitudes are timed on a sample: every pass runs
+    // its first 2^(31 - R - T) tiles only (tens of thousands of workgroups,
     // still many per CU), which ranks the candidates as the full sweep does
-    // at a sixteenth of the cost at 34 qubits.
-    constexpr int kSampleQubits = 30;
+    // at an eighth of the cost at 34 qubits.
+    constexpr int kSampleQubits = 31;
+    constexpr int kReps = 5;  // timings per candidate (median): forms differ by a few percent
     auto sample_tiles = [&](const qsv_fuse_opts &o) -> uint64_t {
         const int L = o.reg_qubits + o.thread_qubits;
         return (c->n > kSampleQubits && L > 0) ? (1ull << (kSampleQubits - L)) : 0;
     };
-    // warm-up (plans and compiles), then the median of three timed runs of
+    // warm-up (plans and compiles), then the median of kReps timed runs of
     // the whole sweep as sv_simulate runs it (state generated by the first
     // pass); compiled sweeps are timed pass by pass (summed)
     auto time_one = [&](const qsv_fuse_opts &o, float *ms) {
         std::vector<float> pm;
         if (time_sweep_passes(c, layer_begin, layer_end, &o, amps_scratch, workspace, ws_bytes, s,
                               sample_tiles(o), pm) == QSV_OK) {
-            float t[3];
-            for (int r = 0; r < 3; ++r) {
+            float t[kReps];
+            for (int r = 0; r < kReps; ++r) {
                 if (time_sweep_passes(c, layer_begin, layer_end, &o, amps_scratch, workspace, ws_bytes, s,
                                       sample_tiles(o), pm) != QSV_OK)
                     return false;
                 t[r] = 0.f;
                 for (float x : pm) t[r] += x;
             }
-            std::sort(t, t + 3);
-            *ms = t[1];
+            std::sort(t, t + kReps);
+            *ms = t[kReps / 2];
             return true;
         }
         if (sv_simulate(amps_scratch, c, 0, QSV_INIT_PLUS, 0, layer_begin, layer_end, &o, nullptr,
                         nullptr, 0, nullptr, 0, workspace, ws_bytes, stream) != QSV_OK)
             return false;
-        float t[3];
-        for (int r = 0; r < 3; ++r) {
+        float t[kReps];
+        for (int r = 0; r < kReps; ++r) {
             if (hipEventRecord(e0, s) != hipSuccess ||
                 sv_simulate(amps_scratch, c, 0, QSV_INIT_PLUS, 0, layer_begin, layer_end, &o, nullptr,
                             nullptr, 0, nullptr, 0, workspace, ws_bytes, stream) != QSV_OK ||
@@ -200,12 +202,12 @@ extern "C" qsv_status sv_tune(void *amps_scratch, const qsv_circuit *c, int laye
                 hipEventElapsedTime(&t[r], e0, e1) != hipSuccess)
                 return false;
         }
-        std::sort(t, t + 3);
-        *ms = t[1];
+        std::sort(t, t + kReps);
+        *ms = t[kReps / 2];
         return true;
     };
-    // shapes first with the default kernel form, then the persistent form of
-    // the fastest three
+    // shapes first with the default kernel form, then, for the fastest three,
+    // the persistent form and the form that stages exchanges whole
     std::vector<std::pair<float, qsv_fuse_opts>> timed;
     for (auto &pp : plans) {
         if (pp.first > best_passes + 1) continue;
@@ -218,32 +220,38 @@ extern "C" qsv_status sv_tune(void *amps_scratch, const qsv_circuit *c, int laye
               });
     const size_t shapes = timed.size();
     for (size_t i = 0; i < std::min<size_t>(3, shapes); ++i) {
-        qsv_fuse_opts o = timed[i].second;
-        o.jit = 2;
-        float ms;
-        if (time_one(o, &ms)) timed.push_back({ms, o});
+        for (int form : {2, 4}) {  // persistent; one tile per workgroup with exchanges staged whole
+            qsv_fuse_opts o = timed[i].second;
+            o.jit = form;
+            float ms;
+            if (time_one(o, &ms)) timed.push_back({ms, o});
+        }
     }
     if (shapes > 0) {
         // per-pass kernel form for the fastest shape: each pass in the faster
-        // of the two forms (median of three timings per pass)
+        // of the two forms (median of kReps timings per pass)
         qsv_fuse_opts o1 = timed[0].second, o2 = timed[0].second;
         o1.jit = 1;
         o2.jit = 2;
-        std::vector<std::vector<float>> t1(3), t2(3);
+        std::vector<std::vector<float>> t1(kReps), t2(kReps);
         bool ok = true;
-        for (int r = 0; r < 3 && ok; ++r)
+        for (int r = 0; r < kReps && ok; ++r)
             ok = time_sweep_passes(c, layer_begin, layer_end, &o1, amps_scratch, workspace, ws_bytes, s,
                                    sample_tiles(o1), t1[r]) == QSV_OK &&
                  time_sweep_passes(c, layer_begin, layer_end, &o2, amps_scratch, workspace, ws_bytes, s,
                                    sample_tiles(o2), t2[r]) == QSV_OK;
         if (ok && t1[0].size() == t2[0].size()) {
             uint32_t mask = 0;
-            const size_t np = std::min<size_t>(t1[0].size(), 23);
+            const size_t np = std::min<size_t>(t1[0].size(), kJitPassBits);
             for (size_t p = 0; p < np; ++p) {
-                float a[3] = {t1[0][p], t1[1][p], t1[2][p]}, b[3] = {t2[0][p], t2[1][p], t2[2][p]};
-                std::sort(a, a + 3);
-                std::sort(b, b + 3);
-                if (b[1] < a[1]) mask |= 1u << p;
+                float a[kReps], b[kReps];
+                for (int r = 0; r < kReps; ++r) {
+                    a[r] = t1[size_t(r)][p];
+                    b[r] = t2[size_t(r)][p];
+                }
+                std::sort(a, a + kReps);
+                std::sort(b, b + kReps);
+                if (b[kReps / 2] < a[kReps / 2]) mask |= 1u << p;
             }
             const uint32_t all = np >= 32 ? ~0u : ((1u << np) - 1);
             if (mask != 0 && mask != all) {

@@ -104,11 +104,13 @@ def _opts(shape, jit=0):
     return dict(reg_qubits=shape[0], thread_qubits=shape[1], low_qubits=shape[2], plain=0, jit=jit)
 
 
-@pytest.mark.parametrize("jit", [-1, 1, 2])
+@pytest.mark.parametrize("jit", [-1, 1, 2, 4])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_fused_4x5_all_shapes(shape, jit):
-    """Generic pass kernel (jit=-1), per-pass compiled kernels (jit=1) and their
-    persistent prefetching form (jit=2)."""
+    """Generic pass kernel (jit=-1), per-pass compiled kernels (jit=1: LDS
+    exchanges staged in halves from 32 KiB buffers), their persistent
+    prefetching form (jit=2) and the one-tile form with exchanges staged whole
+    (jit=4)."""
     _gpu()
     spec, c, lat = _lattice_circuit("4x5-d10")
     ref = sim.simulate(_oracle_gates(c), lat.n)
