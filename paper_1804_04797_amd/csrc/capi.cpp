@@ -301,7 +301,7 @@ qsv_status qsv_release_device_buffers(void) {
     return QSV_OK;
 }
 
-const char *qsv_version(void) { return "qsv 0.8 gfx950"; }
+const char *qsv_version(void) { return "qsv 0.9 gfx950"; }
 
 qsv_status circuit_create(int rows, int cols, const uint8_t *present, int depth, uint64_t seed,
                           const qsv_gate *gates, size_t n_gates, qsv_circuit **out) {

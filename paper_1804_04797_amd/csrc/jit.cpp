@@ -459,12 +459,18 @@ struct Gen {
     // The buffer is indexed in the slot coordinates of either the old layout
     // (the store is a plain register store, the load gathers) or the new one
     // (the other way round), leaving out the split slot.  Coordinate q has the
-    // element weight 2^tau[q] (register slots) or (M + 1) * 2^sigma[q - R]
-    // (thread slots), M = registers per half (or all): tau and sigma are bit
-    // permutations, so the address is injective and stays below (M + 1) * 2^T,
-    // and each register's offset is a literal.  They are chosen so that the
-    // lanes the LDS serves together hit distinct banks on the store and on the
-    // load.
+    // element weight 2^tau[q] (register slots) or (M + 1) * 2^k + d[k] with
+    // k = sigma[q - R] (thread slots), M = registers per half (or all): tau
+    // and sigma are bit permutations, and d[k] >= d[0] + ... + d[k-1] - 1
+    // keeps the weights super-increasing (each exceeds the sum of all smaller
+    // ones), so the address is injective and stays below
+    // (M + 1) * 2^T + d[0] + ... + d[T-1]; each register's offset is a
+    // literal.  They are chosen so that the lanes the LDS serves together hit
+    // distinct banks on the store and on the load.  With d = 0 the weights of
+    // the thread coordinates from k = 4 on are multiples of 16 elements, i.e.
+    // all in one bank pair; a nonzero d[k] moves such a coordinate to another
+    // bank pair, which an exchange needs when more than four thread
+    // coordinates sit at the low lane bits of the store or of the load.
     struct XLayout {
         bool by_new = false;
         int split = -1;      // new register slot s of the split, or -1
@@ -473,6 +479,8 @@ struct Gen {
         int M = 0;           // registers per staged part
         int tau[kMaxSlots] = {};
         int sigma[kMaxSlots] = {};
+        uint32_t d[kMaxSlots] = {};  // extra weight of the thread coordinate of rank k
+        uint32_t dsum = 0;           // sum of d
     };
     int lds_elems = 0;       // largest staging buffer of the pass (elements)
     bool persistent = false; // generating the persistent (prefetching) form
@@ -481,20 +489,26 @@ struct Gen {
 
     uint32_t xweight(const XLayout &x, int q) const {
         if (q == x.skip) return 0;
-        return q < R ? (1u << x.tau[q]) : (uint32_t(x.M + 1) << x.sigma[q - R]);
+        return q < R ? (1u << x.tau[q]) : (uint32_t(x.M + 1) << x.sigma[q - R]) + x.d[x.sigma[q - R]];
     }
     // worst number of lanes sharing a bank pair among the lanes whose low
     // `lanes_log2` bits vary (lane bit u carries weight w[u]), for 8-byte
-    // elements on `banks` 4-byte banks
+    // elements on `banks` 4-byte banks.  A lane bit of weight 0 is the thread
+    // split of a part: the lanes with the other value of that bit sit the
+    // part out, so it does not vary among the lanes served together.
     static int conflict(const uint32_t *w, int nb, int lanes_log2, int banks) {
         const int bits = std::min(nb, lanes_log2);
         const uint32_t mod = uint32_t(banks / 2);
+        uint32_t wv[kMaxSlots];
+        int nv = 0;
+        for (int u = 0; u < bits; ++u)
+            if (w[u]) wv[nv++] = w[u];
         int cnt[64] = {};
         int worst = 0;
-        for (int l = 0; l < (1 << bits); ++l) {
+        for (int l = 0; l < (1 << nv); ++l) {
             uint32_t a = 0;
-            for (int u = 0; u < bits; ++u)
-                if ((l >> u) & 1) a += w[u];
+            for (int u = 0; u < nv; ++u)
+                if ((l >> u) & 1) a += wv[u];
             worst = std::max(worst, ++cnt[a % mod]);
         }
         return worst;
@@ -527,6 +541,8 @@ struct Gen {
     }
     // thread slots of the buffer: all, or all but a thread split's
     int buf_threads_log2(const XLayout &x) const { return x.tsplit >= 0 ? T - 1 : T; }
+    // elements of the staging buffer (one past the largest address)
+    int buf_elems(const XLayout &x) const { return ((x.M + 1) << buf_threads_log2(x)) + int(x.dsum); }
     // new thread slot of a qubit that is a thread slot in both layouts, or
     // -1: preferably one that keeps its slot (a thread then stores and loads
     // in the same half, straight back into its registers) and is a wave
@@ -546,6 +562,42 @@ struct Gen {
         for (int q = 0; q < R; ++q)
             if (perm[q] < R) return q;
         return -1;
+    }
+    // Every element of every part has one address, the same for its store
+    // (old thread, old register) and its load (new thread, new register),
+    // below buf_elems, and no two elements of a part share one.
+    bool layout_valid(const XLayout &x, const int *perm, const int *inv) const {
+        uint32_t ww[kMaxSlots], wr[kMaxSlots];
+        lane_weights(x, perm, inv, ww, wr);
+        const int parts = (x.split < 0 && x.tsplit < 0) ? 1 : 2;
+        const int tso = x.tsplit >= 0 ? perm[x.tsplit] - R : -1;
+        const uint32_t lim = uint32_t(buf_elems(x));
+        std::vector<char> used(lim);
+        for (int h = 0; h < parts; ++h) {
+            std::fill(used.begin(), used.end(), 0);
+            for (uint32_t t = 0; t < (1u << T); ++t) {
+                if (tso >= 0 && ((t >> tso) & 1u) != uint32_t(h)) continue;
+                for (int j = 0; j < N; ++j) {
+                    if (x.split >= 0 && ((j >> perm[x.split]) & 1) != h) continue;
+                    int val[kMaxSlots];
+                    for (int s2 = 0; s2 < L; ++s2) val[s2] = s2 < R ? (j >> s2) & 1 : int((t >> (s2 - R)) & 1u);
+                    uint32_t st = 0, ld = 0, tn = 0;
+                    int jn = 0;
+                    for (int u = 0; u < T; ++u) {
+                        if ((t >> u) & 1u) st += ww[u];
+                        if (val[perm[R + u]]) { ld += wr[u]; tn |= 1u << u; }
+                    }
+                    for (int s2 = 0; s2 < R; ++s2) {
+                        if ((j >> s2) & 1) st += xweight(x, x.by_new ? inv[s2] : s2);
+                        if (val[perm[s2]]) { ld += xweight(x, x.by_new ? s2 : perm[s2]); jn |= 1 << s2; }
+                    }
+                    (void)tn; (void)jn;
+                    if (st != ld || st >= lim || used[st]) return false;
+                    used[st] = 1;
+                }
+            }
+        }
+        return true;
     }
     XLayout choose_layout(const int *perm, const int *inv) const {
         // Staging in two halves (on a register slot that stays a register
@@ -571,7 +623,9 @@ struct Gen {
             rng ^= rng << 13; rng ^= rng >> 7; rng ^= rng << 17;
             return rng;
         };
-        for (int trial = 0; trial < 4000 && best_cost > floor_cost; ++trial) {
+        // extra weights (complex64 staging only): at most kMaxPad elements in all
+        constexpr uint32_t kMaxPad = 256;
+        for (int trial = 0; trial < 8000 && best_cost > floor_cost; ++trial) {
             XLayout x;
             base_layout(x, (trial & 1) != 0, split, perm, tsplit);
             if (trial >= 2) {
@@ -586,8 +640,29 @@ struct Gen {
                 for (int i = nt - 1; i > 0; --i)
                     std::swap(x.sigma[thr[i]], x.sigma[thr[next() % uint64_t(i + 1)]]);
             }
+            if (!dp && trial >= 4000) {
+                // move some of the thread coordinates of rank 4 and up off
+                // the bank pair of multiples of 16 (their weight mod 16 is d)
+                uint32_t D = 0;
+                const int tb = buf_threads_log2(x);
+                for (int k = 4; k < tb; ++k) {
+                    const uint32_t lo = D > 0 ? D - 1 : 0;
+                    uint32_t dk = lo;
+                    if (next() & 1) {
+                        const uint32_t r = uint32_t(next() % 16);
+                        dk = lo + ((r + 16 - lo % 16) % 16);
+                    }
+                    x.d[k] = dk;
+                    D += dk;
+                }
+                x.dsum = D;
+                if (D > kMaxPad) continue;
+            }
             const int c = xcost(x, perm, inv);
-            if (c < best_cost) { best_cost = c; best = x; }
+            if (c < best_cost || (c == best_cost && x.dsum < best.dsum)) { best_cost = c; best = x; }
+        }
+        if (best.dsum && !layout_valid(best, perm, inv)) {  // keep to the plain weights
+            base_layout(best, false, split, perm, tsplit);
         }
         return best;
     }
@@ -646,7 +721,7 @@ struct Gen {
             return;
         }
         const XLayout x = choose_layout(perm, inv);
-        lds_elems = std::max(lds_elems, (x.M + 1) << buf_threads_log2(x));
+        lds_elems = std::max(lds_elems, buf_elems(x));
         uint32_t ww[kMaxSlots], wr[kMaxSlots];
         lane_weights(x, perm, inv, ww, wr);
         const int id = uid++;
