@@ -264,7 +264,10 @@ qsv_status sv_apply_fused(void *amps, const qsv_circuit *c, uint64_t branch,
  * The init kinds are those of sv_init (Section 2: the opening Hadamard
  * layer makes |+>^n from |0>).  workspace / ws_bytes as for
  * sv_apply_fused; the norm needs it (its partial sums live there:
- * QSV_EINVAL without a workspace of sv_workspace_bytes bytes).
+ * QSV_EINVAL without a workspace of sv_workspace_bytes bytes).  With m > 0
+ * the bitstrings are range-checked as in sv_amplitudes, after the plan is
+ * built and before anything is enqueued (the call then waits for the work
+ * already queued on stream; QSV_ERANGE enqueues nothing).
  */
 qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int init_kind,
                        uint64_t basis, int layer_begin, int layer_end, const qsv_fuse_opts *opts,
@@ -299,7 +302,7 @@ qsv_status sv_simulate_dot(void *amps, const qsv_circuit *c, uint64_t branch, in
  * fast path; tile shape fixed at 4 register x 8 thread qubits, in place.
  * Output amplitudes are complex128[m]; norm_out_dev may be NULL (else the
  * norm's partial sums go to workspace, as for sv_simulate).  Needs
- * 12 <= n <= 34.
+ * 12 <= n <= 34.  Bitstrings are range-checked as in sv_amplitudes.
  */
 qsv_status sv_simulate_c128(void *amps, const qsv_circuit *c, uint64_t branch, int init_kind,
                             uint64_t basis, int layer_begin, int layer_end, double *norm_out_dev,
@@ -407,9 +410,12 @@ void sv_sampler_destroy(qsv_sampler *s);
 /*
  * sv_amplitudes - gather alpha_x for m bitstrings (Task 2 of Section 1).
  * bitstrings_dev: device uint64[m]; out_dev: device complex64[m]
- * (out_c128 = 0) or complex128[m] (out_c128 = 1).  A bitstring >= 2^n makes
- * the kernel write NaN for that entry (ranges cannot be checked on the host
- * without a copy).
+ * (out_c128 = 0) or complex128[m] (out_c128 = 1).  Range check: before
+ * anything is enqueued, a small kernel tests every bitstring against 2^n and
+ * the call waits for the stream (so for the work queued before it); a
+ * bitstring >= 2^n returns QSV_ERANGE with nothing enqueued.  On a stream
+ * under graph capture the wait is impossible: the check is skipped and the
+ * gather writes NaN for such entries.  Otherwise asynchronous on stream.
  */
 qsv_status sv_amplitudes(const void *amps, int n_qubits, const uint64_t *bitstrings_dev,
                          size_t m, void *out_dev, int out_c128, void *stream);
@@ -521,7 +527,9 @@ qsv_status sv_branch_combine_full(const void *a_states, const void *b_states, si
  * m > 0, the amplitudes at bitstrings_dev[i*m .. i*m+m-1] (device uint64,
  * local numbering of entry i) are written to amp_table_dev[i*m + k] (device
  * complex64).  The first call captures a graph for these pointers; later
- * calls with the same pointers replay it.  Asynchronous on stream.
+ * calls with the same pointers replay it.  Asynchronous on stream; the
+ * bitstrings are not range-checked (the replayed graph cannot wait for a
+ * check): an entry's bitstring >= 2^n_i gives NaN in its table slot.
  * sv_batch_status: synchronises stream and reports QSV_EINTERNAL if a wait of
  * a persistent launch gave up since the last status call (its bounded spin
  * ran out, or sv_batch_abort was called): the results of that run are then

@@ -90,6 +90,41 @@ qsv_status check_state(const void *amps, int n) {
     return QSV_OK;
 }
 
+// Range check of m device bitstrings against 2^n, before a call enqueues
+// anything: a small kernel raises a flag in mapped host memory (one word per
+// thread and device, allocated on first use and kept), and the host waits
+// for the stream, so the call returns QSV_ERANGE with nothing enqueued.  On
+// a stream under graph capture the wait is impossible: the check is skipped
+// and the gather writes NaN for such entries.
+qsv_status check_bitstrings(const uint64_t *xs, size_t m, int n, hipStream_t s, const char *who) {
+    if (m == 0 || n >= 64) return QSV_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cs);
+    if (e != hipSuccess) return hip_fail(e, who);
+    if (cs != hipStreamCaptureStatusNone) return QSV_OK;
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, who);
+    thread_local std::map<int, std::pair<unsigned int *, unsigned int *>> flags;  // host, device address
+    auto &f = flags[dev];
+    if (!f.first) {
+        unsigned int *h = nullptr, *d = nullptr;
+        if ((e = hipHostMalloc(reinterpret_cast<void **>(&h), sizeof(unsigned int),
+                               hipHostMallocCoherent | hipHostMallocMapped)) != hipSuccess)
+            return fail(QSV_ENOMEM, std::string(who) + ": range-check flag");
+        if ((e = hipHostGetDevicePointer(reinterpret_cast<void **>(&d), h, 0)) != hipSuccess) {
+            (void)hipHostFree(h);
+            return hip_fail(e, who);
+        }
+        f = {h, d};
+    }
+    __atomic_store_n(f.first, 0u, __ATOMIC_SEQ_CST);
+    if ((e = launch_check_range(xs, m, n, f.second, s)) != hipSuccess) return hip_fail(e, who);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, who);
+    if (__atomic_load_n(f.first, __ATOMIC_SEQ_CST))
+        return fail(QSV_ERANGE, std::string(who) + ": bitstring >= 2^n");
+    return QSV_OK;
+}
+
 // Caller-owned workspace of a sweep call (sv_workspace_bytes): when the
 // plan runs out of place, the second state buffer (8 * 2^n bytes) at offset
 // 0 and the FP64 partial sums of the norm or inner-product epilogue after
@@ -729,6 +764,9 @@ qsv_status sv_amplitudes(const void *amps, int n_qubits, const uint64_t *bitstri
     if (st != QSV_OK) return st;
     if (m && (!bitstrings_dev || !out_dev)) return fail(QSV_EINVAL, "sv_amplitudes: null buffer");
     if ((st = check_device()) != QSV_OK) return st;
+    if ((st = check_bitstrings(bitstrings_dev, m, n_qubits, static_cast<hipStream_t>(stream), "sv_amplitudes")) !=
+        QSV_OK)
+        return st;
     hipError_t e = launch_gather(static_cast<const float2 *>(amps), n_qubits, bitstrings_dev, m,
                                  out_dev, out_c128 ? 1 : 0, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? QSV_OK : hip_fail(e, "sv_amplitudes");
@@ -981,6 +1019,7 @@ qsv_status sv_simulate(void *amps, const qsv_circuit *c, uint64_t branch, int in
     } else if (fused && (st = get_plan(c, layer_begin, layer_end, sh, plan)) != QSV_OK) {
         return st;
     }
+    if ((st = check_bitstrings(bitstrings_dev, m, c->n, s, "sv_simulate")) != QSV_OK) return st;
     if (jm && !plan->passes.empty()) {
         // initial state generated by the first pass, norm by the last
         const int variant = kJitInit | init_kind | (norm_out_dev ? kJitNorm : 0) | (jm & ~3);
@@ -1107,6 +1146,7 @@ qsv_status sv_simulate_c128(void *amps, const qsv_circuit *c, uint64_t branch, i
         if ((st = jit_prepare(*plan, variant)) != QSV_OK) return st;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = check_bitstrings(bitstrings_dev, m, c->n, s, "sv_simulate_c128")) != QSV_OK) return st;
     double *part = norm_out_dev ? static_cast<double *>(workspace) : nullptr;
     if ((st = jit_launch(*plan, variant, amps, nullptr, branch, basis, part, s)) != QSV_OK) return st;
     if (norm_out_dev) {

@@ -40,6 +40,8 @@ hipError_t launch_gather(const float2 *amps, int n, const uint64_t *xs, uint64_t
                          int c128, hipStream_t s);
 hipError_t launch_gather_c128(const void *amps, int n, const uint64_t *xs, uint64_t m, void *out,
                               hipStream_t s);
+// sets *flag (mapped host memory) when some xs[k] >= 2^n
+hipError_t launch_check_range(const uint64_t *xs, uint64_t m, int n, unsigned int *flag, hipStream_t s);
 hipError_t launch_norm(const float2 *amps, int n, double *out, double *partials, hipStream_t s);
 // partial sums launch_norm writes for a state of 2^n amplitudes (at most 65536)
 size_t norm_partial_count(int n);

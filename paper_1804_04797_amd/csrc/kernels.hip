@@ -853,6 +853,16 @@ k_gather(const float2 *__restrict__ a, uint64_t dim, const uint64_t *__restrict_
     else reinterpret_cast<float2 *>(out)[k] = v;
 }
 
+// Range check of device bitstrings: raises *flag (mapped host memory) when
+// some xs[k] >= dim.  Grid-stride; the flag is only ever set, never read here.
+__global__ void __launch_bounds__(256)
+k_check_range(const uint64_t *__restrict__ xs, uint64_t m, uint64_t dim, unsigned int *flag) {
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    bool bad = false;
+    for (uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < m; k += stride) bad = bad || xs[k] >= dim;
+    if (bad) __hip_atomic_fetch_or(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ void __launch_bounds__(256)
 k_gather_c128(const double2 *__restrict__ a, uint64_t dim, const uint64_t *__restrict__ xs,
               uint64_t m, double2 *__restrict__ out) {
@@ -1251,6 +1261,12 @@ hipError_t launch_gather(const float2 *amps, int n, const uint64_t *xs, uint64_t
     if (m == 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather, dim3(grid_for(m, 256, 1u << 30)), dim3(256), 0, s, amps,
                        1ull << n, xs, m, out, c128);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_range(const uint64_t *xs, uint64_t m, int n, unsigned int *flag, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_range, dim3(grid_for(m, 256, 1024)), dim3(256), 0, s, xs, m, 1ull << n, flag);
     return hipGetLastError();
 }
 

@@ -107,6 +107,47 @@ def test_stream_copy_exact(nbytes):
         qsv.sv_stream_copy(src, src[16:], 64)
 
 
+def test_amplitudes_refuse_out_of_range_bitstrings():
+    """A bitstring >= 2^n: QSV_ERANGE and nothing enqueued (the output keeps
+    its contents); in range, the gather returns the state's entries."""
+    n = 16
+    g = torch.Generator().manual_seed(7)
+    st = torch.complex(torch.randn(1 << n, generator=g), torch.randn(1 << n, generator=g)).to(DEV)
+    out = torch.full((3,), complex(7.0, -7.0), dtype=torch.complex64, device=DEV)
+    bad = torch.tensor([0, 5, 1 << n], dtype=torch.int64, device=DEV)
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.sv_amplitudes(st, n, bad, out)
+    assert e.value.status == 2
+    torch.cuda.synchronize()
+    assert torch.all(out == complex(7.0, -7.0))
+    good = torch.tensor([0, 5, (1 << n) - 1], dtype=torch.int64, device=DEV)
+    qsv.sv_amplitudes(st, n, good, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out.cpu(), st.cpu()[[0, 5, (1 << n) - 1]])
+
+
+@pytest.mark.parametrize("jit", [1, -1])
+def test_simulate_with_out_of_range_bitstring_enqueues_nothing(jit):
+    """sv_simulate (compiled and generic path) refuses a bitstring >= 2^n
+    before it enqueues anything: the state and the outputs keep their
+    contents."""
+    c = qsv.circuit_create(4, 5, None, 10, 99)
+    n = 20
+    opts = {"reg_qubits": 5, "thread_qubits": 8, "low_qubits": 4, "jit": jit}
+    amps = torch.full((1 << n,), complex(3.0, 1.0), dtype=torch.complex64, device=DEV)
+    out = torch.full((2,), complex(7.0, -7.0), dtype=torch.complex64, device=DEV)
+    nrm = torch.full((1,), -1.0, dtype=torch.float64, device=DEV)
+    xs = torch.tensor([1, 1 << (n + 3)], dtype=torch.int64, device=DEV)
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.sv_simulate(amps, c, init_kind=qsv.INIT_PLUS, layer_begin=1, opts=opts, norm_out=nrm,
+                        bitstrings=xs, amps_out=out)
+    assert e.value.status == 2
+    torch.cuda.synchronize()
+    assert torch.all(amps == complex(3.0, 1.0))
+    assert torch.all(out == complex(7.0, -7.0))
+    assert nrm.item() == -1.0
+
+
 def test_tune_and_code_caches_across_processes(tmp_path):
     """QSV_TUNE_CACHE and QSV_JIT_CACHE: a second process takes the tuned
     options from the file and the compiled kernels from the directory, so its
