@@ -208,7 +208,10 @@ qsv_status circuit_branch_stage(const qsv_circuit *c, int level_begin, int level
 /*
  * sv_init - write a basis or uniform state into amps (device complex64[2^n]).
  *   kind 0 = |0...0>, 1 = |+>^n (every amplitude 2^{-n/2}, i.e. layer 0
- *   applied), 2 = |basis>.
+ *   applied), 2 = |basis>.  The simulated circuits start from |0...0> and
+ *   open with a Hadamard on every qubit (Section 2, the random circuit
+ *   rules); |basis> is the start of the adjoint half-sweep of Task 2
+ *   (Section 2.2).  QSV_ERANGE for basis >= 2^n; asynchronous on stream.
  */
 enum { QSV_INIT_ZERO = 0, QSV_INIT_PLUS = 1, QSV_INIT_BASIS = 2 };
 qsv_status sv_init(void *amps, int n_qubits, int kind, uint64_t basis, void *stream);
