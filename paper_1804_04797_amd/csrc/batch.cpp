@@ -76,6 +76,11 @@ struct qsv_batch {
     // captured graph and the arguments it was captured for
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
+    // side streams of the capture: the compiled plans' launches become
+    // parallel branches of the graph (fork and join events)
+    std::vector<hipStream_t> lanes;
+    std::vector<hipEvent_t> lane_done;
+    hipEvent_t fork = nullptr;
     std::vector<void *> g_ptrs;
     int g_init = -1;
     const void *g_bits = nullptr;
@@ -116,6 +121,7 @@ void drop_graph(qsv_batch *b) {
 // per plan shared by >= 8 entries): states of at most 2^14 amplitudes on a
 // tile that holds the whole state, the others on the batch's tile shape.
 constexpr int kBigState = 21;
+constexpr int kLanes = 4;  // side streams of a batch's capture
 constexpr int kLdsState = 14;
 bool big_state(const qsv_batch *b, int n) { return b->jit_mode >= 0 && n >= kBigState; }
 
@@ -391,6 +397,18 @@ qsv_status sv_batch_create(const qsv_circuit *const *circs, const uint64_t *bran
     if (e != hipSuccess) return fail(QSV_EHIP, "sv_batch_create: abort flag device address");
     e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) return fail(QSV_EHIP, "sv_batch_create: capture stream");
+    e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(QSV_EHIP, "sv_batch_create: fork event");
+    for (int k = 0; k < kLanes; ++k) {
+        hipStream_t ls = nullptr;
+        hipEvent_t le = nullptr;
+        if ((e = hipStreamCreateWithFlags(&ls, hipStreamNonBlocking)) != hipSuccess)
+            return fail(QSV_EHIP, "sv_batch_create: side stream");
+        b->lanes.push_back(ls);
+        if ((e = hipEventCreateWithFlags(&le, hipEventDisableTiming)) != hipSuccess)
+            return fail(QSV_EHIP, "sv_batch_create: join event");
+        b->lane_done.push_back(le);
+    }
     *out = b.release();
     return QSV_OK;
 }
@@ -457,10 +475,33 @@ qsv_status sv_batch_run(qsv_batch *b, void *const *amps_dev, int init_plus,
         if (e != hipSuccess) return hipfail(e, "sv_batch_run: begin capture");
         // counters of the persistent launches start at zero in every replay
         hipError_t le = b->persistent ? launch_zero_u32(b->d_done, b->n_counters, b->cap) : hipSuccess;
-        for (size_t p = 0; p < b->plans.size() && le == hipSuccess; ++p) {
-            if (!b->plan_jit[p]) continue;
-            if (jit_launch_batched(*b->plans[p], variant, b->d_group_ents[p],
-                                   unsigned(b->group[p].size()), b->cap) != QSV_OK)
+        // Each compiled plan's passes form a chain of their own: the chains
+        // go to the side streams (largest work first, each to the least
+        // loaded stream), so the graph holds them as parallel branches and
+        // small states do not leave the device idle one after another; the
+        // generic-kernel rounds stay on the capture stream, alongside.
+        std::vector<size_t> jplans;
+        for (size_t p = 0; p < b->plans.size(); ++p)
+            if (b->plan_jit[p]) jplans.push_back(p);
+        auto work = [&](size_t p) {
+            return double(b->group[p].size()) * std::ldexp(double(b->plans[p]->passes.size()), b->plans[p]->n);
+        };
+        std::stable_sort(jplans.begin(), jplans.end(), [&](size_t x, size_t y) { return work(x) > work(y); });
+        size_t joined = 0;  // side streams that joined the capture
+        if (le == hipSuccess && !jplans.empty()) {
+            le = hipEventRecord(b->fork, b->cap);
+            while (le == hipSuccess && joined < b->lanes.size()) {
+                le = hipStreamWaitEvent(b->lanes[joined], b->fork, 0);
+                if (le == hipSuccess) ++joined;
+            }
+        }
+        std::vector<double> load(std::max<size_t>(joined, 1), 0.0);
+        for (size_t p : jplans) {
+            if (le != hipSuccess) break;
+            const size_t k = size_t(std::min_element(load.begin(), load.end()) - load.begin());
+            load[k] += work(p);
+            if (jit_launch_batched(*b->plans[p], variant, b->d_group_ents[p], unsigned(b->group[p].size()),
+                                   joined ? b->lanes[k] : b->cap) != QSV_OK)
                 le = hipErrorLaunchFailure;
         }
         for (const BatchShape &bs : b->shapes) {
@@ -475,6 +516,13 @@ qsv_status sv_batch_run(qsv_batch *b, void *const *amps_dev, int init_plus,
                                             b->d_ents, b->d_progs, int(r), bs.round_blocks[r],
                                             init_plus ? 1 : 0, b->cap);
             }
+        }
+        // join every side stream back (also after an error: the capture
+        // must end with all of them joined)
+        for (size_t k = 0; k < joined; ++k) {
+            hipError_t je = hipEventRecord(b->lane_done[k], b->lanes[k]);
+            if (je == hipSuccess) je = hipStreamWaitEvent(b->cap, b->lane_done[k], 0);
+            if (le == hipSuccess) le = je;
         }
         if (le == hipSuccess && m)
             le = launch_gather_batch(b->d_ents, count, bitstrings_dev, m,
@@ -599,6 +647,9 @@ void sv_batch_destroy(qsv_batch *b) {
     drop_graph(b);
     free_tables(b);
     if (b->cap) hipStreamDestroy(b->cap);
+    for (hipStream_t ls : b->lanes) hipStreamDestroy(ls);
+    for (hipEvent_t ev : b->lane_done) hipEventDestroy(ev);
+    if (b->fork) hipEventDestroy(b->fork);
     if (b->h_abort) hipHostFree(b->h_abort);
     delete b;
 }
