@@ -376,14 +376,32 @@ def test_branch_combine_identical_inputs():
         assert np.max(np.abs(out.cpu().numpy() - want)) <= 1e-12 * max(1.0, math.sqrt(nb))
 
 
-def test_gather_out_of_range_is_nan():
+def test_gather_out_of_range_is_refused_eagerly_and_nan_in_a_graph():
+    """Eagerly, a bitstring >= 2^n gives QSV_ERANGE and the output keeps its
+    contents.  Captured into a graph (where the call cannot wait for its
+    range check) the gather writes NaN for those entries: every replay, with
+    eager work between replays, gives the in-range values and NaN."""
     _gpu()
     a = _state(10, qsv.INIT_PLUS)
     xs = torch.tensor([0, 1023, 1024, 5000], dtype=torch.int64, device=DEV)
-    out = torch.empty(4, dtype=torch.complex64, device=DEV)
-    qsv.sv_amplitudes(a, 10, xs, out)
-    o = out.cpu().numpy()
-    assert np.allclose(o[:2], 2 ** -5) and np.isnan(o[2:].real).all()
+    out = torch.full((4,), complex(9.0, 9.0), dtype=torch.complex64, device=DEV)
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.sv_amplitudes(a, 10, xs, out)
+    assert e.value.status == 2
+    assert torch.all(out == complex(9.0, 9.0))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        qsv.sv_amplitudes(a, 10, xs, out, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.fill_(complex(9.0, 9.0))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        assert np.allclose(o[:2], 2 ** -5) and np.isnan(o[2:].real).all(), rep
 
 
 def test_split_end_to_end_gpu():
