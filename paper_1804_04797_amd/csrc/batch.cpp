@@ -399,18 +399,6 @@ qsv_status sv_batch_create(const qsv_circuit *const *circs, const uint64_t *bran
     if (e != hipSuccess) return fail(QSV_EHIP, "sv_batch_create: abort flag device address");
     e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) return fail(QSV_EHIP, "sv_batch_create: capture stream");
-    e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
-    if (e != hipSuccess) return fail(QSV_EHIP, "sv_batch_create: fork event");
-    for (int k = 0; k < kLanes; ++k) {
-        hipStream_t ls = nullptr;
-        hipEvent_t le = nullptr;
-        if ((e = hipStreamCreateWithFlags(&ls, hipStreamNonBlocking)) != hipSuccess)
-            return fail(QSV_EHIP, "sv_batch_create: side stream");
-        b->lanes.push_back(ls);
-        if ((e = hipEventCreateWithFlags(&le, hipEventDisableTiming)) != hipSuccess)
-            return fail(QSV_EHIP, "sv_batch_create: join event");
-        b->lane_done.push_back(le);
-    }
     *out = b.release();
     return QSV_OK;
 }
@@ -473,6 +461,24 @@ qsv_status sv_batch_run(qsv_batch *b, void *const *amps_dev, int init_plus,
             for (qsv_status r : res)
                 if (r != QSV_OK) return fail(r, "sv_batch_run: compiling pass kernels failed");
         }
+        // the side streams and their events (below), made before the first
+        // capture that has two compiled chains to run side by side
+        if (std::count_if(b->plan_jit.begin(), b->plan_jit.end(), [](char j) { return j != 0; }) > 1 &&
+            b->lanes.empty()) {
+            e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+            for (int k = 0; k < kLanes && e == hipSuccess; ++k) {
+                hipStream_t ls = nullptr;
+                hipEvent_t je = nullptr;
+                if ((e = hipStreamCreateWithFlags(&ls, hipStreamNonBlocking)) != hipSuccess) break;
+                if ((e = hipEventCreateWithFlags(&je, hipEventDisableTiming)) != hipSuccess) {
+                    hipStreamDestroy(ls);
+                    break;
+                }
+                b->lanes.push_back(ls);
+                b->lane_done.push_back(je);
+            }
+            if (e != hipSuccess) return hipfail(e, "sv_batch_run: side streams");
+        }
         e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hipfail(e, "sv_batch_run: begin capture");
         // counters of the persistent launches start at zero in every replay
@@ -490,7 +496,7 @@ qsv_status sv_batch_run(qsv_batch *b, void *const *amps_dev, int init_plus,
         };
         std::stable_sort(jplans.begin(), jplans.end(), [&](size_t x, size_t y) { return work(x) > work(y); });
         size_t joined = 0;  // side streams that joined the capture
-        if (le == hipSuccess && !jplans.empty()) {
+        if (le == hipSuccess && jplans.size() > 1 && !b->lanes.empty()) {
             le = hipEventRecord(b->fork, b->cap);
             while (le == hipSuccess && joined < b->lanes.size()) {
                 le = hipStreamWaitEvent(b->lanes[joined], b->fork, 0);
