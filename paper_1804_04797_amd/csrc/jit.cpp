@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -126,6 +127,10 @@ std::string scatter_expr(const std::string &src, const std::vector<int> &target,
 //    flag: diagonal gates on thread or tile-index qubits only update e.
 // All of them are applied (at most one complex multiply per amplitude) before
 // an LDS exchange and, together with the pass scale, before the store.
+// Exchanges whose chosen layout failed its injectivity check and fell back
+// to the plain weights (a generator defect; sv_debug_jit_compile reports it).
+std::atomic<unsigned> g_layout_fallbacks{0};
+
 struct Gen {
     const PassProg &P;
     int R, T, N, L;
@@ -663,6 +668,7 @@ struct Gen {
         }
         if (best.dsum && !layout_valid(best, perm, inv)) {  // keep to the plain weights
             base_layout(best, false, split, perm, tsplit);
+            g_layout_fallbacks.fetch_add(1, std::memory_order_relaxed);
         }
         return best;
     }
@@ -1235,6 +1241,15 @@ qsv_status jit_compile_only(const Plan &plan, size_t *code_bytes, double *second
     std::vector<size_t> lds;
     std::vector<char> code;
     std::string log;
+    {
+        // every form's exchange layouts pass their check (generation only)
+        const unsigned before = g_layout_fallbacks.load();
+        for (int v : {kJitInit | 1 | kJitNorm, kJitInit | 1 | kJitNorm | kJitLoop,
+                      kJitInit | 1 | kJitNorm | kJitWhole, kJitSample, kJitBatched | kJitInit | 1})
+            (void)jit_source(plan, &lds, v);
+        if (g_layout_fallbacks.load() != before)
+            return fail(QSV_EINTERNAL, "an exchange layout failed its injectivity check");
+    }
     auto t0 = std::chrono::steady_clock::now();
     // the complex128 instantiation must compile too
     qsv_status st = compile_source(jit_source(plan, &lds, kJitDouble | kJitInit | 1 | kJitNorm), code, log);

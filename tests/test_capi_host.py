@@ -320,6 +320,19 @@ def test_compiled_pass_source_compiles(shape):
     assert nbytes > 1000
 
 
+@pytest.mark.parametrize("name,shape", [("6x6m2-d30", (5, 8, 4)), ("5x6-d20", (5, 9, 5))])
+def test_exchange_layouts_checked_for_the_headline_plans(name, shape):
+    """Every exchange layout of the 34- and 30-qubit sweeps' plans (one tile
+    per workgroup staged in halves or whole, persistent, sampling, batched)
+    passes the generator's injectivity check (no fall-back to plain weights,
+    else QSV_EINTERNAL), and the sources compile."""
+    spec = dict(workloads.WORKLOADS[name])
+    c = qsv.circuit_create(spec["rows"], spec["cols"], workloads.present_mask(spec), spec["depth"], spec["seed"])
+    o = dict(reg_qubits=shape[0], thread_qubits=shape[1], low_qubits=shape[2], plain=0, jit=1, out_of_place=0)
+    nbytes, _ = qsv.sv_debug_jit_compile(c, layer_begin=1, opts=o)
+    assert nbytes > 1000
+
+
 def test_circuit_inverse_matches_oracle():
     """circuit_inverse: reversed order, adjoint kinds, mirrored layers, against
     the oracle generator's adjoint of the same circuit."""
