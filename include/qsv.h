@@ -511,7 +511,10 @@ qsv_status sv_branch_combine_full(const void *a_states, const void *b_states, si
  * states below 2^21 amplitudes on the batch's tile shape; both with the
  * generic pass kernel, one launch per tile shape and pass round.  States of
  * 2^21 amplitudes or more run compiled kernels of their own plan on the tile
- * shape tuned for their class (sv_tune / sv_tune_set).  A persistent form
+ * shape tuned for their class (sv_tune / sv_tune_set); in the captured graph
+ * each such plan's chain of passes is a branch of its own, so independent
+ * states run side by side (the batch makes four side streams for the
+ * capture when it has two or more such plans).  A persistent form
  * (one launch per tile shape whose workgroups take work items (pass round,
  * entry, tile) in order from a device counter, per-entry counters of
  * completed tiles ordering each entry's passes) is switched off in this
